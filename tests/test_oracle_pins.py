@@ -1,0 +1,422 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test names what pins it: a printed value, a closed form, an identity or a
+brute-force construction.  None re-types the oracle's own formula.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import ftlm_workloads as W
+from oracle import dense
+from oracle import ftlm as of
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+def _sys(two_s, J=None, d=None, e=None, g=None, B=(0, 0, 0), pos=None):
+    n = len(two_s)
+    return W.System(two_s=np.asarray(two_s, np.int32),
+                    J=None if J is None else np.asarray(J, float),
+                    d=None if d is None else np.asarray(d, float),
+                    e=np.tile([0.0, 0.0, 1.0], (n, 1)) if e is None else np.asarray(e, float),
+                    g=np.full(n, 2.0) if g is None else np.asarray(g, float),
+                    B=np.asarray(B, float), pos=None if pos is None else np.asarray(pos, float))
+
+
+def _dense_from_c(system, B=None):
+    """Full matrix of the C oracle's H*v, by applying it to every unit vector."""
+    ham = of.Ham(system, B)
+    H = np.zeros((ham.dim, ham.dim), np.complex128)
+    for k in range(ham.dim):
+        e = np.zeros(ham.dim, np.complex128)
+        e[k] = 1.0
+        H[:, k] = ham.apply(e)
+    return H
+
+
+# ---------------------------------------------------------------- C1 dimension
+def test_dimension_printed_values():
+    g = json.load(open(GOLDEN))
+    assert W.dimension(g["mn9_dimension"]["two_s"]) == g["mn9_dimension"]["value"]
+    assert W.dimension(g["ring_dimension"]["two_s"]) == g["ring_dimension"]["value"]
+    s = _sys([5, 4, 4, 4, 4, 4, 4, 4, 4])
+    assert of.Ham(s).dim == 2343750
+
+
+# ------------------------------------------------------------- spin matrices
+@pytest.mark.parametrize("two_s", [1, 2, 3, 4, 5])
+def test_spin_algebra(two_s):
+    """[s_x, s_y] = i s_z (cyclic) and s^2 = s(s+1): fixes the sign of s_y."""
+    s = two_s / 2
+    for sx, sy, sz in (dense.spin_matrices(two_s)[:3], of.spin_matrices(two_s)):
+        assert np.allclose(sx @ sy - sy @ sx, 1j * sz, atol=1e-14)
+        assert np.allclose(sy @ sz - sz @ sy, 1j * sx, atol=1e-14)
+        assert np.allclose(sz @ sx - sx @ sz, 1j * sy, atol=1e-14)
+        assert np.allclose(sx @ sx + sy @ sy + sz @ sz, s * (s + 1) * np.eye(two_s + 1), atol=1e-13)
+        # |m> ascending: s_z diagonal -s..s
+        assert np.allclose(np.diag(sz).real, -s + np.arange(two_s + 1))
+
+
+# ---------------------------------------------------------- C3 closed forms
+def _spectra(system):
+    return (np.linalg.eigvalsh(dense.hamiltonian_dense(system)),
+            np.linalg.eigvalsh(_dense_from_c(system)))
+
+
+@pytest.mark.parametrize("s1,s2", [(1, 1), (2, 3), (5, 4)])
+def test_dimer_heisenberg_zeeman(s1, s2):
+    """2J s1.s2 + g mu_B B.S: E = J[S(S+1) - s1(s1+1) - s2(s2+1)] + g mu_B |B| M."""
+    J = 0.7
+    B = np.array([0.3, -0.8, 0.5])
+    sysm = _sys([s1, s2], J=[[0, J], [0, 0]], B=B, g=[2.1, 2.1])
+    a, b = s1 / 2, s2 / 2
+    ref = []
+    for S2 in range(abs(s1 - s2), s1 + s2 + 1, 2):
+        S = S2 / 2
+        for k in range(S2 + 1):
+            M = -S + k
+            ref.append(J * (S * (S + 1) - a * (a + 1) - b * (b + 1))
+                       + 2.1 * dense.MU_B_K_PER_T * np.linalg.norm(B) * M)
+    ref = np.sort(ref)
+    for ev in _spectra(sysm):
+        assert np.allclose(np.sort(ev), ref, atol=1e-12)
+
+
+def test_kambe_square():
+    """Square ring, 2J sum s_i.s_{i+1} = J[S^2 - S13^2 - S24^2] (Kambe), plus Zeeman."""
+    two_s = [2, 2, 2, 2]
+    J = W.ring_couplings(4, 0.9)
+    B = np.array([0.0, 0.4, -0.2])
+    sysm = _sys(two_s, J=J, B=B)
+    ref = []
+    for S13 in range(0, 3):
+        for S24 in range(0, 3):
+            for S in range(abs(S13 - S24), S13 + S24 + 1):
+                for M in range(-S, S + 1):
+                    ref.append(0.9 * (S * (S + 1) - S13 * (S13 + 1) - S24 * (S24 + 1))
+                               + 2.0 * dense.MU_B_K_PER_T * np.linalg.norm(B) * M)
+    for ev in _spectra(sysm):
+        assert np.allclose(np.sort(ev), np.sort(ref), atol=1e-11)
+
+
+@pytest.mark.parametrize("two_s", [2, 3, 5])
+def test_single_ion_field_along_axis(two_s):
+    """d (s.e)^2 + g mu_B B.s with B || e: E = d m^2 + g mu_B |B| m."""
+    e = np.array([0.3, -0.5, 0.81])
+    e = e / np.linalg.norm(e)
+    B = 1.7 * e
+    d = -2.3
+    sysm = _sys([two_s], d=[d], e=[e], B=B, g=[1.95])
+    m = -two_s / 2 + np.arange(two_s + 1)
+    ref = np.sort(d * m ** 2 + 1.95 * dense.MU_B_K_PER_T * 1.7 * m)
+    for ev in _spectra(sysm):
+        assert np.allclose(np.sort(ev), ref, atol=1e-12)
+
+
+def test_dipolar_dimer_closed_form():
+    """Two s=1/2: D(s1.s2 - 3 (s1.e)(s2.e)) has levels {-D/2, -D/2, 0, D},
+    D = mu0 mu_B^2 g1 g2 / (4 pi r^3)."""
+    pos = np.array([[0.1, 0.2, -0.3], [0.35, -0.05, 0.12]])
+    g = [2.0, 2.2]
+    r = np.linalg.norm(pos[1] - pos[0])
+    D = dense.C_DIP_K_NM3 * g[0] * g[1] / r ** 3
+    sysm = _sys([1, 1], pos=pos, g=g)
+    ref = np.sort([-D / 2, -D / 2, 0.0, D])
+    for ev in _spectra(sysm):
+        assert np.allclose(np.sort(ev), ref, atol=1e-15)
+
+
+def test_rotation_and_field_reversal_invariance():
+    rng = np.random.default_rng(11)
+    sysm = W.random_small_system(rng, 4, max_two_s=3)
+    ev0 = np.linalg.eigvalsh(_dense_from_c(sysm))
+    Rm = scipy.linalg.expm(np.cross(np.eye(3), rng.standard_normal(3)))  # random rotation
+    rot = W.System(two_s=sysm.two_s, J=sysm.J, d=sysm.d, e=sysm.e @ Rm.T, g=sysm.g,
+                   B=Rm @ sysm.B, pos=sysm.pos @ Rm.T)
+    assert np.allclose(np.linalg.eigvalsh(_dense_from_c(rot)), ev0, atol=1e-11)
+    assert np.allclose(np.linalg.eigvalsh(_dense_from_c(sysm, -sysm.B)), ev0, atol=1e-11)
+
+
+def test_decoupled_ions_additive():
+    rng = np.random.default_rng(3)
+    two_s = [2, 3, 4]
+    e = W.unit_vectors(rng, 3)
+    sysm = _sys(two_s, d=[-1.0, 2.0, 0.5], e=e, B=[0.2, 0.7, -1.1], g=[2.0, 1.9, 2.1])
+    T = W.t_grid(20)
+    full = dense.exact_thermo(sysm, T)
+    parts = [dense.exact_thermo(_sys([two_s[i]], d=[sysm.d[i]], e=[e[i]], B=sysm.B, g=[sysm.g[i]]), T)
+             for i in range(3)]
+    assert np.allclose(full["lnZ"], sum(p["lnZ"] for p in parts), rtol=1e-12, atol=1e-12)
+    assert np.allclose(full["M"], sum(p["M"] for p in parts), rtol=1e-10, atol=1e-12)
+
+
+def _brillouin(s, x):
+    a = (2 * s + 1) / (2 * s)
+    b = 1 / (2 * s)
+    return a / np.tanh(a * x) - b / np.tanh(b * x)
+
+
+def test_brillouin_magnetisation():
+    """Free spins: M = g s B_s(g s mu_B B / T) per spin, positive along B."""
+    B = np.array([0.5, -0.5, 1.0])
+    sysm = _sys([3, 3], B=B, g=[2.0, 2.0])
+    T = W.t_grid(30)
+    res = dense.exact_thermo(sysm, T)
+    s = 1.5
+    x = 2.0 * s * dense.MU_B_K_PER_T * np.linalg.norm(B) / T
+    assert np.allclose(res["M"], 2 * 2.0 * s * _brillouin(s, x), rtol=1e-10)
+
+
+# ------------------------------------------------------------- C4 traces
+def test_trace_identities():
+    rng = np.random.default_rng(5)
+    sysm = W.random_small_system(rng, 4, max_two_s=3)
+    for H in (dense.hamiltonian_dense(sysm), _dense_from_c(sysm)):
+        dim = H.shape[0]
+        s = sysm.two_s / 2
+        c = s * (s + 1) / 3
+        q = s * (s + 1) * (3 * s ** 2 + 3 * s - 1) / 15
+        dc = sysm.d * c
+        t1 = dc.sum()
+        b = dense.MU_B_K_PER_T * sysm.g * np.linalg.norm(sysm.B)
+        t2 = t1 ** 2 - (dc ** 2).sum() + (sysm.d ** 2 * q + b ** 2 * c).sum()
+        n = len(s)
+        for i in range(n):
+            for j in range(i + 1, n):
+                r = np.linalg.norm(sysm.pos[j] - sysm.pos[i])
+                D = dense.C_DIP_K_NM3 * sysm.g[i] * sysm.g[j] / r ** 3
+                t2 += (12 * sysm.J[i, j] ** 2 + 6 * D ** 2) * c[i] * c[j]
+        assert abs(np.trace(H).real / dim - t1) < 1e-12
+        assert abs(np.trace(H @ H).real / dim - t2) < 1e-11 * max(1, abs(t2))
+
+
+# --------------------------------------------------- C5 matrix-free H*v
+@pytest.mark.parametrize("seed", range(6))
+def test_c_hv_matches_dense_kronecker(seed):
+    """Brute force: the C oracle's matrix-free H*v equals the Kronecker-built
+    matrix times v element by element (separates H from its conjugate)."""
+    rng = np.random.default_rng(100 + seed)
+    sysm = W.random_small_system(rng, int(rng.integers(2, 6)), max_two_s=4)
+    H = dense.hamiltonian_dense(sysm)
+    v = rng.standard_normal(H.shape[0]) + 1j * rng.standard_normal(H.shape[0])
+    w = of.hv(sysm, v)
+    assert np.max(np.abs(w - H @ v)) <= 1e-13 * np.max(np.abs(H @ v))
+    assert np.linalg.norm(H - H.conj()) > 1e-3  # the case really is complex
+
+
+def test_hermitian_and_time_reversal():
+    rng = np.random.default_rng(21)
+    sysm = W.random_small_system(rng, 5, max_two_s=3)
+    ham = of.Ham(sysm)
+    dim = ham.dim
+    x = rng.standard_normal(dim) + 1j * rng.standard_normal(dim)
+    y = rng.standard_normal(dim) + 1j * rng.standard_normal(dim)
+    assert abs(np.vdot(x, ham.apply(y)) - np.vdot(ham.apply(x), y)) < 1e-12 * dim
+    # Theta x: index nu -> dim-1-nu, sign (-1)^{sum(2 s_i - d_i)}, complex conjugation
+    digits = np.zeros((dim, len(sysm.two_s)), int)
+    rest = np.arange(dim)
+    for i, t in enumerate(sysm.two_s):
+        digits[:, i] = rest % (t + 1)
+        rest //= (t + 1)
+    sign = (-1.0) ** ((sysm.two_s[None, :] - digits).sum(1))
+
+    def theta(z):
+        out = np.empty_like(z)
+        out[dim - 1 - np.arange(dim)] = sign * np.conj(z)
+        return out
+    lhs = theta(ham.apply(x))
+    rhs = of.Ham(sysm, -sysm.B).apply(theta(x))
+    assert np.max(np.abs(lhs - rhs)) < 1e-12 * np.max(np.abs(lhs))
+
+
+def test_sz_sectors_preserved():
+    """No anisotropy, no dipolar, B || z: total M is conserved."""
+    sysm = _sys([1, 2, 3, 1, 2], J=np.triu(np.ones((5, 5)), 1) * 0.4, B=[0, 0, 0.8])
+    ham = of.Ham(sysm)
+    dims = [t + 1 for t in sysm.two_s]
+    Mtot = np.zeros(ham.dim)
+    rest = np.arange(ham.dim)
+    for t in sysm.two_s:
+        Mtot += rest % (t + 1) - t / 2
+        rest //= (t + 1)
+    rng = np.random.default_rng(0)
+    for M in np.unique(Mtot):
+        x = np.where(Mtot == M, rng.standard_normal(ham.dim), 0).astype(np.complex128)
+        w = ham.apply(x)
+        assert np.max(np.abs(w[Mtot != M])) < 1e-14
+
+
+# ---------------------------------------------------------------- C6 Lanczos
+def test_lanczos_moments():
+    """sum_n Q_1n^2 eps_n^k = <v1|H^k|v1> for k < 2 N_L."""
+    sysm, _ = W.cfg1()
+    sysm = _sys([2] * 6, J=W.ring_couplings(6, 1.0), d=[-2.0] * 6, e=sysm.e[:6], B=[0, 0, 1])
+    ham = of.Ham(sysm)
+    r = of.gaussian_vector(7, 0, 0, 0, ham.dim)
+    a, b, y, k = of.lanczos(ham, None, r, 8)
+    eps, q1, _ = of.krylov_eigen(a, b)
+    v = r / np.linalg.norm(r)
+    hk = v.copy()
+    for p in range(0, 12):
+        mom_exact = np.vdot(v, hk).real
+        mom_krylov = np.sum(q1 ** 2 * eps ** p)
+        assert abs(mom_exact - mom_krylov) <= 1e-11 * max(1.0, abs(mom_exact)), p
+        hk = ham.apply(hk)
+
+
+def test_invariant_subspace_is_exact():
+    """dim <= N_L with re-orthogonalisation: the Krylov estimate of
+    <r|exp(-H/T)|r> and <r|O exp(-H/T)|r> equals the dense value."""
+    rng = np.random.default_rng(9)
+    sysm = W.random_small_system(rng, 3, max_two_s=2)
+    H = dense.hamiltonian_dense(sysm)
+    O = dense.moment_operator(sysm).toarray()
+    ham, mom = of.Ham(sysm), of.Moment(sysm, of.field_direction(sysm.B))
+    r = of.gaussian_vector(3, 1, 0, 0, ham.dim)
+    a, b, y, k = of.lanczos(ham, mom, r, ham.dim + 4, reorth=True)
+    eps, q1, u = of.krylov_eigen(a, b, y)
+    v = r / np.linalg.norm(r)
+    for t in (0.3, 2.0, 20.0):
+        E = scipy.linalg.expm(-H / t)
+        z_ref = np.vdot(v, E @ v).real
+        assert abs(np.sum(np.exp(-eps / t) * q1 ** 2) - z_ref) < 1e-10 * z_ref
+        m_kr = np.sum(np.exp(-eps / t) * q1 * np.real(u))
+        assert abs(m_kr - np.vdot(v, O @ E @ v).real) < 1e-10 * z_ref
+
+
+def test_all_basis_vectors_give_exact_thermo():
+    """Start vectors = every basis vector (R = dim): Eq. (E-2-D) becomes the exact trace."""
+    rng = np.random.default_rng(4)
+    sysm = W.random_small_system(rng, 3, max_two_s=2)
+    ham = of.Ham(sysm)
+    dim = ham.dim
+    starts = np.eye(dim, dtype=np.complex128)[None]
+    T = W.t_grid(15)
+    res = of.ftlm(sysm, dim, dim + 2, T, start_vectors=starts, reorth=True)[0]
+    ex = dense.exact_thermo(sysm, T)
+    for key in ("lnZ", "E", "C", "M"):
+        assert np.allclose(res[key], ex[key], rtol=1e-9, atol=1e-10), key
+
+
+# ---------------------------------------------------------- C7 tridiagonal
+def test_tridiagonal_toeplitz():
+    n, a, b = 37, 0.3, -1.2
+    eps, q1, _ = of.krylov_eigen(np.full(n, a), np.full(n, b))
+    ref = np.sort(a + 2 * b * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    assert np.allclose(eps, ref, atol=1e-13 * 3)
+
+
+# ---------------------------------------------------------- C10 Boltzmann
+def test_boltzmann_schottky():
+    """Two levels -D/2, +D/2 with equal weights: C = (D/T)^2 e^{D/T}/(1+e^{D/T})^2."""
+    Dl = 3.0
+    T = W.t_grid(50)
+    res = of.boltzmann(2, [np.array([-Dl / 2, Dl / 2])], [np.full(2, 1 / np.sqrt(2))],
+                       [np.zeros(2)], T)
+    x = Dl / T
+    ref = x ** 2 * np.exp(-x) / (1 + np.exp(-x)) ** 2
+    assert np.allclose(res["C"], ref, rtol=1e-12, atol=1e-300)
+    assert np.allclose(res["lnZ"], np.log(2 * np.cosh(Dl / (2 * T))), rtol=1e-13)
+
+
+def test_high_temperature_limit():
+    """C T^2 -> <H^2> - <H>^2 as T -> infinity (exact diagonalisation)."""
+    rng = np.random.default_rng(6)
+    sysm = W.random_small_system(rng, 3, max_two_s=2)
+    H = dense.hamiltonian_dense(sysm)
+    dim = H.shape[0]
+    var = np.trace(H @ H).real / dim - (np.trace(H).real / dim) ** 2
+    T = np.array([1e5])
+    res = dense.exact_thermo(sysm, T)
+    assert abs(res["C"][0] * T[0] ** 2 - var) < 1e-3 * var
+
+
+# ---------------------------------------------------------- RNG pins
+def test_philox_known_answers():
+    """Published known-answer vectors of Philox4x32-10 (Random123 distribution)."""
+    assert of.philox4x32_10([0, 0, 0, 0], [0, 0]) == [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]
+    assert of.philox4x32_10([0xffffffff] * 4, [0xffffffff] * 2) == \
+        [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]
+    assert of.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344],
+                            [0xa4093822, 0x299f31d0]) == [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+
+
+def test_gaussian_vector_statistics():
+    """Re and Im i.i.d. N(0,1): mean 0, variance 1 each, uncorrelated."""
+    z = of.gaussian_vector(123, 2, 1, 0, 400000)
+    n = len(z)
+    for x in (z.real, z.imag):
+        assert abs(x.mean()) < 5 / math.sqrt(n)
+        assert abs(x.var() - 1) < 5 * math.sqrt(2 / n)
+        assert abs(np.mean(x ** 4) - 3) < 0.05
+    assert abs(np.mean(z.real * z.imag)) < 5 / math.sqrt(n)
+    z2 = of.gaussian_vector(123, 3, 1, 0, 1000)
+    assert not np.allclose(z[:1000], z2)
+    assert np.array_equal(of.gaussian_vector(123, 2, 1, 0, 1000), z[:1000])
+
+
+# ------------------------------------------------------ C8 FTLM vs exact
+def test_ftlm_statistical_vs_exact():
+    """FTLM (Eqs. E-2-C, E-2-D) against exact diagonalisation: the exact curve
+    lies inside a 4-sigma jackknife band over the random vectors, and the error
+    shrinks as R grows."""
+    base, _ = W.cfg1()
+    sysm = _sys([2] * 6, J=W.ring_couplings(6, 1.0), d=[-2.0] * 6, e=base.e[:6], B=[0, 0, 1])
+    T = W.t_grid(40)
+    ex = dense.exact_thermo(sysm, T)
+    R = 24
+    res = of.ftlm(sysm, R, 60, T, seed=77, return_columns=True)[0]
+    # jackknife over random vectors for C
+    ham_dim = 3 ** 6
+    loo = []
+    for k in range(R):
+        keep = [i for i in range(R) if i != k]
+        b = of.boltzmann(ham_dim, [res["eps"][i] for i in keep], [res["q1"][i] for i in keep],
+                         [np.zeros_like(res["q1"][i]) for i in keep], T)
+        loo.append(b["C"])
+    loo = np.array(loo)
+    sig = np.sqrt((R - 1) / R * ((loo - loo.mean(0)) ** 2).sum(0))
+    assert np.all(np.abs(res["C"] - ex["C"]) <= 4 * sig + 1e-3 * ex["C"].max())
+    # error shrinks with R
+    big = of.ftlm(sysm, 8 * R, 60, T, seed=78)[0]
+    err_small = np.sqrt(np.mean((res["C"] - ex["C"]) ** 2))
+    err_big = np.sqrt(np.mean((big["C"] - ex["C"]) ** 2))
+    assert err_big < err_small
+
+
+# ---------------------------------------------------------- C12 MLP oracle
+def test_mlp_gradient_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    params = mlp.init_params(rng, (7, 16, 12, 9, 3))
+    params = [p + 0.05 * rng.standard_normal(p.shape) for p in params]
+    x = rng.standard_normal((5, 7))
+    t = rng.standard_normal((5, 3))
+    loss, grads = mlp.loss_and_grad(params, x, t)
+    h = 1e-6
+    for k, p in enumerate(params):
+        flat = p.reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = mlp.loss_and_grad(params, x, t)
+            flat[idx] = old - h
+            lm, _ = mlp.loss_and_grad(params, x, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = grads[k].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1e-3, abs(fd)) + 1e-9, (k, idx, fd, an)
+
+
+def test_adam_first_step_closed_form():
+    """With zero moments, the first bias-corrected step is -lr g/(|g| + eps)."""
+    from oracle import mlp
+    g = [np.array([0.3, -2.0, 1e-3])]
+    p, m, v = mlp.adam_step([np.zeros(3)], g, [np.zeros(3)], [np.zeros(3)], 1, lr=0.01)
+    assert np.allclose(p[0], -0.01 * g[0] / (np.abs(g[0]) + 1e-8), rtol=1e-12)
