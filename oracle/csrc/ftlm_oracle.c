@@ -254,6 +254,42 @@ void oracle_hv(const oracle_ham *H, const double *v_ri, double *w_ri) {
   hv(H, (const cplx *)v_ri, (cplx *)w_ri);
 }
 
+/* Selected rows of H v: out[k] = (H v)[rows[k]], by the same definition. */
+void oracle_hv_rows(const oracle_ham *H, const double *v_ri, const int64_t *rows, int64_t nrows,
+                    double *out_ri) {
+  const cplx *v = (const cplx *)v_ri;
+  cplx *out = (cplx *)out_ri;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < nrows; k++) {
+    const int64_t nu = rows[k];
+    int dig[ORACLE_MAX_SITES];
+    int64_t x = nu;
+    for (int i = 0; i < H->n; i++) {
+      dig[i] = (int)(x % H->ns[i]);
+      x /= H->ns[i];
+    }
+    cplx acc = 0;
+    for (int i = 0; i < H->n; i++) {
+      int ni = H->ns[i];
+      const cplx *row = H->h[i] + (size_t)dig[i] * ni;
+      for (int b = 0; b < ni; b++)
+        if (row[b] != 0) acc += row[b] * v[nu + (int64_t)(b - dig[i]) * H->st[i]];
+    }
+    for (int p = 0; p < H->npair; p++) {
+      int i = H->pi[p], j = H->pj[p];
+      int ni = H->ns[i], nj = H->ns[j], nn = ni * nj;
+      const cplx *row = H->P[p] + (size_t)(dig[i] + ni * dig[j]) * nn;
+      for (int bj = 0; bj < nj; bj++)
+        for (int bi = 0; bi < ni; bi++) {
+          cplx c = row[bi + ni * bj];
+          if (c != 0)
+            acc += c * v[nu + (int64_t)(bi - dig[i]) * H->st[i] + (int64_t)(bj - dig[j]) * H->st[j]];
+        }
+    }
+    out[k] = acc;
+  }
+}
+
 /* ---- Philox4x32-10 (Salmon et al., SC'11) ---- */
 static void philox_round(uint32_t c[4], const uint32_t k[2]) {
   const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];

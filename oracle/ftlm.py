@@ -58,6 +58,8 @@ def lib():
         L.oracle_npairs.restype = ctypes.c_int
         L.oracle_npairs.argtypes = [ctypes.c_void_p]
         L.oracle_hv.argtypes = [ctypes.c_void_p, dp, dp]
+        L.oracle_hv_rows.argtypes = [ctypes.c_void_p, dp, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.c_int64, dp]
         L.oracle_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
         L.oracle_gaussian_vector.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                              ctypes.c_uint32, ctypes.c_int64, dp]
@@ -113,6 +115,17 @@ class Ham:
         w = np.empty_like(v)
         lib().oracle_hv(self.ptr, _dp(v.view(np.float64)), _dp(w.view(np.float64)))
         return w
+
+    def apply_rows(self, v, rows):
+        """(H v)[rows] without forming the whole product."""
+        v = np.ascontiguousarray(np.asarray(v, np.complex128))
+        assert v.shape == (self.dim,)
+        rows = np.ascontiguousarray(np.asarray(rows, np.int64))
+        out = np.empty(len(rows), np.complex128)
+        lib().oracle_hv_rows(self.ptr, _dp(v.view(np.float64)),
+                             rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(rows),
+                             _dp(out.view(np.float64)))
+        return out
 
 
 class Moment:

@@ -1,0 +1,350 @@
+// C ABI of the FTLM library (include/ftlm.h): handle lifetime, device tables,
+// H*v, start vectors and the plain (one Hamiltonian) FTLM run driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ftlm_internal.hpp"
+
+namespace ftlm {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+#define HIP_OK(expr)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));           \
+      return FTLM_EHIP;                                                       \
+    }                                                                         \
+  } while (0)
+
+// ---------------------------------------------------------------- table upload
+namespace {
+
+struct Blob {
+  std::vector<unsigned char> bytes;
+  size_t add(const void *src, size_t n) {
+    size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + n);
+    if (n) std::memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+};
+
+template <typename R>
+struct TableOffsets {
+  size_t hdiag, hoff, gp, gm, mval, pij, pc, pzz, zz, czp, czm, pc_half, hflip, cz_half, lowf;
+};
+
+template <typename R>
+static TableOffsets<R> pack_tables(const HostHam &hh, const std::vector<int> &perm, Blob &b) {
+  const int n = hh.n, np = hh.npair;
+  TableOffsets<R> o{};
+  std::vector<R> hdiag(n * 16, 0), gp(n * 16, 0), gm(n * 16, 0), mval(n * 16, 0);
+  std::vector<Cx<R>> hoff(n * 64, Cx<R>{0, 0});
+  for (int k = 0; k < n; k++) {
+    const int r = hh.radix[k];
+    const double s = 0.5 * hh.two_s[k];
+    for (int dk = 0; dk < r; dk++) {
+      const double m = dk - s;
+      hdiag[k * 16 + dk] = (R)hh.h[(size_t)k * 256 + dk * 16 + dk].re;
+      mval[k * 16 + dk] = (R)m;
+      if (dk >= 1) gp[k * 16 + dk] = (R)std::sqrt(s * (s + 1) - m * (m - 1));
+      if (dk <= r - 2) gm[k * 16 + dk] = (R)std::sqrt(s * (s + 1) - m * (m + 1));
+      const int Ds[4] = {-2, -1, 1, 2};
+      for (int di = 0; di < 4; di++) {
+        const int nd = dk + Ds[di];
+        if (nd < 0 || nd >= r) continue;
+        const Cx<double> c = hh.h[(size_t)k * 256 + dk * 16 + nd];
+        hoff[(k * 4 + di) * 16 + dk] = Cx<R>{(R)c.re, (R)c.im};
+      }
+    }
+  }
+  std::vector<int2> pij(std::max(np, 1));
+  std::vector<Cx<R>> pc(4 * std::max(np, 1), Cx<R>{0, 0}), pch(4 * std::max(np, 1), Cx<R>{0, 0});
+  std::vector<R> pzz(std::max(np, 1), 0);
+  for (int q = 0; q < np; q++) {
+    const int p = perm[q];
+    pij[q] = make_int2(hh.pi[p], hh.pj[p]);
+    for (int a = 0; a < 4; a++) pc[4 * q + a] = Cx<R>{(R)hh.pc[4 * p + a].re, (R)hh.pc[4 * p + a].im};
+    // row bits (b_i, b_j) -> ladder pair: (0,0) --, (0,1) -+, (1,0) +-, (1,1) ++
+    pch[4 * q + 0] = pc[4 * q + 3];
+    pch[4 * q + 1] = pc[4 * q + 2];
+    pch[4 * q + 2] = pc[4 * q + 1];
+    pch[4 * q + 3] = pc[4 * q + 0];
+    pzz[q] = (R)hh.pzz[p];
+  }
+  std::vector<R> zz(n * n);
+  std::vector<Cx<R>> czp(n * n), czm(n * n), czh(n * n * 2);
+  for (int k = 0; k < n * n; k++) {
+    zz[k] = (R)hh.zz[k];
+    czp[k] = Cx<R>{(R)hh.czp[k].re, (R)hh.czp[k].im};
+    czm[k] = Cx<R>{(R)hh.czm[k].re, (R)hh.czm[k].im};
+    czh[2 * k + 0] = czm[k];
+    czh[2 * k + 1] = czp[k];
+  }
+  std::vector<Cx<R>> hflip(2 * n, Cx<R>{0, 0});
+  for (int k = 0; k < n; k++)
+    if (hh.radix[k] == 2) {
+      const Cx<double> a = hh.h[(size_t)k * 256 + 0 * 16 + 1], c = hh.h[(size_t)k * 256 + 1 * 16 + 0];
+      hflip[2 * k + 0] = Cx<R>{(R)a.re, (R)a.im};
+      hflip[2 * k + 1] = Cx<R>{(R)c.re, (R)c.im};
+    }
+  std::vector<Cx<R>> lowf;
+  if (hh.spin_half && n >= kLowBits) {
+    lowf.assign((size_t)n * 2 * 256, Cx<R>{0, 0});
+    for (int k = 0; k < n; k++)
+      for (int sel = 0; sel < 2; sel++)
+        for (int t = 0; t < 256; t++) {
+          double fr = 0, fi = 0;
+          for (int l = 0; l < kLowBits; l++) {
+            if (l == k) continue;
+            const double ml = ((t >> l) & 1) ? 0.5 : -0.5;
+            const Cx<double> c = sel ? hh.czp[k * n + l] : hh.czm[k * n + l];
+            fr += c.re * ml;
+            fi += c.im * ml;
+          }
+          lowf[((size_t)k * 2 + sel) * 256 + t] = Cx<R>{(R)fr, (R)fi};
+        }
+  } else {
+    lowf.assign(1, Cx<R>{0, 0});
+  }
+  o.hdiag = b.add(hdiag.data(), hdiag.size() * sizeof(R));
+  o.hoff = b.add(hoff.data(), hoff.size() * sizeof(Cx<R>));
+  o.gp = b.add(gp.data(), gp.size() * sizeof(R));
+  o.gm = b.add(gm.data(), gm.size() * sizeof(R));
+  o.mval = b.add(mval.data(), mval.size() * sizeof(R));
+  o.pij = b.add(pij.data(), pij.size() * sizeof(int2));
+  o.pc = b.add(pc.data(), pc.size() * sizeof(Cx<R>));
+  o.pzz = b.add(pzz.data(), pzz.size() * sizeof(R));
+  o.zz = b.add(zz.data(), zz.size() * sizeof(R));
+  o.czp = b.add(czp.data(), czp.size() * sizeof(Cx<R>));
+  o.czm = b.add(czm.data(), czm.size() * sizeof(Cx<R>));
+  o.pc_half = b.add(pch.data(), pch.size() * sizeof(Cx<R>));
+  o.hflip = b.add(hflip.data(), hflip.size() * sizeof(Cx<R>));
+  o.cz_half = b.add(czh.data(), czh.size() * sizeof(Cx<R>));
+  o.lowf = b.add(lowf.data(), lowf.size() * sizeof(Cx<R>));
+  return o;
+}
+
+template <typename R>
+static DevTables<R> resolve(const TableOffsets<R> &o, unsigned char *base) {
+  DevTables<R> t;
+  t.hdiag = reinterpret_cast<const R *>(base + o.hdiag);
+  t.hoff = reinterpret_cast<const Cx<R> *>(base + o.hoff);
+  t.gp = reinterpret_cast<const R *>(base + o.gp);
+  t.gm = reinterpret_cast<const R *>(base + o.gm);
+  t.mval = reinterpret_cast<const R *>(base + o.mval);
+  t.pij = reinterpret_cast<const int2 *>(base + o.pij);
+  t.pc = reinterpret_cast<const Cx<R> *>(base + o.pc);
+  t.pzz = reinterpret_cast<const R *>(base + o.pzz);
+  t.zz = reinterpret_cast<const R *>(base + o.zz);
+  t.czp = reinterpret_cast<const Cx<R> *>(base + o.czp);
+  t.czm = reinterpret_cast<const Cx<R> *>(base + o.czm);
+  t.pc_half = reinterpret_cast<const Cx<R> *>(base + o.pc_half);
+  t.hflip = reinterpret_cast<const Cx<R> *>(base + o.hflip);
+  t.cz_half = reinterpret_cast<const Cx<R> *>(base + o.cz_half);
+  t.lowf = reinterpret_cast<const Cx<R> *>(base + o.lowf);
+  return t;
+}
+
+}  // namespace
+
+// Packs every table of hh for both precisions and copies it to the device.
+// Reuses dh.block when its size matches (so captured graphs stay valid).
+int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
+  const int n = hh.n, np = hh.npair;
+  // spin-1/2 pair order: low-low | low-high | high-high (sites < 8 are "low")
+  std::vector<int> perm(np);
+  for (int p = 0; p < np; p++) perm[p] = p;
+  int n_ll = 0, n_lh = 0;
+  auto cls = [&](int p) { return (hh.pi[p] >= kLowBits) + (hh.pj[p] >= kLowBits); };
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return cls(a) < cls(b); });
+  for (int p = 0; p < np; p++) {
+    n_ll += cls(p) == 0;
+    n_lh += cls(p) == 1;
+  }
+  Blob b;
+  TableOffsets<double> o64 = pack_tables<double>(hh, perm, b);
+  TableOffsets<float> o32 = pack_tables<float>(hh, perm, b);
+  const size_t bytes = (b.bytes.size() + 255) & ~size_t(255);
+  if (dh.block && dh.block_bytes != bytes) {
+    (void)hipFree(dh.block);
+    dh.block = nullptr;
+  }
+  if (!dh.block) {
+    if (hipMalloc(&dh.block, bytes) != hipSuccess) {
+      err = "hipMalloc of Hamiltonian tables failed";
+      dh.block = nullptr;
+      return FTLM_ENOMEM;
+    }
+    dh.block_bytes = bytes;
+  }
+  if (hipMemcpy(dh.block, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    err = "hipMemcpy of Hamiltonian tables failed";
+    return FTLM_EHIP;
+  }
+  unsigned char *base = reinterpret_cast<unsigned char *>(dh.block);
+  dh.t64 = resolve<double>(o64, base);
+  dh.t32 = resolve<float>(o32, base);
+  HamGeom &g = dh.geom;
+  std::memset(&g, 0, sizeof(g));
+  g.n = n;
+  g.npair = np;
+  g.has_z = hh.has_z;
+  g.spin_half = hh.spin_half && n >= kLowBits;
+  g.n_ll = n_ll;
+  g.n_lh = n_lh;
+  g.dim = (uint32_t)hh.dim;
+  for (int k = 0; k < n; k++) {
+    g.radix[k] = hh.radix[k];
+    g.stride[k] = hh.stride[k];
+    g.s[k] = 0.5f * hh.two_s[k];
+  }
+  return FTLM_OK;
+}
+
+static void field_direction(const double B[3], double out[3]) {
+  const double nb = std::sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+  if (nb > 0) {
+    for (int a = 0; a < 3; a++) out[a] = B[a] / nb;
+  } else {
+    out[0] = out[1] = 0;
+    out[2] = 1;
+  }
+}
+
+// O = -sum_i g_i s_i.B_hat, built as a site-only Hamiltonian whose Zeeman field
+// is -B_hat/mu_B.
+int build_moment(ftlm_hamiltonian *h, std::string &err) {
+  const HostHam &hh = h->host;
+  double bh[3], beff[3];
+  field_direction(hh.B, bh);
+  for (int a = 0; a < 3; a++) beff[a] = -bh[a] / kMuB;
+  ftlm_system s{};
+  s.n_sites = hh.n;
+  s.two_s = hh.two_s;
+  s.g = hh.g.data();
+  s.B = beff;
+  int rc = compile_hamiltonian(&s, h->mom_host, err);
+  if (rc) return rc;
+  return upload_tables(h->mom_host, h->mom_dev, err);
+}
+
+}  // namespace ftlm
+
+using namespace ftlm;
+
+extern "C" {
+
+const char *ftlm_last_error(void) { return g_last_error.c_str(); }
+int ftlm_version(void) { return 10000; }
+
+int ftlm_hamiltonian_create(const ftlm_system *sys, ftlm_hamiltonian **out) {
+  if (!out) { set_error("out is NULL"); return FTLM_EINVAL; }
+  ftlm_hamiltonian *h = new (std::nothrow) ftlm_hamiltonian();
+  if (!h) { set_error("out of host memory"); return FTLM_ENOMEM; }
+  std::string err;
+  int rc = compile_hamiltonian(sys, h->host, err);
+  if (!rc) {
+    if (hipGetDevice(&h->device) != hipSuccess) { err = "no HIP device"; rc = FTLM_EHIP; }
+  }
+  if (!rc) rc = upload_tables(h->host, h->dev, err);
+  if (!rc) rc = build_moment(h, err);
+  if (rc) {
+    set_error(err);
+    ftlm_hamiltonian_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return FTLM_OK;
+}
+
+void ftlm_hamiltonian_destroy(ftlm_hamiltonian *h) {
+  if (!h) return;
+  if (h->dev.block) (void)hipFree(h->dev.block);
+  if (h->mom_dev.block) (void)hipFree(h->mom_dev.block);
+  delete h;
+}
+
+int ftlm_hamiltonian_dim(const ftlm_hamiltonian *h, uint64_t *dim) {
+  if (!h || !dim) { set_error("NULL argument"); return FTLM_EINVAL; }
+  *dim = h->host.dim;
+  return FTLM_OK;
+}
+
+int ftlm_hamiltonian_nnz_per_row(const ftlm_hamiltonian *h, double *nnz) {
+  if (!h || !nnz) { set_error("NULL argument"); return FTLM_EINVAL; }
+  *nnz = h->host.nnz_per_row;
+  return FTLM_OK;
+}
+
+int ftlm_hamiltonian_set_field(ftlm_hamiltonian *h, const double B[3]) {
+  if (!h || !B) { set_error("NULL argument"); return FTLM_EINVAL; }
+  for (int a = 0; a < 3; a++)
+    if (!std::isfinite(B[a])) { set_error("B must be finite"); return FTLM_EINVAL; }
+  HIP_OK(hipDeviceSynchronize());
+  for (int a = 0; a < 3; a++) h->host.B[a] = B[a];
+  compile_site_terms(h->host);
+  h->host.nnz_per_row = count_nnz_per_row(h->host);
+  std::string err;
+  int rc = upload_tables(h->host, h->dev, err);
+  if (!rc) rc = build_moment(h, err);
+  if (rc) set_error(err);
+  return rc;
+}
+
+int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, const void *v,
+               void *w, void *stream) {
+  if (!h || !v || !w) { set_error("NULL argument"); return FTLM_EINVAL; }
+  if (precision != FTLM_C128 && precision != FTLM_C64) { set_error("bad precision"); return FTLM_EINVAL; }
+  if (n_cols < 1 || n_cols > 64) { set_error("n_cols must be in [1, 64]"); return FTLM_ERANGE; }
+  if (v == w) { set_error("v and w must differ"); return FTLM_EINVAL; }
+  const size_t es = precision == FTLM_C64 ? 8 : 16;
+  const size_t span = (size_t)h->host.dim * n_cols * es;
+  const char *pv = (const char *)v, *pw = (const char *)w;
+  if (pv < pw + span && pw < pv + span) { set_error("v and w overlap"); return FTLM_EINVAL; }
+  if (((uintptr_t)v | (uintptr_t)w) & 15) { set_error("v and w must be 16-byte aligned"); return FTLM_EINVAL; }
+  HvLaunch L{};
+  L.precision = precision;
+  L.K = n_cols;
+  L.v = v;
+  L.w = w;
+  int rc = launch_hv(h->dev, L, (hipStream_t)stream);
+  if (rc) set_error(std::string("H*v launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return rc;
+}
+
+int ftlm_gaussian_vectors(uint64_t seed, uint32_t instance, uint32_t field, uint32_t r0,
+                          int32_t n_cols, uint64_t dim, void *out, void *stream) {
+  if (!out) { set_error("out is NULL"); return FTLM_EINVAL; }
+  if (n_cols < 1 || n_cols > 64) { set_error("n_cols must be in [1, 64]"); return FTLM_ERANGE; }
+  if (dim < 1 || dim >= (1ull << 32)) { set_error("dim out of range"); return FTLM_ERANGE; }
+  // scratch for the norm partials is not needed here: use a small private buffer
+  static thread_local double *scratch = nullptr;
+  static thread_local int scratch_dev = -1;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  const size_t need = sizeof(double) * (2048 * 64 + 64) + 256;
+  if (!scratch || scratch_dev != dev) {
+    HIP_OK(hipMalloc(&scratch, need));
+    HIP_OK(hipMemset(scratch, 0, need));
+    scratch_dev = dev;
+  }
+  unsigned *counter = reinterpret_cast<unsigned *>(scratch + 2048 * 64 + 64);
+  int rc = launch_gaussian(seed, instance, field, r0, n_cols, (uint32_t)dim, FTLM_C128, out,
+                           scratch, counter, scratch + 2048 * 64, 0, (hipStream_t)stream);
+  if (rc) set_error("gaussian launch failed");
+  return rc;
+}
+
+}  // extern "C"

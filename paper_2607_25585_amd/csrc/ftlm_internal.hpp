@@ -1,0 +1,192 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// FTLM library.  Not part of the public ABI (include/ftlm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ftlm.h"
+
+namespace ftlm {
+
+constexpr double kMuB = 0.67171381563;    // mu_B / k_B in K/T (CODATA 2018)
+constexpr double kCDip = 6.2294807e-4;    // mu0 mu_B^2 / (4 pi k_B) in K nm^3
+constexpr int kMaxSites = FTLM_MAX_SITES;
+constexpr int kMaxRadix = FTLM_MAX_TWO_S + 1;  // 16
+constexpr int kLowBits = 8;                    // spin-1/2 tile: 256 rows, sites 0..7 vary
+constexpr int kBlock = 256;
+
+template <typename R>
+struct alignas(2 * sizeof(R)) Cx {
+  R re, im;
+};
+
+// ---------------------------------------------------------------------------
+// Host-side compiled Hamiltonian (Sec. 2.1, Eq. mce-hamop, in ladder form).
+//
+// Row nu with digits d_k (m_k = d_k - s_k) couples to partner pi through
+//   diagonal   sum_k h_k[d,d] + sum_{i<j} c^zz_ij m_i m_j
+//   site flip  pi = nu + D st_k, D in {-2,-1,1,2}:
+//              h_k[d_k][d_k+D] + (D=-1: gp_k(m_k) F^+_k) + (D=+1: gm_k(m_k) F^-_k)
+//              with F^{+-}_k = sum_{l != k} C^{+-z}_{kl} m_l
+//   pair flip  pi = nu + Di st_i + Dj st_j, Di,Dj in {-1,+1}:
+//              c^{ab}_ij g_a(m_i) g_b(m_j), a = '+' for Di = -1, '-' for Di = +1
+// where gp(m) = <m|s+|m-1> and gm(m) = <m|s-|m+1>.
+// ---------------------------------------------------------------------------
+struct HostHam {
+  int n = 0;
+  int two_s[kMaxSites] = {0};
+  int radix[kMaxSites] = {0};
+  uint32_t stride[kMaxSites] = {0};
+  uint64_t dim = 0;
+  // inputs kept for set_field
+  std::vector<double> J, d, e, g, pos;
+  bool has_J = false, has_d = false, has_pos = false;
+  double B[3] = {0, 0, 0};
+  // one-site matrices h_k, [k][a*16+b] (a = row digit)
+  std::vector<Cx<double>> h;  // n * 256
+  // interacting pairs
+  int npair = 0;
+  std::vector<int> pi, pj;
+  std::vector<Cx<double>> pc;   // [p][4]: c^{++}, c^{+-}, c^{-+}, c^{--}
+  std::vector<double> pzz;      // [p]
+  std::vector<double> zz;       // [n*n] symmetric c^zz matrix (0 off-pairs)
+  // C^{+z}_{kl} (site k raised with s^+, times s^z of l) and C^{-z}_{kl}; [k*n+l]
+  std::vector<Cx<double>> czp, czm;
+  bool has_z = false;
+  double nnz_per_row = 0;
+  bool spin_half = false;  // every site s = 1/2
+};
+
+// Builds everything field-independent plus the one-site matrices for hh.B.
+int compile_hamiltonian(const ftlm_system *sys, HostHam &hh, std::string &err);
+void compile_site_terms(HostHam &hh);
+double count_nnz_per_row(const HostHam &hh);
+
+// ---------------------------------------------------------------------------
+// Device tables.  All pointers refer to one contiguous device allocation
+// owned by the handle.  Real = double for the complex128 path, float for the
+// complex64 path.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct DevTables {
+  // site tables, [k][16]
+  const R *hdiag;          // h_k[d][d]
+  const Cx<R> *hoff;       // [k][4][16]: h_k[d][d+D] for D = -2,-1,+1,+2
+  const R *gp;             // <m|s+|m-1>
+  const R *gm;             // <m|s-|m+1>
+  const R *mval;           // m = d - s
+  // pairs
+  const int2 *pij;         // [p] (i, j)
+  const Cx<R> *pc;         // [p][4] ordered (++, +-, -+, --)
+  const R *pzz;            // [p]
+  const R *zz;             // [n*n]
+  const Cx<R> *czp, *czm;  // [n*n]
+  // spin-1/2 tables
+  const Cx<R> *pc_half;    // [p][4] indexed by row bits (b_i<<1 | b_j)
+  const Cx<R> *hflip;      // [k][2]: h_k[b][1-b]
+  const Cx<R> *cz_half;    // [k][l][2]: row bit b_k selects C^{-z} (b=0) or C^{+z} (b=1)
+  const Cx<R> *lowf;       // [k][2][256]: sum_{l<8, l!=k} cz_half[k][l][sel] m_l(t)
+};
+
+struct HamGeom {
+  int n, npair, has_z, spin_half;
+  int n_ll, n_lh;          // spin-1/2: pairs sorted low-low | low-high | high-high
+  uint32_t dim;
+  int radix[kMaxSites];
+  uint32_t stride[kMaxSites];
+  float s[kMaxSites];
+};
+
+struct DevHam {
+  HamGeom geom;
+  DevTables<double> t64;
+  DevTables<float> t32;
+  void *block = nullptr;  // device allocation holding every table
+  size_t block_bytes = 0;
+};
+
+}  // namespace ftlm
+
+// Opaque handle of the public ABI.
+struct ftlm_hamiltonian {
+  ftlm::HostHam host;
+  ftlm::DevHam dev;
+  // moment operator O = -sum g_i s_i.B_hat as a site-only Hamiltonian
+  ftlm::HostHam mom_host;
+  ftlm::DevHam mom_dev;
+  int device = 0;
+};
+
+namespace ftlm {
+
+void set_error(const std::string &msg);
+int upload_tables(const HostHam &hh, DevHam &dh, std::string &err);
+int build_moment(ftlm_hamiltonian *h, std::string &err);
+
+// ---- kernel launchers (kernels.hip) ----
+struct EpiLanczos {
+  // w = sx[j] * (H X_j) - beta[j-1] * sx[j-1] * X_{j-1}; alpha/y partials
+  const void *xprev;       // X_{j-1} (nullptr at j = 0)
+  const void *ov1;         // O v_1 (nullptr: no y)
+  const double *sx_cur;    // [K] scale of X_j
+  const double *sx_prev;   // [K]
+  const double *beta_prev; // [K] (nullptr at j = 0)
+  double *part;            // [grid][3][K] partials (alpha, y.re, y.im)
+  unsigned *counter;
+  double *alpha_out;       // [K]
+  double *yre_out, *yim_out;  // [K]
+};
+
+struct HvLaunch {
+  int precision;       // 0 c128, 1 c64
+  int K;               // columns (row stride)
+  const void *v;
+  void *w;
+  const double *scale; // optional per-column scale of v (nullptr = 1)
+  const EpiLanczos *lz;  // nullptr = plain product
+  int grid_cap;        // max blocks along x (0 = default)
+  int kc;              // columns per lane (0 = auto)
+};
+
+int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s);
+int hv_grid_blocks(const DevHam &dh, const HvLaunch &L, int *gx, int *gy, int *kc);
+
+int launch_gaussian(uint64_t seed, uint32_t inst, uint32_t field, uint32_t r0, int K,
+                    uint32_t dim, int precision, void *out, double *part, unsigned *counter,
+                    double *sx0, int grid_cap, hipStream_t s);
+int launch_copy_start(const void *src_c128, int src_cols, int col0, int K, uint32_t dim,
+                      int precision, void *out, double *part, unsigned *counter, double *sx0,
+                      int grid_cap, hipStream_t s);
+struct UpdateArgs {
+  int precision, K, step, n_lanczos;
+  uint32_t dim;
+  void *w;               // in: w, out: u = w - alpha sx X_j
+  const void *x;         // X_j
+  const double *sx_cur;  // [K]
+  const double *alpha;   // [K] alpha_j
+  double *beta;          // [K] beta_j (out)
+  double *sx_next;       // [K] (out)
+  double *scale_max;     // [K] running max(|alpha|, beta)
+  int *done;             // [K]
+  int *n_used;           // [K]
+  double *part;          // [grid][K]
+  unsigned *counter;
+  int grid_cap;
+};
+int launch_update(const UpdateArgs &a, hipStream_t s);
+int launch_zero_state(double *scale_max, int *done, int *n_used, unsigned *counters,
+                      int n_counters, int K, hipStream_t s);
+int launch_tridiag(int n_cols, int n_lanczos, const int *n_used, int used_stride, int in_stride,
+                   const double *alpha, const double *beta, const double *y, double *eps,
+                   double *q1, double *qy, int out_stride, int out_col0, double *scratch,
+                   hipStream_t s);
+int launch_boltzmann(int n_curves, int R, int n_lanczos, const int *n_used, const double *eps,
+                     const double *q1, const double *qy, const double *dims, const double *T,
+                     int n_T, double *lnZ, double *E, double *C, double *M, double *E_min,
+                     hipStream_t s);
+
+}  // namespace ftlm

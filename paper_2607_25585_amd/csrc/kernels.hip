@@ -1,0 +1,874 @@
+// HIP kernels (gfx950) of the FTLM hot path.
+//
+//  * hv_half / hv_gen : matrix-free w = H v on the product basis (Sec. 2.1),
+//    gather form, one row per lane and KC column vectors per lane, optional
+//    fused Lanczos epilogue (w -= beta_{j-1} v_{j-1}; alpha_j and y_j partials).
+//  * gaussian / copy_start : start vectors of Eqs. (E-1-1), (E-1-2) and their norms.
+//  * update : u = w - alpha_j v_j, beta_j = |u| (Lanczos recursion of Sec. 2.3).
+//  * tridiag : Krylov eigenpairs by implicit QL (Bowdler, Martin, Reinsch and
+//    Wilkinson, Numer. Math. 11 (1968)) tracking two rows of the eigenvector
+//    matrix.
+//  * boltzmann : the sums of Eqs. (E-2-C) and (E-2-D) in log-sum-exp form.
+//
+// Every reduction is a fixed-order tree (wave shuffles, LDS, then one block that
+// sums the per-block partials in block order), so results are bitwise
+// reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "ftlm_internal.hpp"
+
+namespace ftlm {
+
+// ------------------------------------------------------------------ helpers
+template <typename R, int KC>
+struct Acc {
+  R re[KC];
+  R im[KC];
+};
+
+template <typename R, int KC>
+__device__ __forceinline__ void acc_zero(Acc<R, KC> &a) {
+#pragma unroll
+  for (int q = 0; q < KC; q++) a.re[q] = a.im[q] = R(0);
+}
+
+// a += c * x[0..KC)
+template <typename R, int KC>
+__device__ __forceinline__ void mac(Acc<R, KC> &a, Cx<R> c, const Cx<R> *__restrict__ x) {
+  Cx<R> xv[KC];
+#pragma unroll
+  for (int q = 0; q < KC; q++) xv[q] = x[q];
+#pragma unroll
+  for (int q = 0; q < KC; q++) {
+    a.re[q] = fma(c.re, xv[q].re, a.re[q]);
+    a.re[q] = fma(-c.im, xv[q].im, a.re[q]);
+    a.im[q] = fma(c.re, xv[q].im, a.im[q]);
+    a.im[q] = fma(c.im, xv[q].re, a.im[q]);
+  }
+}
+
+template <typename R, int KC>
+__device__ __forceinline__ void mac_real(Acc<R, KC> &a, R c, const Cx<R> *__restrict__ x) {
+#pragma unroll
+  for (int q = 0; q < KC; q++) {
+    Cx<R> xv = x[q];
+    a.re[q] = fma(c, xv.re, a.re[q]);
+    a.im[q] = fma(c, xv.im, a.im[q]);
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sums NV*KC per-lane values over the block (fixed order) and writes them to
+// part[slot*NV*KC ...].  Then the last block to finish (device-wide) reduces
+// all nslots partials in slot order and calls fin(idx, value) for idx in
+// [0, NV*KC*ncb) where the partial arrays of the ncb column blocks are
+// contiguous.  Returns nothing; fin runs on the last block only.
+template <int NV, int KC>
+__device__ __forceinline__ bool block_partials(const double (&val)[NV][KC], double *part,
+                                               int slot, unsigned *counter, unsigned total) {
+  __shared__ double red[kBlock / 64][NV * KC];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NV; a++)
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      double s = wave_sum(val[a][q]);
+      if (lane == 0) red[wv][a * KC + q] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < NV * KC) {
+    double s = 0;
+    for (int w2 = 0; w2 < kBlock / 64; w2++) s += red[w2][threadIdx.x];
+    part[(size_t)slot * NV * KC + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == total - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+// ------------------------------------------------------------------ H*v
+struct HvParams {
+  int K;             // row stride in columns
+  uint32_t ntile;    // number of 256-row tiles
+  const void *v;
+  void *w;
+  const double *scale;  // per-column scale of v (or nullptr)
+  // Lanczos epilogue
+  int lanczos;
+  const void *xprev;
+  const void *ov1;
+  const double *sx_prev;
+  const double *beta_prev;
+  double *part;
+  unsigned *counter;
+  double *alpha_out, *yre_out, *yim_out;
+};
+
+template <typename R, int KC>
+__device__ __forceinline__ void hv_epilogue(const HvParams &P, uint32_t row, int c0,
+                                            const Acc<R, KC> &acc, const Cx<R> *own,
+                                            double (&red)[3][KC]) {
+  Cx<R> *w = reinterpret_cast<Cx<R> *>(P.w) + (size_t)row * P.K + c0;
+  if (!P.lanczos) {
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      R sc = P.scale ? (R)P.scale[c0 + q] : R(1);
+      w[q] = Cx<R>{acc.re[q] * sc, acc.im[q] * sc};
+    }
+    return;
+  }
+  const Cx<R> *xp = P.xprev ? reinterpret_cast<const Cx<R> *>(P.xprev) + (size_t)row * P.K + c0 : nullptr;
+  const Cx<R> *o1 = P.ov1 ? reinterpret_cast<const Cx<R> *>(P.ov1) + (size_t)row * P.K + c0 : nullptr;
+#pragma unroll
+  for (int q = 0; q < KC; q++) {
+    const double sx = P.scale[c0 + q];
+    double wr = (double)acc.re[q] * sx, wi = (double)acc.im[q] * sx;
+    if (xp) {
+      const double bp = P.beta_prev[c0 + q] * P.sx_prev[c0 + q];
+      Cx<R> a = xp[q];
+      wr -= bp * (double)a.re;
+      wi -= bp * (double)a.im;
+    }
+    Cx<R> out{(R)wr, (R)wi};
+    w[q] = out;
+    Cx<R> xo = own[q];
+    // alpha partial uses the stored (rounded) w so that the update sees the same numbers
+    red[0][q] += (double)xo.re * (double)out.re + (double)xo.im * (double)out.im;
+    if (o1) {
+      Cx<R> ov = o1[q];
+      red[1][q] += (double)ov.re * (double)xo.re + (double)ov.im * (double)xo.im;
+      red[2][q] += (double)ov.re * (double)xo.im - (double)ov.im * (double)xo.re;
+    }
+  }
+}
+
+template <int KC>
+__device__ __forceinline__ void hv_finish(const HvParams &P, double (&red)[3][KC]) {
+  if (!P.lanczos) return;
+  const unsigned total = gridDim.x * gridDim.y;
+  const int slot = blockIdx.y * gridDim.x + blockIdx.x;
+  if (block_partials<3, KC>(red, P.part, slot, P.counter, total)) {
+    // columns c = cb*KC + q; partial layout [cb][bx][3][KC]
+    const int ncol = gridDim.y * KC;
+    for (int idx = threadIdx.x; idx < 3 * ncol; idx += blockDim.x) {
+      const int c = idx / 3, a = idx % 3;
+      const int cb = c / KC, q = c % KC;
+      double s = 0;
+      for (unsigned bx = 0; bx < gridDim.x; bx++)
+        s += P.part[((size_t)(cb * gridDim.x + bx) * 3 + a) * KC + q];
+      s *= P.scale[c];
+      if (a == 0) P.alpha_out[c] = s;
+      else if (a == 1) { if (P.ov1) P.yre_out[c] = s; }
+      else { if (P.ov1) P.yim_out[c] = s; }
+    }
+    if (threadIdx.x == 0) *P.counter = 0u;
+  }
+}
+
+// Spin-1/2 systems with N >= 8: tile = 256 rows whose low 8 bits run over the
+// lanes; bits >= 8 (the tile index) are uniform over the block.
+template <typename R, int KC>
+__global__ __launch_bounds__(kBlock) void hv_half(HamGeom g, DevTables<R> tb, HvParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = g.n, np = g.npair;
+  Cx<R> *s_pc = reinterpret_cast<Cx<R> *>(smem);   // [np][4]
+  Cx<R> *s_hf = s_pc + 4 * np;                     // [n][2]
+  Cx<R> *s_fh = s_hf + 2 * n;                      // [n][2] high part of F (per tile)
+  R *s_hd = reinterpret_cast<R *>(s_fh + 2 * n);   // [n][2]
+  R *s_phi = s_hd + 2 * n;                         // [8]
+  R *s_dt = s_phi + 8;                             // [n]
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.y * KC;
+  for (int i = t; i < 4 * np; i += kBlock) s_pc[i] = tb.pc_half[i];
+  for (int i = t; i < 2 * n; i += kBlock) {
+    s_hf[i] = tb.hflip[i];
+    s_hd[i] = tb.hdiag[(i >> 1) * 16 + (i & 1)];
+  }
+  __syncthreads();
+  // low-bit part of the diagonal (identical for every tile)
+  R dlow = 0;
+  for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((t >> k) & 1)];
+  for (int p = 0; p < g.n_ll; p++) {
+    const int2 ij = tb.pij[p];
+    const R mm = (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25);
+    dlow = fma(tb.pzz[p], mm, dlow);
+  }
+  const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v) + c0;
+  double red[3][KC];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int q = 0; q < KC; q++) red[a][q] = 0.0;
+
+  for (uint32_t tile = blockIdx.x; tile < P.ntile; tile += gridDim.x) {
+    const uint32_t hi = tile << kLowBits;  // row bits >= 8
+    __syncthreads();
+    if (t < 2 * n) {
+      const int k = t >> 1, sel = t & 1;
+      R fr = 0, fi = 0;
+      for (int l = kLowBits; l < n; l++) {
+        if (l == k) continue;
+        const R ml = ((hi >> l) & 1) ? R(0.5) : R(-0.5);
+        const Cx<R> c = tb.cz_half[(k * n + l) * 2 + sel];
+        fr = fma(c.re, ml, fr);
+        fi = fma(c.im, ml, fi);
+      }
+      s_fh[t] = Cx<R>{fr, fi};
+    } else if (t >= 64 && t < 64 + kLowBits) {
+      const int i = t - 64;
+      R ph = 0;
+      for (int j = kLowBits; j < n; j++) ph = fma(tb.zz[i * n + j], ((hi >> j) & 1) ? R(0.5) : R(-0.5), ph);
+      s_phi[i] = ph;
+    } else if (t >= 128 && t < 128 + n - kLowBits) {
+      const int k = kLowBits + (t - 128);
+      const R mk = ((hi >> k) & 1) ? R(0.5) : R(-0.5);
+      R acc = s_hd[2 * k + ((hi >> k) & 1)];
+      for (int j = k + 1; j < n; j++) acc = fma(tb.zz[k * n + j] * mk, ((hi >> j) & 1) ? R(0.5) : R(-0.5), acc);
+      s_dt[k - kLowBits] = acc;
+    }
+    __syncthreads();
+    R diag = dlow;
+    for (int k = 0; k < n - kLowBits; k++) diag += s_dt[k];
+#pragma unroll
+    for (int i = 0; i < kLowBits; i++) diag = fma(((t >> i) & 1) ? R(0.5) : R(-0.5), s_phi[i], diag);
+
+    const uint32_t row = hi | (uint32_t)t;
+    Acc<R, KC> acc;
+    acc_zero(acc);
+    const Cx<R> *own = v + (size_t)row * P.K;
+    mac_real(acc, diag, own);
+    // single-site flips: h_k[b][1-b] + F_k (s^{+-}_k s^z_l pieces)
+    for (int k = 0; k < n; k++) {
+      const int b = (row >> k) & 1;
+      const Cx<R> a1 = s_hf[2 * k + b], a2 = s_fh[2 * k + b];
+      const Cx<R> a3 = tb.lowf[(k * 2 + b) * 256 + t];
+      const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
+      mac(acc, c, v + (size_t)(row ^ (1u << k)) * P.K);
+    }
+    // pair flips: exactly one of the four ladder pairs connects each row
+    for (int p = 0; p < np; p++) {
+      const int2 ij = tb.pij[p];
+      const int type = (((row >> ij.x) & 1) << 1) | ((row >> ij.y) & 1);
+      const Cx<R> c = s_pc[4 * p + type];
+      mac(acc, c, v + (size_t)(row ^ ((1u << ij.x) | (1u << ij.y))) * P.K);
+    }
+    hv_epilogue<R, KC>(P, row, c0, acc, own, red);
+  }
+  hv_finish<KC>(P, red);
+}
+
+// General mixed-radix systems (any 2 s_i <= 15, N <= 32).
+template <typename R, int KC>
+__global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, HvParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = g.n;
+  Cx<R> *s_hoff = reinterpret_cast<Cx<R> *>(smem);  // [n][4][16]
+  R *s_hd = reinterpret_cast<R *>(s_hoff + n * 64);  // [n][16]
+  R *s_gp = s_hd + n * 16;
+  R *s_gm = s_gp + n * 16;
+  R *s_m = s_gm + n * 16;
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.y * KC;
+  for (int i = t; i < n * 64; i += kBlock) s_hoff[i] = tb.hoff[i];
+  for (int i = t; i < n * 16; i += kBlock) {
+    s_hd[i] = tb.hdiag[i];
+    s_gp[i] = tb.gp[i];
+    s_gm[i] = tb.gm[i];
+    s_m[i] = tb.mval[i];
+  }
+  __syncthreads();
+  const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v) + c0;
+  double red[3][KC];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int q = 0; q < KC; q++) red[a][q] = 0.0;
+
+  for (uint32_t tile = blockIdx.x; tile < P.ntile; tile += gridDim.x) {
+    const uint32_t row = tile * kBlock + t;
+    if (row >= g.dim) continue;
+    // digits, 4 bits each: sites 0..15 in dlo, 16..31 in dhi
+    uint64_t dlo = 0, dhi = 0;
+    {
+      uint32_t rem = row;
+      for (int k = 0; k < n; k++) {
+        const uint32_t r = (uint32_t)g.radix[k];
+        const uint32_t q = rem / r;
+        const uint64_t dk = rem - q * r;
+        rem = q;
+        if (k < 16) dlo |= dk << (4 * k);
+        else dhi |= dk << (4 * (k - 16));
+      }
+    }
+    auto digit = [&](int k) -> int {
+      return (int)(((k < 16) ? (dlo >> (4 * k)) : (dhi >> (4 * (k - 16)))) & 15u);
+    };
+    R diag = 0;
+    for (int k = 0; k < n; k++) diag += s_hd[k * 16 + digit(k)];
+    for (int p = 0; p < g.npair; p++) {
+      const int2 ij = tb.pij[p];
+      diag = fma(tb.pzz[p], s_m[ij.x * 16 + digit(ij.x)] * s_m[ij.y * 16 + digit(ij.y)], diag);
+    }
+    Acc<R, KC> acc;
+    acc_zero(acc);
+    const Cx<R> *own = v + (size_t)row * P.K;
+    mac_real(acc, diag, own);
+    for (int k = 0; k < n; k++) {
+      const int dk = digit(k), rk = g.radix[k];
+      const uint32_t st = g.stride[k];
+      R fpr = 0, fpi = 0, fmr = 0, fmi = 0;
+      if (g.has_z) {
+        for (int l = 0; l < n; l++) {
+          if (l == k) continue;
+          const R ml = s_m[l * 16 + digit(l)];
+          const Cx<R> cp = tb.czp[k * n + l], cm = tb.czm[k * n + l];
+          fpr = fma(cp.re, ml, fpr);
+          fpi = fma(cp.im, ml, fpi);
+          fmr = fma(cm.re, ml, fmr);
+          fmi = fma(cm.im, ml, fmi);
+        }
+      }
+#pragma unroll
+      for (int di = 0; di < 4; di++) {
+        const int D = (di < 2) ? di - 2 : di - 1;  // -2,-1,+1,+2
+        const int nd = dk + D;
+        if (nd < 0 || nd >= rk) continue;
+        Cx<R> c = s_hoff[(k * 4 + di) * 16 + dk];
+        if (D == -1) {
+          const R gg = s_gp[k * 16 + dk];
+          c.re = fma(gg, fpr, c.re);
+          c.im = fma(gg, fpi, c.im);
+        } else if (D == 1) {
+          const R gg = s_gm[k * 16 + dk];
+          c.re = fma(gg, fmr, c.re);
+          c.im = fma(gg, fmi, c.im);
+        }
+        const uint32_t partner = row + (uint32_t)(D * (int)st);
+        mac(acc, c, v + (size_t)partner * P.K);
+      }
+    }
+    for (int p = 0; p < g.npair; p++) {
+      const int2 ij = tb.pij[p];
+      const int di = digit(ij.x), dj = digit(ij.y);
+      const int ri = g.radix[ij.x], rj = g.radix[ij.y];
+      const uint32_t si = g.stride[ij.x], sj = g.stride[ij.y];
+      const R gpi = s_gp[ij.x * 16 + di], gmi = s_gm[ij.x * 16 + di];
+      const R gpj = s_gp[ij.y * 16 + dj], gmj = s_gm[ij.y * 16 + dj];
+      const Cx<R> *pc = tb.pc + 4 * p;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const Cx<R> cq = pc[q];
+        if (cq.re == R(0) && cq.im == R(0)) continue;
+        const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;  // '-' ladder on site i / j
+        const bool vi = im_ ? (di <= ri - 2) : (di >= 1);
+        const bool vj = jm ? (dj <= rj - 2) : (dj >= 1);
+        if (!(vi && vj)) continue;
+        const R f = (im_ ? gmi : gpi) * (jm ? gmj : gpj);
+        const uint32_t partner = row + (im_ ? si : (uint32_t)(-(int)si)) + (jm ? sj : (uint32_t)(-(int)sj));
+        mac(acc, Cx<R>{cq.re * f, cq.im * f}, v + (size_t)partner * P.K);
+      }
+    }
+    hv_epilogue<R, KC>(P, row, c0, acc, own, red);
+  }
+  hv_finish<KC>(P, red);
+}
+
+template <typename R>
+static size_t hv_smem(const HamGeom &g) {
+  if (g.spin_half && g.n >= kLowBits)
+    return sizeof(Cx<R>) * (4 * (size_t)g.npair + 4 * g.n) + sizeof(R) * (3 * g.n + 8);
+  return sizeof(Cx<R>) * 64 * (size_t)g.n + sizeof(R) * 64 * g.n;
+}
+
+static int pick_kc(int K, int want) {
+  const int opts[4] = {8, 4, 2, 1};
+  for (int o : opts)
+    if (o <= want && K % o == 0) return o;
+  return 1;
+}
+
+int hv_grid_blocks(const DevHam &dh, const HvLaunch &L, int *gx, int *gy, int *kc) {
+  const HamGeom &g = dh.geom;
+  int want = L.kc > 0 ? L.kc : 8;
+  int k = pick_kc(L.K, want);
+  uint32_t ntile = (g.spin_half && g.n >= kLowBits) ? (g.dim >> kLowBits)
+                                                     : (uint32_t)(((uint64_t)g.dim + kBlock - 1) / kBlock);
+  int cap = L.grid_cap > 0 ? L.grid_cap : 2048;
+  if (L.lz) cap = cap < 2048 ? cap : 2048;  // partials buffer holds 2048 slots per column block
+  *gx = (int)(ntile < (uint32_t)cap ? ntile : (uint32_t)cap);
+  *gy = L.K / k;
+  *kc = k;
+  return FTLM_OK;
+}
+
+template <typename R, int KC>
+static void launch_hv_t(const DevHam &dh, const DevTables<R> &tb, const HvParams &P, dim3 grid,
+                        hipStream_t s) {
+  const HamGeom &g = dh.geom;
+  const size_t sm = hv_smem<R>(g);
+  if (g.spin_half && g.n >= kLowBits)
+    hipLaunchKernelGGL((hv_half<R, KC>), grid, dim3(kBlock), sm, s, g, tb, P);
+  else
+    hipLaunchKernelGGL((hv_gen<R, KC>), grid, dim3(kBlock), sm, s, g, tb, P);
+}
+
+template <typename R>
+static void launch_hv_r(const DevHam &dh, const DevTables<R> &tb, const HvParams &P, dim3 grid,
+                        int kc, hipStream_t s) {
+  switch (kc) {
+    case 8: launch_hv_t<R, 8>(dh, tb, P, grid, s); break;
+    case 4: launch_hv_t<R, 4>(dh, tb, P, grid, s); break;
+    case 2: launch_hv_t<R, 2>(dh, tb, P, grid, s); break;
+    default: launch_hv_t<R, 1>(dh, tb, P, grid, s); break;
+  }
+}
+
+int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s) {
+  int gx, gy, kc;
+  hv_grid_blocks(dh, L, &gx, &gy, &kc);
+  HvParams P{};
+  P.K = L.K;
+  P.ntile = (dh.geom.spin_half && dh.geom.n >= kLowBits)
+                ? (dh.geom.dim >> kLowBits)
+                : (uint32_t)(((uint64_t)dh.geom.dim + kBlock - 1) / kBlock);
+  P.v = L.v;
+  P.w = L.w;
+  P.scale = L.scale;
+  if (L.lz) {
+    P.lanczos = 1;
+    P.scale = L.lz->sx_cur;
+    P.xprev = L.lz->xprev;
+    P.ov1 = L.lz->ov1;
+    P.sx_prev = L.lz->sx_prev;
+    P.beta_prev = L.lz->beta_prev;
+    P.part = L.lz->part;
+    P.counter = L.lz->counter;
+    P.alpha_out = L.lz->alpha_out;
+    P.yre_out = L.lz->yre_out;
+    P.yim_out = L.lz->yim_out;
+  }
+  dim3 grid(gx, gy);
+  if (L.precision == FTLM_C64) launch_hv_r<float>(dh, dh.t32, P, grid, kc, s);
+  else launch_hv_r<double>(dh, dh.t64, P, grid, kc, s);
+  return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
+}
+
+// ------------------------------------------------------------------ start vectors
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies with the round constants 0xD2511F53 / 0xCD9E8D57 and Weyl key
+// increments 0x9E3779B9 / 0xBB67AE85.
+__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ void gauss(uint64_t seed, uint32_t nu, uint32_t r, uint32_t f,
+                                      uint32_t inst, double &x, double &y) {
+  uint32_t c[4] = {nu, r, f, inst};
+  philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t a = ((uint64_t)(c[0] >> 5) << 26) | (c[1] >> 6);
+  const uint64_t b = ((uint64_t)(c[2] >> 5) << 26) | (c[3] >> 6);
+  const double u1 = (double)(a + 1) * 0x1.0p-53;
+  const double u2 = (double)b * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos(2.0 * M_PI * u2, &sn, &cs);
+  x = rad * cs;
+  y = rad * sn;
+}
+
+struct StartParams {
+  uint64_t seed;
+  uint32_t inst, field, r0;
+  int K;
+  uint32_t dim;
+  void *out;
+  const double2 *src;  // copy mode: source [dim][src_cols] c128
+  int src_cols, col0;
+  double *part;
+  unsigned *counter;
+  double *sx0;
+};
+
+template <typename R, int KC, bool COPY>
+__global__ __launch_bounds__(kBlock) void start_kernel(StartParams S) {
+  const int c0 = blockIdx.y * KC;
+  double red[1][KC];
+#pragma unroll
+  for (int q = 0; q < KC; q++) red[0][q] = 0.0;
+  Cx<R> *out = reinterpret_cast<Cx<R> *>(S.out);
+  for (uint32_t row = blockIdx.x * kBlock + threadIdx.x; row < S.dim; row += gridDim.x * kBlock) {
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      double x, y;
+      if (COPY) {
+        const double2 z = S.src[(size_t)row * S.src_cols + S.col0 + c0 + q];
+        x = z.x;
+        y = z.y;
+      } else {
+        gauss(S.seed, row, S.r0 + c0 + q, S.field, S.inst, x, y);
+      }
+      const Cx<R> z{(R)x, (R)y};
+      out[(size_t)row * S.K + c0 + q] = z;
+      red[0][q] += (double)z.re * (double)z.re + (double)z.im * (double)z.im;
+    }
+  }
+  const unsigned total = gridDim.x * gridDim.y;
+  if (block_partials<1, KC>(red, S.part, blockIdx.y * gridDim.x + blockIdx.x, S.counter, total)) {
+    const int ncol = gridDim.y * KC;
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+      const int cb = c / KC, q = c % KC;
+      double s = 0;
+      for (unsigned bx = 0; bx < gridDim.x; bx++) s += S.part[(size_t)(cb * gridDim.x + bx) * KC + q];
+      S.sx0[c] = s > 0 ? 1.0 / sqrt(s) : 0.0;
+    }
+    if (threadIdx.x == 0) *S.counter = 0u;
+  }
+}
+
+template <typename R, bool COPY>
+static void launch_start_r(const StartParams &S, int grid_cap, hipStream_t s) {
+  const int kc = pick_kc(S.K, 8);
+  uint32_t nb = (uint32_t)(((uint64_t)S.dim + kBlock - 1) / kBlock);
+  const uint32_t cap = grid_cap > 0 ? (uint32_t)grid_cap : 2048u;
+  dim3 grid(nb < cap ? nb : cap, S.K / kc);
+  switch (kc) {
+    case 8: hipLaunchKernelGGL((start_kernel<R, 8, COPY>), grid, dim3(kBlock), 0, s, S); break;
+    case 4: hipLaunchKernelGGL((start_kernel<R, 4, COPY>), grid, dim3(kBlock), 0, s, S); break;
+    case 2: hipLaunchKernelGGL((start_kernel<R, 2, COPY>), grid, dim3(kBlock), 0, s, S); break;
+    default: hipLaunchKernelGGL((start_kernel<R, 1, COPY>), grid, dim3(kBlock), 0, s, S); break;
+  }
+}
+
+int launch_gaussian(uint64_t seed, uint32_t inst, uint32_t field, uint32_t r0, int K,
+                    uint32_t dim, int precision, void *out, double *part, unsigned *counter,
+                    double *sx0, int grid_cap, hipStream_t s) {
+  StartParams S{};
+  S.seed = seed;
+  S.inst = inst;
+  S.field = field;
+  S.r0 = r0;
+  S.K = K;
+  S.dim = dim;
+  S.out = out;
+  S.part = part;
+  S.counter = counter;
+  S.sx0 = sx0;
+  if (precision == FTLM_C64) launch_start_r<float, false>(S, grid_cap, s);
+  else launch_start_r<double, false>(S, grid_cap, s);
+  return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
+}
+
+int launch_copy_start(const void *src_c128, int src_cols, int col0, int K, uint32_t dim,
+                      int precision, void *out, double *part, unsigned *counter, double *sx0,
+                      int grid_cap, hipStream_t s) {
+  StartParams S{};
+  S.K = K;
+  S.dim = dim;
+  S.out = out;
+  S.src = reinterpret_cast<const double2 *>(src_c128);
+  S.src_cols = src_cols;
+  S.col0 = col0;
+  S.part = part;
+  S.counter = counter;
+  S.sx0 = sx0;
+  if (precision == FTLM_C64) launch_start_r<float, true>(S, grid_cap, s);
+  else launch_start_r<double, true>(S, grid_cap, s);
+  return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
+}
+
+// ------------------------------------------------------------------ Lanczos update
+template <typename R, int KC>
+__global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs A) {
+  const int c0 = blockIdx.y * KC;
+  double red[1][KC];
+  double coef[KC];
+#pragma unroll
+  for (int q = 0; q < KC; q++) {
+    red[0][q] = 0.0;
+    coef[q] = A.alpha[c0 + q] * A.sx_cur[c0 + q];
+  }
+  Cx<R> *w = reinterpret_cast<Cx<R> *>(A.w);
+  const Cx<R> *x = reinterpret_cast<const Cx<R> *>(A.x);
+  for (uint32_t row = blockIdx.x * kBlock + threadIdx.x; row < A.dim; row += gridDim.x * kBlock) {
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      const size_t o = (size_t)row * A.K + c0 + q;
+      const Cx<R> a = w[o], b = x[o];
+      const double ur = (double)a.re - coef[q] * (double)b.re;
+      const double ui = (double)a.im - coef[q] * (double)b.im;
+      const Cx<R> u{(R)ur, (R)ui};
+      w[o] = u;
+      red[0][q] += (double)u.re * (double)u.re + (double)u.im * (double)u.im;
+    }
+  }
+  const unsigned total = gridDim.x * gridDim.y;
+  if (block_partials<1, KC>(red, A.part, blockIdx.y * gridDim.x + blockIdx.x, A.counter, total)) {
+    const int ncol = gridDim.y * KC;
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+      const int cb = c / KC, q = c % KC;
+      double s = 0;
+      for (unsigned bx = 0; bx < gridDim.x; bx++) s += A.part[(size_t)(cb * gridDim.x + bx) * KC + q];
+      double b = sqrt(s);
+      const double al = fabs(A.alpha[c]);
+      double sm = A.scale_max[c];
+      if (al > sm) sm = al;
+      if (A.done[c]) {
+        A.beta[c] = 0.0;
+        A.sx_next[c] = 0.0;
+      } else {
+        A.n_used[c] = A.step + 1;
+        const bool breakdown = (A.step + 1 < A.n_lanczos) && !(b > 1e-12 * sm);
+        A.beta[c] = b;
+        if (breakdown) {
+          A.done[c] = 1;
+          A.sx_next[c] = 0.0;
+        } else {
+          A.sx_next[c] = b > 0 ? 1.0 / b : 0.0;
+        }
+        if (b > sm) sm = b;
+      }
+      A.scale_max[c] = sm;
+    }
+    if (threadIdx.x == 0) *A.counter = 0u;
+  }
+}
+
+int launch_update(const UpdateArgs &a, hipStream_t s) {
+  const int kc = pick_kc(a.K, 8);
+  uint32_t nb = (uint32_t)(((uint64_t)a.dim + kBlock - 1) / kBlock);
+  const uint32_t cap = a.grid_cap > 0 ? (uint32_t)a.grid_cap : 2048u;
+  dim3 grid(nb < cap ? nb : cap, a.K / kc);
+  const bool f32 = a.precision == FTLM_C64;
+  switch (kc) {
+    case 8:
+      if (f32) hipLaunchKernelGGL((update_kernel<float, 8>), grid, dim3(kBlock), 0, s, a);
+      else hipLaunchKernelGGL((update_kernel<double, 8>), grid, dim3(kBlock), 0, s, a);
+      break;
+    case 4:
+      if (f32) hipLaunchKernelGGL((update_kernel<float, 4>), grid, dim3(kBlock), 0, s, a);
+      else hipLaunchKernelGGL((update_kernel<double, 4>), grid, dim3(kBlock), 0, s, a);
+      break;
+    case 2:
+      if (f32) hipLaunchKernelGGL((update_kernel<float, 2>), grid, dim3(kBlock), 0, s, a);
+      else hipLaunchKernelGGL((update_kernel<double, 2>), grid, dim3(kBlock), 0, s, a);
+      break;
+    default:
+      if (f32) hipLaunchKernelGGL((update_kernel<float, 1>), grid, dim3(kBlock), 0, s, a);
+      else hipLaunchKernelGGL((update_kernel<double, 1>), grid, dim3(kBlock), 0, s, a);
+      break;
+  }
+  return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
+}
+
+__global__ void zero_state_kernel(double *scale_max, int *done, int *n_used, unsigned *counters,
+                                  int n_counters, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) {
+    scale_max[i] = 0.0;
+    done[i] = 0;
+    n_used[i] = 0;
+  }
+  if (i < n_counters) counters[i] = 0u;
+}
+
+int launch_zero_state(double *scale_max, int *done, int *n_used, unsigned *counters,
+                      int n_counters, int K, hipStream_t s) {
+  const int n = K > n_counters ? K : n_counters;
+  hipLaunchKernelGGL(zero_state_kernel, dim3((n + 255) / 256), dim3(256), 0, s, scale_max, done,
+                     n_used, counters, n_counters, K);
+  return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
+}
+
+// ------------------------------------------------------------------ tridiagonal
+// Implicit QL with shifts on T = tridiag(alpha, beta) (n <= n_lanczos), one
+// thread per column; Z = product of the plane rotations, of which only the rows
+// e_1^T Z (-> Q_1n) and y^T Z (-> sum_a y_a Q_an) are carried along.
+// Scratch layout [4][n_lanczos][n_cols].
+__global__ void tridiag_kernel(int n_cols, int nl, const int *n_used, int used_stride,
+                               int in_stride, const double *alpha, const double *beta, const double *y,
+                               double *eps, double *q1, double *qy, int out_stride, int out_col0,
+                               double *scratch) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n_cols) return;
+  const int n = n_used ? n_used[col * used_stride] : nl;
+  const size_t S = (size_t)n_cols;
+  double *d = scratch + col;
+  double *e = scratch + (size_t)nl * S + col;
+  double *z1 = scratch + 2 * (size_t)nl * S + col;
+  double *zy = scratch + 3 * (size_t)nl * S + col;
+#define AT(p, i) (p)[(size_t)(i)*S]
+  for (int i = 0; i < n; i++) {
+    AT(d, i) = alpha[(size_t)i * in_stride + col];
+    AT(e, i) = (i + 1 < n) ? beta[(size_t)i * in_stride + col] : 0.0;
+    AT(z1, i) = (i == 0) ? 1.0 : 0.0;
+    AT(zy, i) = y ? y[(size_t)i * in_stride + col] : 0.0;
+  }
+  for (int l = 0; l < n; l++) {
+    int iter = 0;
+    while (true) {
+      int m = l;
+      for (; m < n - 1; m++) {
+        const double dd = fabs(AT(d, m)) + fabs(AT(d, m + 1));
+        if (fabs(AT(e, m)) <= 2.220446049250313e-16 * dd) break;
+      }
+      if (m == l || iter++ >= 100) break;
+      double gg = (AT(d, l + 1) - AT(d, l)) / (2.0 * AT(e, l));
+      double r = hypot(gg, 1.0);
+      gg = AT(d, m) - AT(d, l) + AT(e, l) / (gg + copysign(r, gg));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = m - 1;
+      bool underflow = false;
+      for (; i >= l; i--) {
+        const double f = s * AT(e, i), b = c * AT(e, i);
+        r = hypot(f, gg);
+        AT(e, i + 1) = r;
+        if (r == 0.0) {
+          AT(d, i + 1) -= p;
+          AT(e, m) = 0.0;
+          underflow = true;
+          break;
+        }
+        s = f / r;
+        c = gg / r;
+        gg = AT(d, i + 1) - p;
+        r = (AT(d, i) - gg) * s + 2.0 * c * b;
+        p = s * r;
+        AT(d, i + 1) = gg + p;
+        gg = c * r - b;
+        // rotate columns i, i+1 of Z in the two tracked rows
+        double fz = AT(z1, i + 1);
+        AT(z1, i + 1) = s * AT(z1, i) + c * fz;
+        AT(z1, i) = c * AT(z1, i) - s * fz;
+        fz = AT(zy, i + 1);
+        AT(zy, i + 1) = s * AT(zy, i) + c * fz;
+        AT(zy, i) = c * AT(zy, i) - s * fz;
+      }
+      if (underflow) continue;
+      AT(d, l) -= p;
+      AT(e, l) = gg;
+      AT(e, m) = 0.0;
+    }
+  }
+  const size_t os = (size_t)out_stride;
+  for (int i = 0; i < nl; i++) {
+    const bool ok = i < n;
+    eps[(size_t)i * os + out_col0 + col] = ok ? AT(d, i) : 0.0;
+    q1[(size_t)i * os + out_col0 + col] = ok ? AT(z1, i) : 0.0;
+    qy[(size_t)i * os + out_col0 + col] = ok ? AT(zy, i) : 0.0;
+  }
+#undef AT
+}
+
+int launch_tridiag(int n_cols, int n_lanczos, const int *n_used, int used_stride, int in_stride,
+                   const double *alpha, const double *beta, const double *y, double *eps,
+                   double *q1, double *qy, int out_stride, int out_col0, double *scratch,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(tridiag_kernel, dim3((n_cols + 63) / 64), dim3(64), 0, s, n_cols, n_lanczos,
+                     n_used, used_stride, in_stride, alpha, beta, y, eps, q1, qy, out_stride, out_col0,
+                     scratch);
+  return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
+}
+
+// ------------------------------------------------------------------ Boltzmann sums
+// One thread per (curve, temperature).  Columns f*R .. f*R+R-1 of the
+// [n_lanczos][n_curves*R] arrays belong to curve f.  With
+//   l_{rn} = ln Q_1n^2 - (eps_n - E_min)/T,  lmax = max l:
+//   ln Z = ln(dim/R) - E_min/T + lmax + ln sum exp(l - lmax)        (Eq. E-2-D)
+//   <A>  = sum exp(l - lmax) A(eps) / sum exp(l - lmax)
+//   M    = sum exp(-(eps-E_min)/T - lmax) Q_1n (sum_a Q_an y_a) / sum exp(l - lmax)
+__global__ void boltzmann_kernel(int n_curves, int R, int nl, const int *n_used,
+                                 const double *eps, const double *q1, const double *qy,
+                                 const double *dims, const double *T, int n_T, double *lnZ,
+                                 double *E, double *C, double *M, double *E_min) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n_curves * n_T) return;
+  const int f = id / n_T, it = id % n_T;
+  const int ncol = n_curves * R;
+  const double temp = T[it];
+  double emin = INFINITY;
+  for (int r = 0; r < R; r++) {
+    const int c = f * R + r;
+    const int n = n_used[c];
+    for (int i = 0; i < n; i++) emin = fmin(emin, eps[(size_t)i * ncol + c]);
+  }
+  double lmax = -INFINITY;
+  for (int r = 0; r < R; r++) {
+    const int c = f * R + r;
+    const int n = n_used[c];
+    for (int i = 0; i < n; i++) {
+      const double qq = q1[(size_t)i * ncol + c];
+      if (qq == 0.0) continue;
+      const double l = log(qq * qq) - (eps[(size_t)i * ncol + c] - emin) / temp;
+      lmax = fmax(lmax, l);
+    }
+  }
+  double z = 0, ez = 0, mz = 0;
+  for (int r = 0; r < R; r++) {
+    const int c = f * R + r;
+    const int n = n_used[c];
+    for (int i = 0; i < n; i++) {
+      const size_t o = (size_t)i * ncol + c;
+      const double w = exp(-(eps[o] - emin) / temp - lmax);
+      const double qq = q1[o];
+      z += w * qq * qq;
+      ez += w * qq * qq * eps[o];
+      mz += w * qq * qy[o];
+    }
+  }
+  const double em = ez / z;
+  double cz = 0;
+  for (int r = 0; r < R; r++) {
+    const int c = f * R + r;
+    const int n = n_used[c];
+    for (int i = 0; i < n; i++) {
+      const size_t o = (size_t)i * ncol + c;
+      const double w = exp(-(eps[o] - emin) / temp - lmax);
+      const double qq = q1[o];
+      const double de = eps[o] - em;
+      cz += w * qq * qq * de * de;
+    }
+  }
+  const size_t out = (size_t)f * n_T + it;
+  lnZ[out] = log(dims[f] / R) - emin / temp + lmax + log(z);
+  E[out] = em;
+  C[out] = cz / z / (temp * temp);
+  M[out] = mz / z;
+  if (it == 0 && E_min) E_min[f] = emin;
+}
+
+int launch_boltzmann(int n_curves, int R, int n_lanczos, const int *n_used, const double *eps,
+                     const double *q1, const double *qy, const double *dims, const double *T,
+                     int n_T, double *lnZ, double *E, double *C, double *M, double *E_min,
+                     hipStream_t s) {
+  const int n = n_curves * n_T;
+  hipLaunchKernelGGL(boltzmann_kernel, dim3((n + 127) / 128), dim3(128), 0, s, n_curves, R,
+                     n_lanczos, n_used, eps, q1, qy, dims, T, n_T, lnZ, E, C, M, E_min);
+  return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
+}
+
+}  // namespace ftlm

@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI library: it loads, exports every declared entry point,
+and the host-side argument checks reject bad input without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ftlm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ftlm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def libftlm():
+    from paper_2607_25585_amd import _ffi
+    if not os.path.exists(_ffi.LIB_PATH):
+        from paper_2607_25585_amd import build
+        build.build()
+    return _ffi.lib()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("ftlm_hamiltonian_create", "ftlm_apply", "ftlm_run", "ftlm_run_batched",
+                 "ftlm_tridiag_eigen", "ftlm_boltzmann", "ftlm_mlp_forward",
+                 "ftlm_mlp_backward", "ftlm_adam_step", "ftlm_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(libftlm):
+    missing = [n for n in _declared() if not hasattr(libftlm, n)]
+    assert not missing, missing
+
+
+def test_version(libftlm):
+    assert libftlm.ftlm_version() >= 10000
+
+
+def test_library_is_gfx950_code_object():
+    from paper_2607_25585_amd import _ffi
+    data = open(_ffi.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_create_rejects_bad_arguments_on_host(libftlm):
+    """Validation happens before any device call, so it is testable on the CPU."""
+    from paper_2607_25585_amd import _ffi
+    h = ctypes.c_void_p()
+    assert libftlm.ftlm_hamiltonian_create(None, ctypes.byref(h)) == -1
+    two_s = (ctypes.c_int32 * 2)(1, 16)
+    g = (ctypes.c_double * 2)(2.0, 2.0)
+    B = (ctypes.c_double * 3)(0, 0, 1)
+    s = _ffi.FtlmSystem(2, two_s, None, None, None, g, B, None)
+    assert libftlm.ftlm_hamiltonian_create(ctypes.byref(s), ctypes.byref(h)) == -4  # 2s > 15
+    two_s = (ctypes.c_int32 * 2)(1, 1)
+    pos = (ctypes.c_double * 6)(0, 0, 0, 0, 0, 0)
+    s = _ffi.FtlmSystem(2, two_s, None, None, None, g, B, pos)
+    assert libftlm.ftlm_hamiltonian_create(ctypes.byref(s), ctypes.byref(h)) == -1  # coincident
+    assert b"coincident" in libftlm.ftlm_last_error()
+    big = (ctypes.c_int32 * 17)(*([3] * 17))  # 4^17 > 2^32
+    g17 = (ctypes.c_double * 17)(*([2.0] * 17))
+    s = _ffi.FtlmSystem(17, big, None, None, None, g17, B, None)
+    assert libftlm.ftlm_hamiltonian_create(ctypes.byref(s), ctypes.byref(h)) == -4
+
+
+def test_apply_and_run_reject_null(libftlm):
+    assert libftlm.ftlm_apply(None, 0, 1, None, None, None) == -1
+    assert libftlm.ftlm_run(None, None, None, 0, None, None) == -1
+    assert libftlm.ftlm_gaussian_vectors(1, 0, 0, 0, 0, 10, None, None) == -1
