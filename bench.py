@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the FTLM hot path on one MI355X.
+
+Workload (default): 24 spins s=1/2 on a ring, J = 1 K nearest neighbour plus
+all-pairs dipolar coupling at seeded positions on a 1 nm sphere, g = 2,
+B = 0.5 T along a seeded direction; Hilbert dimension 2^24; complex128;
+R = 10 Gaussian random vectors, N_L = 150 Lanczos steps, 200 temperatures.
+One step = one complete FTLM curve: start vectors, O v_1, 150 Lanczos steps
+(H*v + update), Krylov eigenpairs, Boltzmann sums for ln Z, E, C, M.
+
+Prints one JSON line.  value = FTLM curves per second (inputs resident in HBM).
+roofline = the dominant kernel (the Lanczos H*v launch): algorithmic flops
+8 * nnz/row * dim * columns per launch over its mean duration measured with HIP
+events around each launch in one extra profiled run.
+cpu_baseline = the CPU oracle (plain C, OpenMP) timed on a bounded sample: a few
+of its H*v products on one column of the same workload, extrapolated to curves/s
+as R * N_L products per curve (vector updates, tridiagonal and sums ignored).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3}  # TFLOP/s, MI355X published vector peaks
+HBM_PEAK_GBPS = 8000.0
+
+
+def _kernel_sha():
+    p = os.path.join(ROOT, "paper_2607_25585_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(workload, precision):
+    """HBM bytes per H*v launch from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "hv_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        e = d.get("%s_%s" % (workload, precision))
+        if not e or e.get("kernel_sha") != _kernel_sha():
+            return None
+        return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(sysm, spec, budget_s=12.0):
+    import numpy as np
+    from oracle import ftlm as of
+    ham = of.Ham(sysm)
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(ham.dim) + 1j * rng.standard_normal(ham.dim)
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        v = ham.apply(v)
+        v /= np.linalg.norm(v)
+        times.append(time.perf_counter() - t0)
+        if len(times) >= 2 and time.perf_counter() - t_start > budget_s:
+            break
+        if len(times) >= 20:
+            break
+    t_hv = float(np.median(times))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / (spec.R * spec.n_lanczos * t_hv), "unit": "curves/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d oracle H*v products on one column (%.2f s each, median), "
+                      "extrapolated x R*N_L = %d per curve" % (len(times), t_hv,
+                                                               spec.R * spec.n_lanczos)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg2_hb", "cfg4", "cfg4_hb"])
+    ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--columns", type=int, default=0,
+                    help="random vectors iterated together (0 = library default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import ftlm_workloads as W
+    import paper_2607_25585_amd as F
+
+    torch.cuda.set_device(0)
+    sysm, spec = W.WORKLOADS[args.workload]()
+    prec = F.FTLM_C128 if args.precision == "c128" else F.FTLM_C64
+    ham = F.Hamiltonian(sysm)
+    K = args.columns if args.columns > 0 else (1 if ham.dim >= (1 << 20) else min(spec.R, 16))
+    ws = None
+
+    def step(time_hv=False):
+        return F.run(ham, spec.R, spec.n_lanczos, spec.T, seed=spec.seed, precision=prec,
+                     columns=K, workspace=ws, time_hv=time_hv)
+
+    # size the workspace once, outside the timed region
+    import ctypes
+    from paper_2607_25585_amd import _ffi
+    p, keep = F._params(spec.R, spec.n_lanczos, spec.T, spec.seed, None, prec, K, None, 0)
+    nb = ctypes.c_size_t()
+    _ffi.check(_ffi.lib().ftlm_run_workspace_size(ham.handle, ctypes.byref(p), ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+
+    for _ in range(args.warmup):
+        step()
+        print("warmup step done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = step()
+        print("timed step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = args.steps / elapsed
+
+    prof = step(time_hv=True)
+    hv_ms = float(prof["hv_ms"][0] / max(int(prof["hv_launches"][0]), 1))
+    nnz = ham.nnz_per_row
+    flops = 8.0 * nnz * ham.dim * K
+    dt = "f64" if prec == F.FTLM_C128 else "f32"
+    achieved = flops / (hv_ms * 1e-3) / 1e12
+    es = 16 if prec == F.FTLM_C128 else 8
+    hv_gbps = 2.0 * es * ham.dim * K / (hv_ms * 1e-3) / 1e9
+    traffic = _traffic(args.workload, args.precision)
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK[dt], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[dt], 4), "traffic": traffic}
+
+    out = {
+        "metric": "H·v HBM GB/s; FTLM curves/s batched-FP32 vs plain FP64 at C(T) ≤1e-3 rel",
+        "value": round(value, 5),
+        "unit": "curves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == F.FTLM_C128 else "f32-storage/f64-recurrence",
+        "data": "synthetic",
+        "config": {"workload": "%s: N=%d spins, dim %d, %s, R=%d, N_L=%d, %d temperatures, "
+                               "%d columns per wave" % (args.workload, sysm.n_sites, ham.dim,
+                                                        args.precision, spec.R, spec.n_lanczos,
+                                                        len(spec.T), K),
+                   "nnz_per_row": round(nnz, 3)},
+        "hv_ms_per_launch": round(hv_ms, 4),
+        "hv_algorithmic_GBps": round(hv_gbps, 1),
+        "hv_hbm_frac_algorithmic": round(hv_gbps / HBM_PEAK_GBPS, 4),
+        "roofline": roof,
+        "E_min": float(res["E_min"][0]),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sysm, spec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

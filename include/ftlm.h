@@ -119,7 +119,8 @@ typedef struct {
                            the handle's field is restored on return */
   int32_t n_fields;
   int32_t precision;    /* ftlm_precision */
-  int32_t columns;      /* K: random vectors iterated together, 1..64; 0 = min(R, 16) */
+  int32_t columns;      /* K: random vectors iterated together, 1..64; 0 = automatic
+                           (1 for dim >= 2^20, else min(R, 16)) */
   const void *r_init;   /* optional device complex128 start vectors (not
                            normalised) replacing the generator, element (f, nu, r)
                            at offset (f*dim + nu)*R + r; NULL */
@@ -131,6 +132,10 @@ typedef struct {
   int32_t *n_lanczos_used;   /* [n_fields*R]; < N_L after a Lanczos breakdown */
   double *E_min;             /* [n_fields] lowest Ritz value over the R vectors */
   double *alpha, *beta;      /* [n_fields*R*N_L] tridiagonals (diagnostics) */
+  double *hv_ms;             /* if non-NULL: summed duration (ms) of the run's Lanczos
+                                H*v kernels, from HIP events recorded around each launch
+                                on the run's stream (the run then skips graph replay) */
+  int32_t *hv_launches;      /* number of H*v launches timed into *hv_ms */
 } ftlm_result;
 
 /* Bytes of device workspace ftlm_run needs for these parameters. */
@@ -205,6 +210,19 @@ int ftlm_mlp_backward(const ftlm_mlp_weights *w, int32_t batch, const float *t, 
  * bf16 copy pb (may be NULL).  step counts from 1. */
 int ftlm_adam_step(int64_t n, float *p, const float *grad, float *m, float *v, uint16_t *pb,
                    float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
+
+/* Host-only (no device work): compiles the Hamiltonian and reports the plan the
+ * one-column H*v uses in the given precision.  Each pass stages windows of rows
+ * that share every digit except those of its active sites and applies from LDS
+ * the terms it owns.  Per pass p < max_pass: window_rows[p], n_active[p] (sites
+ * spanning the window), n_pairs[p] (pair terms it applies), n_singles[p] (sites
+ * whose single-site flips it applies); pair_sites (may be NULL) receives the
+ * (i, j) sites of every pair term, pass by pass (2 * total pairs ints).
+ * nnz_per_row (may be NULL) as ftlm_hamiltonian_nnz_per_row. */
+int ftlm_describe_passes(const ftlm_system *sys, int32_t precision, int32_t max_pass,
+                         int32_t *n_pass, uint32_t *window_rows, int32_t *n_active,
+                         int32_t *n_pairs, int32_t *n_singles, int32_t *pair_sites,
+                         double *nnz_per_row);
 
 const char *ftlm_last_error(void);
 int ftlm_version(void);

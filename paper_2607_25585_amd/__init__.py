@@ -47,6 +47,43 @@ def _f64(a, shape=None):
     return out.reshape(shape) if shape is not None else out
 
 
+def _system_struct(system):
+    n = len(system.two_s)
+    keep = dict(two_s=np.ascontiguousarray(np.asarray(system.two_s, np.int32)),
+                J=_f64(system.J, (n, n)) if system.J is not None else None,
+                d=_f64(system.d) if system.d is not None else None,
+                e=_f64(system.e, (n, 3)) if system.e is not None else None,
+                g=_f64(system.g), B=_f64(system.B, (3,)),
+                pos=_f64(system.pos, (n, 3)) if system.pos is not None else None)
+    s = _ffi.FtlmSystem(n, keep["two_s"].ctypes.data_as(_ffi.c_int32_p), _dptr(keep["J"]),
+                        _dptr(keep["d"]), _dptr(keep["e"]), _dptr(keep["g"]), _dptr(keep["B"]),
+                        _dptr(keep["pos"]))
+    return s, keep
+
+
+def describe_passes(system, precision: int = FTLM_C128):
+    """Host-only: the windowed-pass plan of the one-column H*v (no GPU needed)."""
+    s, keep = _system_struct(system)
+    npass = ctypes.c_int32()
+    check(_ffi.lib().ftlm_describe_passes(ctypes.byref(s), int(precision), 0, ctypes.byref(npass),
+                                          None, None, None, None, None, None),
+          "ftlm_describe_passes")
+    m = npass.value
+    wr = np.zeros(m, np.uint32)
+    na, npp, ns = (np.zeros(m, np.int32) for _ in range(3))
+    n_pairs_total = 4096
+    ps = np.zeros(2 * n_pairs_total, np.int32)
+    nnz = ctypes.c_double()
+    i32 = lambda a: a.ctypes.data_as(_ffi.c_int32_p)  # noqa: E731
+    check(_ffi.lib().ftlm_describe_passes(ctypes.byref(s), int(precision), m, ctypes.byref(npass),
+                                          wr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                          i32(na), i32(npp), i32(ns), i32(ps), ctypes.byref(nnz)),
+          "ftlm_describe_passes")
+    tot = int(npp.sum())
+    return dict(window_rows=wr, n_active=na, n_pairs=npp, n_singles=ns,
+                pair_sites=ps[:2 * tot].reshape(-1, 2), nnz_per_row=nnz.value)
+
+
 class Hamiltonian:
     """Compiled Hamiltonian of Eq. (mce-hamop) on the current HIP device.
 
@@ -151,7 +188,7 @@ def _params(R, n_lanczos, T, seed, fields, precision, columns, r_init, instance)
 
 def run(ham: Hamiltonian, R: int, n_lanczos: int, T, seed: int = 0, fields=None,
         precision: int = FTLM_C128, columns: int = 0, r_init=None, instance: int = 0,
-        return_tridiagonals: bool = False, workspace=None):
+        return_tridiagonals: bool = False, workspace=None, time_hv: bool = False):
     """FTLM thermodynamics (Sec. 2.2) on the GPU.  Returns a dict of NumPy arrays
     lnZ, E, C, M ([n_fields, n_T]), n_lanczos_used ([n_fields, R]), E_min."""
     torch = _torch()
@@ -168,7 +205,12 @@ def run(ham: Hamiltonian, R: int, n_lanczos: int, T, seed: int = 0, fields=None,
     out["E_min"] = np.zeros(nf)
     res = _ffi.FtlmResult(_dptr(out["lnZ"]), _dptr(out["E"]), _dptr(out["C"]), _dptr(out["M"]),
                           out["n_lanczos_used"].ctypes.data_as(_ffi.c_int32_p),
-                          _dptr(out["E_min"]), None, None)
+                          _dptr(out["E_min"]), None, None, None, None)
+    if time_hv:
+        out["hv_ms"] = np.zeros(1)
+        out["hv_launches"] = np.zeros(1, np.int32)
+        res.hv_ms = _dptr(out["hv_ms"])
+        res.hv_launches = out["hv_launches"].ctypes.data_as(_ffi.c_int32_p)
     if return_tridiagonals:
         out["alpha"] = np.zeros((nf, R, n_lanczos))
         out["beta"] = np.zeros((nf, R, n_lanczos))
@@ -210,7 +252,7 @@ def run_batched(hams, R: int, n_lanczos: int, T, fields_per_inst, seed: int = 0,
         o["E_min"] = np.zeros(nf)
         resarr[k] = _ffi.FtlmResult(_dptr(o["lnZ"]), _dptr(o["E"]), _dptr(o["C"]), _dptr(o["M"]),
                                     o["n_lanczos_used"].ctypes.data_as(_ffi.c_int32_p),
-                                    _dptr(o["E_min"]), None, None)
+                                    _dptr(o["E_min"]), None, None, None, None)
         outs.append(o)
     check(_ffi.lib().ftlm_run_batched(hs, n, ps, ctypes.c_void_p(ws.data_ptr()),
                                       ctypes.c_size_t(ws.numel()), _stream(), resarr),

@@ -31,7 +31,7 @@ class FtlmRunParams(ctypes.Structure):
 class FtlmResult(ctypes.Structure):
     _fields_ = [("lnZ", c_double_p), ("E", c_double_p), ("C", c_double_p), ("M", c_double_p),
                 ("n_lanczos_used", c_int32_p), ("E_min", c_double_p), ("alpha", c_double_p),
-                ("beta", c_double_p)]
+                ("beta", c_double_p), ("hv_ms", c_double_p), ("hv_launches", c_int32_p)]
 
 
 class FtlmMlpWeights(ctypes.Structure):
@@ -85,6 +85,10 @@ def lib():
         L.ftlm_adam_step.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_int32, vp]
+        L.ftlm_describe_passes.argtypes = [ctypes.POINTER(FtlmSystem), ctypes.c_int32,
+                                           ctypes.c_int32, c_int32_p,
+                                           ctypes.POINTER(ctypes.c_uint32), c_int32_p, c_int32_p,
+                                           c_int32_p, c_int32_p, c_double_p]
         _lib = L
     return _lib
 

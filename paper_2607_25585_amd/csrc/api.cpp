@@ -159,23 +159,66 @@ static DevTables<R> resolve(const TableOffsets<R> &o, unsigned char *base) {
 
 }  // namespace
 
-// Packs every table of hh for both precisions and copies it to the device.
-// Reuses dh.block when its size matches (so captured graphs stay valid).
-int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
+// Pair order: inside the 11-bit tile | mixed (i inside, j outside), by j then i |
+// outside.  Every kernel that walks the pair list sees this order.
+void sort_pairs(const HostHam &hh, std::vector<int> &perm, int &n_ll, int &n_lh,
+                int mx_off[kMaxSites + 1]) {
   const int n = hh.n, np = hh.npair;
-  // spin-1/2 pair order: low-low | low-high | high-high (sites < 8 are "low")
-  std::vector<int> perm(np);
+  perm.resize(np);
   for (int p = 0; p < np; p++) perm[p] = p;
-  int n_ll = 0, n_lh = 0;
-  auto cls = [&](int p) { return (hh.pi[p] >= kLowBits) + (hh.pj[p] >= kLowBits); };
-  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return cls(a) < cls(b); });
+  auto cls = [&](int p) { return (hh.pi[p] >= kTileBits) + (hh.pj[p] >= kTileBits); };
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+    if (cls(a) != cls(b)) return cls(a) < cls(b);
+    if (cls(a) == 1 && hh.pj[a] != hh.pj[b]) return hh.pj[a] < hh.pj[b];
+    return false;
+  });
+  n_ll = n_lh = 0;
   for (int p = 0; p < np; p++) {
     n_ll += cls(p) == 0;
     n_lh += cls(p) == 1;
   }
+  int q = n_ll;
+  for (int a = 0; a < n; a++) {
+    mx_off[a] = q;
+    while (q < n_ll + n_lh && hh.pj[perm[q]] == a) q++;
+  }
+  for (int a = n; a <= kMaxSites; a++) mx_off[a] = q;
+}
+
+// Packs every table of hh for both precisions and copies it to the device.
+// Reuses dh.block when its size matches (so captured graphs stay valid).
+int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
+  // the pass plans are rebuilt below; keep their record allocations for reuse
+  void *rec64 = dh.plan64.rec_block, *rec32 = dh.plan32.rec_block;
+  const size_t rb64 = dh.plan64.rec_bytes, rb32 = dh.plan32.rec_bytes;
+  const int n = hh.n, np = hh.npair;
+  std::vector<int> perm;
+  int n_ll = 0, n_lh = 0;
+  int mx_off[kMaxSites + 1];
+  sort_pairs(hh, perm, n_ll, n_lh, mx_off);
+  std::vector<int> spi(np), spj(np);
+  for (int q = 0; q < np; q++) {
+    spi[q] = hh.pi[perm[q]];
+    spj[q] = hh.pj[perm[q]];
+  }
+  const size_t wb = window_bytes_setting();
+  int prc = plan_passes_sorted(hh, spi, spj, wb / 16, dh.plan64);
+  if (!prc) prc = plan_passes_sorted(hh, spi, spj, wb / 8, dh.plan32);
+  if (prc) {
+    err = "no windowed-pass plan fits the window size";
+    return prc;
+  }
+  dh.plan64.window_bytes = wb;
+  dh.plan32.window_bytes = wb;
+  dh.plan64.rec_block = rec64;
+  dh.plan64.rec_bytes = rb64;
+  dh.plan32.rec_block = rec32;
+  dh.plan32.rec_bytes = rb32;
   Blob b;
   TableOffsets<double> o64 = pack_tables<double>(hh, perm, b);
   TableOffsets<float> o32 = pack_tables<float>(hh, perm, b);
+  const size_t off_p64 = b.add(dh.plan64.pairs.data(), dh.plan64.pairs.size() * sizeof(int4));
+  const size_t off_p32 = b.add(dh.plan32.pairs.data(), dh.plan32.pairs.size() * sizeof(int4));
   const size_t bytes = (b.bytes.size() + 255) & ~size_t(255);
   if (dh.block && dh.block_bytes != bytes) {
     (void)hipFree(dh.block);
@@ -196,6 +239,8 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   unsigned char *base = reinterpret_cast<unsigned char *>(dh.block);
   dh.t64 = resolve<double>(o64, base);
   dh.t32 = resolve<float>(o32, base);
+  dh.plan64.d_pairs = reinterpret_cast<const int4 *>(base + off_p64);
+  dh.plan32.d_pairs = reinterpret_cast<const int4 *>(base + off_p32);
   HamGeom &g = dh.geom;
   std::memset(&g, 0, sizeof(g));
   g.n = n;
@@ -204,13 +249,25 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   g.spin_half = hh.spin_half && n >= kLowBits;
   g.n_ll = n_ll;
   g.n_lh = n_lh;
+  for (int a = 0; a <= kMaxSites; a++) g.mx_off[a] = mx_off[a];
+  g.single_mask = 0;
+  for (int k = 0; k < n; k++)
+    if (site_has_singles(hh, k)) g.single_mask |= 1u << k;
   g.dim = (uint32_t)hh.dim;
   for (int k = 0; k < n; k++) {
     g.radix[k] = hh.radix[k];
     g.stride[k] = hh.stride[k];
     g.s[k] = 0.5f * hh.two_s[k];
   }
-  return FTLM_OK;
+  return build_pass_records(dh, err);
+}
+
+size_t window_bytes_setting() {
+  const char *e = std::getenv("FTLM_WINDOW_KB");
+  long kb = e ? std::atol(e) : 64;
+  if (kb < 4) kb = 4;
+  if (kb > 128) kb = 128;
+  return (size_t)kb * 1024;
 }
 
 static void field_direction(const double B[3], double out[3]) {
@@ -273,6 +330,8 @@ void ftlm_hamiltonian_destroy(ftlm_hamiltonian *h) {
   if (!h) return;
   if (h->dev.block) (void)hipFree(h->dev.block);
   if (h->mom_dev.block) (void)hipFree(h->mom_dev.block);
+  free_pass_records(h->dev);
+  free_pass_records(h->mom_dev);
   delete h;
 }
 

@@ -18,6 +18,9 @@ constexpr int kMaxSites = FTLM_MAX_SITES;
 constexpr int kMaxRadix = FTLM_MAX_TWO_S + 1;  // 16
 constexpr int kLowBits = 8;                    // spin-1/2 tile: 256 rows, sites 0..7 vary
 constexpr int kBlock = 256;
+constexpr int kTileBits = 11;                  // spin-1/2 LDS tile: 2048 rows, sites 0..10 vary
+constexpr int kTileRows = 1 << kTileBits;
+constexpr int kRowsPerThread = kTileRows / kBlock;  // 8
 
 template <typename R>
 struct alignas(2 * sizeof(R)) Cx {
@@ -94,20 +97,61 @@ struct DevTables {
 
 struct HamGeom {
   int n, npair, has_z, spin_half;
-  int n_ll, n_lh;          // spin-1/2: pairs sorted low-low | low-high | high-high
+  int n_ll, n_lh;          // spin-1/2: pairs sorted inside | mixed | outside the 11-bit tile
+  int mx_off[kMaxSites + 1];  // mixed pairs with outer site a occupy [mx_off[a], mx_off[a+1])
+  uint32_t single_mask;       // bit k: site k has non-zero single-site flip elements
   uint32_t dim;
   int radix[kMaxSites];
   uint32_t stride[kMaxSites];
   float s[kMaxSites];
 };
 
+// One pass of the windowed H*v: the "active" sites span a window of rows that
+// fits in LDS (all other digits fixed); the pass applies the single flips of
+// sites sing[] and the pairs listed at pass_pairs[pp_off .. pp_off+npp), all of
+// whose sites are active.  Pass 0 also applies the diagonal; the last pass adds
+// the partial sums of the earlier passes and runs the epilogue.
+struct PassDesc {
+  int na, ni, first, last, pow2, nsing, npp, pp_off;
+  uint32_t wsize, nwin;
+  int act[kMaxSites];       // active position a -> site
+  int wrad[kMaxSites];      // radix of active position a
+  uint32_t wst[kMaxSites];  // stride of a inside the window
+  uint32_t gst[kMaxSites];  // stride of a in the full basis
+  int inact[kMaxSites];     // inactive sites (ascending)
+  int irad[kMaxSites];
+  uint32_t ist[kMaxSites];
+  int sing[kMaxSites];      // active positions whose single flips this pass applies
+};
+
+struct PassPlan {
+  std::vector<PassDesc> passes;
+  std::vector<int4> pairs;   // (pair index, active pos of i, active pos of j, 0)
+  const int4 *d_pairs = nullptr;  // device copy (inside the handle's table block)
+  size_t window_bytes = 0;
+  // Per-window records (uniform diagonal / z-field parts and window base index)
+  // and per-lane tables, computed on the device once per Hamiltonian and field.
+  std::vector<size_t> rec_off, base_off, lane_off;  // byte offsets into rec_block, per pass
+  void *rec_block = nullptr;
+  size_t rec_bytes = 0;
+};
+
 struct DevHam {
   HamGeom geom;
   DevTables<double> t64;
   DevTables<float> t32;
+  PassPlan plan64, plan32;  // windowed-pass plans for complex128 / complex64
   void *block = nullptr;  // device allocation holding every table
   size_t block_bytes = 0;
 };
+
+// pi/pj: pair sites in the device (sorted) order.
+bool site_has_singles(const HostHam &hh, int k);
+int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
+                       size_t window_rows, PassPlan &plan);
+size_t window_bytes_setting();
+void sort_pairs(const HostHam &hh, std::vector<int> &perm, int &n_ll, int &n_lh,
+                int mx_off[kMaxSites + 1]);
 
 }  // namespace ftlm
 
@@ -150,9 +194,14 @@ struct HvLaunch {
   const EpiLanczos *lz;  // nullptr = plain product
   int grid_cap;        // max blocks along x (0 = default)
   int kc;              // columns per lane (0 = auto)
+  int variant;         // 0 auto, 1 direct kernels, 2 windowed passes
 };
 
 int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s);
+// (Re)computes the per-window records of both pass plans (allocates rec_block on
+// first use).  Synchronous.
+int build_pass_records(DevHam &dh, std::string &err);
+void free_pass_records(DevHam &dh);
 int hv_grid_blocks(const DevHam &dh, const HvLaunch &L, int *gx, int *gy, int *kc);
 
 int launch_gaussian(uint64_t seed, uint32_t inst, uint32_t field, uint32_t r0, int K,

@@ -15,7 +15,9 @@
 // reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "ftlm_internal.hpp"
 
@@ -202,8 +204,9 @@ __global__ __launch_bounds__(kBlock) void hv_half(HamGeom g, DevTables<R> tb, Hv
   // low-bit part of the diagonal (identical for every tile)
   R dlow = 0;
   for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((t >> k) & 1)];
-  for (int p = 0; p < g.n_ll; p++) {
+  for (int p = 0; p < np; p++) {
     const int2 ij = tb.pij[p];
+    if (ij.y >= kLowBits) continue;
     const R mm = (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25);
     dlow = fma(tb.pzz[p], mm, dlow);
   }
@@ -269,6 +272,649 @@ __global__ __launch_bounds__(kBlock) void hv_half(HamGeom g, DevTables<R> tb, Hv
     hv_epilogue<R, KC>(P, row, c0, acc, own, red);
   }
   hv_finish<KC>(P, red);
+}
+
+// Spin-1/2 systems with N >= 11, one column per block: the block owns a tile of
+// 2048 rows (sites 0..10 vary, 8 rows per thread: lane bits 0..7, row slot q =
+// bits 8..10) staged in LDS.  Terms flipping only tile sites read LDS.  For
+// every outer site a the partner tile (tile with bit a flipped) is staged once
+// and serves the single flip of a and all mixed pairs (i < 11, a).  Pairs of two
+// outer sites read the partner tile straight from global memory (one use each).
+template <typename R>
+__global__ __launch_bounds__(kBlock, 2) void hv_tile(HamGeom g, DevTables<R> tb, HvParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int Q = kRowsPerThread;
+  const int n = g.n, np = g.npair, n_in = g.n_ll, n_out0 = g.n_ll + g.n_lh;
+  Cx<R> *own = reinterpret_cast<Cx<R> *>(smem);   // [2048]
+  Cx<R> *part = own + kTileRows;                  // [2048]
+  Cx<R> *s_pc = part + kTileRows;                 // [n_in][4]
+  Cx<R> *s_fmh = s_pc + 4 * n_in;                 // [n][2][Q]
+  Cx<R> *s_hf = s_fmh + 2 * Q * n;                // [n][2]
+  R *s_hd = reinterpret_cast<R *>(s_hf + 2 * n);  // [n][2]
+  R *s_dmh = s_hd + 2 * n;                        // [Q]
+  R *s_phi = s_dmh + Q;                           // [8][Q]
+  R *s_term = s_phi + 8 * Q;                      // [32][Q]
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.y;
+  const int K = P.K;
+  for (int i = t; i < 4 * n_in; i += kBlock) s_pc[i] = tb.pc_half[i];
+  for (int i = t; i < 2 * n; i += kBlock) {
+    s_hf[i] = tb.hflip[i];
+    s_hd[i] = tb.hdiag[(i >> 1) * 16 + (i & 1)];
+  }
+  __syncthreads();
+  R dlow = 0;
+  for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((t >> k) & 1)];
+  for (int p = 0; p < n_in; p++) {
+    const int2 ij = tb.pij[p];
+    if (ij.y >= kLowBits) continue;
+    dlow = fma(tb.pzz[p], (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25), dlow);
+  }
+  R mlane[kLowBits];
+#pragma unroll
+  for (int i = 0; i < kLowBits; i++) mlane[i] = ((t >> i) & 1) ? R(0.5) : R(-0.5);
+  const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v);
+  const uint32_t ntile = g.dim >> kTileBits;
+  double red[3][1] = {{0.0}, {0.0}, {0.0}};
+
+  for (uint32_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const uint32_t base = tile << kTileBits;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; q++) own[q * kBlock + t] = v[(size_t)(base + q * kBlock + t) * K + c0];
+    // per-tile uniform parts: rows of slot q have bits 8..10 = q and bits >= 11 = base
+    for (int e = t; e < 2 * Q * n; e += kBlock) {
+      const int k = e / (2 * Q), sel = (e / Q) & 1, q = e % Q;
+      const uint32_t rb = base | ((uint32_t)q << kLowBits);
+      R fr = 0, fi = 0;
+      for (int l = kLowBits; l < n; l++) {
+        if (l == k) continue;
+        const R ml = ((rb >> l) & 1) ? R(0.5) : R(-0.5);
+        const Cx<R> c = tb.cz_half[(k * n + l) * 2 + sel];
+        fr = fma(c.re, ml, fr);
+        fi = fma(c.im, ml, fi);
+      }
+      s_fmh[e] = Cx<R>{fr, fi};
+    }
+    if (t < 24 * Q) {
+      const int k = kLowBits + t / Q, q = t % Q;
+      if (k < n) {
+        const uint32_t rb = base | ((uint32_t)q << kLowBits);
+        const R mk = ((rb >> k) & 1) ? R(0.5) : R(-0.5);
+        R acc = s_hd[2 * k + ((rb >> k) & 1)];
+        for (int j = k + 1; j < n; j++) acc = fma(tb.zz[k * n + j] * mk, ((rb >> j) & 1) ? R(0.5) : R(-0.5), acc);
+        s_term[(k - kLowBits) * Q + q] = acc;
+      }
+    } else if (t < 24 * Q + 8 * Q) {
+      const int i = (t - 24 * Q) / Q, q = (t - 24 * Q) % Q;
+      const uint32_t rb = base | ((uint32_t)q << kLowBits);
+      R ph = 0;
+      for (int j = kLowBits; j < n; j++) ph = fma(tb.zz[i * n + j], ((rb >> j) & 1) ? R(0.5) : R(-0.5), ph);
+      s_phi[i * Q + q] = ph;
+    }
+    __syncthreads();
+    if (t < Q) {
+      R d = 0;
+      for (int k = kLowBits; k < n; k++) d += s_term[(k - kLowBits) * Q + t];
+      s_dmh[t] = d;
+    }
+    __syncthreads();
+
+    Cx<R> acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      R dg = dlow + s_dmh[q];
+#pragma unroll
+      for (int i = 0; i < kLowBits; i++) dg = fma(mlane[i], s_phi[i * Q + q], dg);
+      const Cx<R> x = own[q * kBlock + t];
+      acc[q] = Cx<R>{dg * x.re, dg * x.im};
+    }
+    // single flips of tile sites
+#pragma unroll 1
+    for (int k = 0; k < kTileBits; k++) {
+      if (!((g.single_mask >> k) & 1u)) continue;
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const int r = q * kBlock + t;
+        const int b = (r >> k) & 1;
+        const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + t], a3 = s_fmh[(k * 2 + b) * Q + q];
+        const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
+        const Cx<R> x = own[r ^ (1 << k)];
+        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+      }
+    }
+    // pairs inside the tile
+#pragma unroll 1
+    for (int p = 0; p < n_in; p++) {
+      const int2 ij = tb.pij[p];
+      const int mask = (1 << ij.x) | (1 << ij.y);
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const int r = q * kBlock + t;
+        const int type = (((r >> ij.x) & 1) << 1) | ((r >> ij.y) & 1);
+        const Cx<R> c = s_pc[4 * p + type];
+        const Cx<R> x = own[r ^ mask];
+        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+      }
+    }
+    // outer sites: stage the partner tile once, then its single flip and mixed pairs
+#pragma unroll 1
+    for (int a = kTileBits; a < n; a++) {
+      const bool single_a = (g.single_mask >> a) & 1u;
+      if (!single_a && g.mx_off[a + 1] == g.mx_off[a]) continue;  // uniform: no term needs this tile
+      __syncthreads();
+      const uint32_t pb = base ^ (1u << a);
+#pragma unroll
+      for (int q = 0; q < Q; q++) part[q * kBlock + t] = v[(size_t)(pb + q * kBlock + t) * K + c0];
+      __syncthreads();
+      const int ba = (base >> a) & 1;
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        if (!single_a) break;
+        const Cx<R> a1 = s_hf[2 * a + ba], a2 = tb.lowf[(a * 2 + ba) * 256 + t], a3 = s_fmh[(a * 2 + ba) * Q + q];
+        const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
+        const Cx<R> x = part[q * kBlock + t];
+        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+      }
+      const int p1 = g.mx_off[a + 1];
+#pragma unroll 1
+      for (int p = g.mx_off[a]; p < p1; p++) {
+        const int i = tb.pij[p].x;
+        const Cx<R> clo = tb.pc_half[4 * p + ba], chi = tb.pc_half[4 * p + 2 + ba];
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          const int r = q * kBlock + t;
+          const Cx<R> c = ((r >> i) & 1) ? chi : clo;
+          const Cx<R> x = part[r ^ (1 << i)];
+          acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+          acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+        }
+      }
+    }
+    // pairs of two outer sites: partner tile read once from global memory
+#pragma unroll 1
+    for (int p = n_out0; p < np; p++) {
+      const int2 ij = tb.pij[p];
+      const int type = (((base >> ij.x) & 1) << 1) | ((base >> ij.y) & 1);
+      const Cx<R> c = tb.pc_half[4 * p + type];
+      const uint32_t pb = base ^ (1u << ij.x) ^ (1u << ij.y);
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const Cx<R> x = v[(size_t)(pb + q * kBlock + t) * K + c0];
+        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      Acc<R, 1> a1;
+      a1.re[0] = acc[q].re;
+      a1.im[0] = acc[q].im;
+      // the epilogue reads the own value through a pointer with the column stride of v
+      hv_epilogue<R, 1>(P, base + q * kBlock + t, c0, a1, v + (size_t)(base + q * kBlock + t) * K + c0, red);
+    }
+  }
+  hv_finish<1>(P, red);
+}
+
+// Windowed pass (any spins, one column per block).  The block stages the
+// window of rows that share the digits of every inactive site, applies from LDS
+// the terms this pass owns, and accumulates into w.  Thread t owns window rows
+// t + 256 q (q < RPT); loops run term-outer / row-inner so that each term's
+// metadata is read once per window and the row updates issue back to back.
+// POW2: every active site is a spin 1/2 (window digits = bits of the row).
+// The window-uniform parts of the diagonal and of the s^{+-}s^z field, and the
+// window's base index, come from records built once per Hamiltonian and field.
+constexpr int kMaxPassSingles = 4;
+
+template <typename R, bool POW2, int RPT>
+struct PassRec {
+  // record layout in units of R
+  static constexpr int kDq = 0;                                  // POW2: [RPT]  general: [1]
+  static constexpr int kPhi = POW2 ? RPT : 1;                    // POW2: [8][RPT]  general: [8]
+  static constexpr int kFq = POW2 ? 9 * RPT : 9;                 // Cx [4][2][RPT] / Cx [4][2]
+  static constexpr int kLen = POW2 ? 9 * RPT + 16 * RPT : 9 + 16;
+  // lane table layout (POW2 only): Cx flane[4][2][256], then R dlane[256]
+  static constexpr int kLaneBytes = POW2 ? (int)(sizeof(Cx<R>) * kMaxPassSingles * 2 * 256 + sizeof(R) * 256) : 0;
+};
+
+// One block builds the record of window wid (and, for block 0 / wid 0, the lane
+// table).  s_min/s_idig/s_tmp: LDS scratch of >= 32, 32 and 32*RPT entries.
+template <typename R, bool POW2, int RPT>
+__global__ __launch_bounds__(kBlock) void pass_record_kernel(HamGeom g, DevTables<R> tb, PassDesc D,
+                                                             R *__restrict__ rec,
+                                                             uint32_t *__restrict__ base_out,
+                                                             unsigned char *__restrict__ lane) {
+  using L = PassRec<R, POW2, RPT>;
+  __shared__ R s_min[32];
+  __shared__ int s_idig[32];
+  __shared__ R s_tmp[32 * RPT];
+  const int t = threadIdx.x;
+  const int na = D.na, ni = D.ni, n = g.n;
+  if (POW2 && blockIdx.x == 0) {
+    // lane table: z-field of each single over active sites < 8, diagonal over sites < 8
+    Cx<R> *flane = reinterpret_cast<Cx<R> *>(lane);
+    R *dlane = reinterpret_cast<R *>(flane + kMaxPassSingles * 2 * 256);
+    for (int s2 = 0; s2 < kMaxPassSingles; s2++) {
+      Cx<R> f0{0, 0}, f1{0, 0};
+      if (s2 < D.nsing && g.has_z) {
+        const int a = D.sing[s2], k = D.act[a];
+        for (int a2 = 0; a2 < na && a2 < kLowBits; a2++) {
+          if (a2 == a) continue;
+          const R m2 = ((t >> a2) & 1) ? R(0.5) : R(-0.5);
+          const Cx<R> cm = tb.czm[k * n + D.act[a2]], cp = tb.czp[k * n + D.act[a2]];
+          f0.re = fma(cm.re, m2, f0.re);
+          f0.im = fma(cm.im, m2, f0.im);
+          f1.re = fma(cp.re, m2, f1.re);
+          f1.im = fma(cp.im, m2, f1.im);
+        }
+      }
+      flane[(s2 * 2 + 0) * 256 + t] = f0;
+      flane[(s2 * 2 + 1) * 256 + t] = f1;
+    }
+    R dl = 0;
+    if (D.first)
+      for (int a = 0; a < na && a < kLowBits; a++) {
+        dl += tb.hdiag[D.act[a] * 16 + ((t >> a) & 1)];
+        const R ma = ((t >> a) & 1) ? R(0.5) : R(-0.5);
+        for (int a2 = a + 1; a2 < na && a2 < kLowBits; a2++)
+          dl = fma(tb.zz[D.act[a] * n + D.act[a2]] * ma, ((t >> a2) & 1) ? R(0.5) : R(-0.5), dl);
+      }
+    dlane[t] = dl;
+  }
+  for (uint32_t wid = blockIdx.x; wid < D.nwin; wid += gridDim.x) {
+    R *out = rec + (size_t)wid * L::kLen;
+    __syncthreads();
+    if (t < ni) {
+      uint32_t rem = wid, dg = 0;
+      for (int i = 0; i <= t; i++) {
+        const uint32_t r = (uint32_t)D.irad[i], q = rem / r;
+        dg = rem - q * r;
+        rem = q;
+      }
+      s_idig[t] = (int)dg;
+      s_min[t] = tb.mval[D.inact[t] * 16 + dg];
+    }
+    if (t == 0) {
+      uint32_t rem = wid, b = 0;
+      for (int i = 0; i < ni; i++) {
+        const uint32_t r = (uint32_t)D.irad[i], q = rem / r;
+        b += (rem - q * r) * D.ist[i];
+        rem = q;
+      }
+      base_out[wid] = b;
+    }
+    __syncthreads();
+    Cx<R> *fq = reinterpret_cast<Cx<R> *>(out + L::kFq);
+    if (POW2) {
+      for (int e = t; e < kMaxPassSingles * 2 * RPT; e += kBlock) {
+        const int s2 = e / (2 * RPT), sel = (e / RPT) & 1, q = e % RPT;
+        R fr = 0, fi = 0;
+        if (s2 < D.nsing && g.has_z) {
+          const int a = D.sing[s2], k = D.act[a];
+          const Cx<R> *cz = sel ? tb.czp : tb.czm;
+          for (int i = 0; i < ni; i++) {
+            const Cx<R> c = cz[k * n + D.inact[i]];
+            fr = fma(c.re, s_min[i], fr);
+            fi = fma(c.im, s_min[i], fi);
+          }
+          for (int a2 = kLowBits; a2 < na; a2++) {
+            if (a2 == a) continue;
+            const R m2 = (((uint32_t)q >> (a2 - kLowBits)) & 1u) ? R(0.5) : R(-0.5);
+            const Cx<R> c = cz[k * n + D.act[a2]];
+            fr = fma(c.re, m2, fr);
+            fi = fma(c.im, m2, fi);
+          }
+        }
+        fq[e] = Cx<R>{fr, fi};
+      }
+      for (int e = t; e < 8 * RPT; e += kBlock) {
+        const int a = e / RPT, q = e % RPT;
+        R ph = 0;
+        if (D.first && a < na) {
+          const int k = D.act[a];
+          for (int i = 0; i < ni; i++) ph = fma(tb.zz[k * n + D.inact[i]], s_min[i], ph);
+          for (int a2 = kLowBits; a2 < na; a2++)
+            ph = fma(tb.zz[k * n + D.act[a2]], (((uint32_t)q >> (a2 - kLowBits)) & 1u) ? R(0.5) : R(-0.5), ph);
+        }
+        out[L::kPhi + e] = ph;
+      }
+      const int nq = na > kLowBits ? na - kLowBits : 0;
+      for (int e = t; e < 32 * RPT; e += kBlock) {
+        const int j = e / RPT, q = e % RPT;
+        R term = 0;
+        if (D.first && j < nq + ni) {
+          int k, dk;
+          R mk;
+          if (j < nq) {
+            k = D.act[kLowBits + j];
+            dk = (int)(((uint32_t)q >> j) & 1u);
+            mk = dk ? R(0.5) : R(-0.5);
+          } else {
+            k = D.inact[j - nq];
+            dk = s_idig[j - nq];
+            mk = s_min[j - nq];
+          }
+          term = tb.hdiag[k * 16 + dk];
+          for (int j2 = j + 1; j2 < nq + ni; j2++) {
+            int k2;
+            R m2;
+            if (j2 < nq) {
+              k2 = D.act[kLowBits + j2];
+              m2 = (((uint32_t)q >> j2) & 1u) ? R(0.5) : R(-0.5);
+            } else {
+              k2 = D.inact[j2 - nq];
+              m2 = s_min[j2 - nq];
+            }
+            term = fma(tb.zz[k * n + k2] * mk, m2, term);
+          }
+        }
+        s_tmp[e] = term;
+      }
+      __syncthreads();
+      for (int q = t; q < RPT; q += kBlock) {
+        R d = 0;
+        for (int j = 0; j < 32; j++) d += s_tmp[j * RPT + q];
+        out[L::kDq + q] = d;
+      }
+    } else {
+      for (int a = t; a < 8; a += kBlock) {
+        R ph = 0;
+        if (D.first && a < na) {
+          const int k = D.act[a];
+          for (int i = 0; i < ni; i++) ph = fma(tb.zz[k * n + D.inact[i]], s_min[i], ph);
+        }
+        out[L::kPhi + a] = ph;
+      }
+      for (int e = t; e < kMaxPassSingles * 2; e += kBlock) {
+        R fr = 0, fi = 0;
+        if ((e >> 1) < D.nsing && g.has_z) {
+          const int a = D.sing[e >> 1], k = D.act[a];
+          const Cx<R> *cz = (e & 1) ? tb.czp : tb.czm;
+          for (int i = 0; i < ni; i++) {
+            const Cx<R> c = cz[k * n + D.inact[i]];
+            fr = fma(c.re, s_min[i], fr);
+            fi = fma(c.im, s_min[i], fi);
+          }
+        }
+        fq[e] = Cx<R>{fr, fi};
+      }
+      for (int i = t; i < 32; i += kBlock) {
+        R term = 0;
+        if (D.first && i < ni) {
+          const int k = D.inact[i];
+          term = tb.hdiag[k * 16 + s_idig[i]];
+          for (int i2 = i + 1; i2 < ni; i2++) term = fma(tb.zz[k * n + D.inact[i2]] * s_min[i], s_min[i2], term);
+        }
+        s_tmp[i] = term;
+      }
+      __syncthreads();
+      if (t == 0) {
+        R d = 0;
+        for (int i = 0; i < 32; i++) d += s_tmp[i];
+        out[L::kDq] = d;
+      }
+    }
+  }
+}
+
+template <typename R, bool POW2, int RPT>
+__global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, PassDesc D,
+                                                  const int4 *__restrict__ pp,
+                                                  const R *__restrict__ rec,
+                                                  const uint32_t *__restrict__ bases,
+                                                  const unsigned char *__restrict__ lane, HvParams P) {
+  using L = PassRec<R, POW2, RPT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t ws = D.wsize;
+  const int na = D.na, n = g.n, npp = D.npp;
+  Cx<R> *win = reinterpret_cast<Cx<R> *>(smem);        // [ws]
+  Cx<R> *s_pc = win + ws;                              // [npp][4]
+  Cx<R> *s_hoff = s_pc + 4 * npp;                      // [4 singles][4 D][16]
+  R *s_rec = reinterpret_cast<R *>(s_hoff + kMaxPassSingles * 64);  // [kLen]
+  R *s_hd = s_rec + L::kLen;                           // [na][16]
+  R *s_gp = s_hd + 16 * na;                            // [na][16]
+  R *s_gm = s_gp + 16 * na;                            // [na][16]
+  R *s_m = s_gm + 16 * na;                             // [na][16]
+  int4 *s_pi = reinterpret_cast<int4 *>(s_m + 16 * na);  // [npp]
+  const int t = threadIdx.x;
+  const int K = P.K, c0 = blockIdx.y;
+
+  for (int i = t; i < 4 * npp; i += kBlock) {
+    const int p = pp[D.pp_off + i / 4].x;
+    s_pc[i] = POW2 ? tb.pc_half[4 * p + (i & 3)] : tb.pc[4 * p + (i & 3)];
+  }
+  for (int i = t; i < npp; i += kBlock) {
+    const int4 e = pp[D.pp_off + i];
+    s_pi[i] = POW2 ? make_int4(e.y, e.z, (int)(D.wst[e.y] | D.wst[e.z]), 0)
+                   : make_int4(e.y, e.z, (int)D.wst[e.y], (int)D.wst[e.z]);
+  }
+  for (int i = t; i < 16 * na; i += kBlock) {
+    const int k = D.act[i / 16];
+    s_hd[i] = tb.hdiag[k * 16 + (i & 15)];
+    s_gp[i] = tb.gp[k * 16 + (i & 15)];
+    s_gm[i] = tb.gm[k * 16 + (i & 15)];
+    s_m[i] = tb.mval[k * 16 + (i & 15)];
+  }
+  for (int i = t; i < D.nsing * 64; i += kBlock) {
+    const int k = D.act[D.sing[i / 64]];
+    s_hoff[i] = tb.hoff[k * 64 + (i & 63)];
+  }
+  // per-thread rows: packed active digits and offset within the full basis
+  uint32_t dig[RPT], gof[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; q++) {
+    const uint32_t r = (uint32_t)(t + kBlock * q);
+    uint32_t packed = 0, off = 0;
+    if (POW2) {
+      for (int a = 0; a < na; a++) off += ((r >> a) & 1u) * D.gst[a];
+      packed = r;
+    } else {
+      uint32_t rem = r;
+      for (int a = 0; a < na; a++) {
+        const uint32_t rr = (uint32_t)D.wrad[a], qq = rem / rr, d = rem - qq * rr;
+        off += d * D.gst[a];
+        packed |= d << (4 * a);
+        rem = qq;
+      }
+    }
+    dig[q] = packed;
+    gof[q] = off;
+  }
+  auto digit = [&](int q, int a) -> uint32_t {
+    return POW2 ? ((dig[q] >> a) & 1u) : ((dig[q] >> (4 * a)) & 15u);
+  };
+  Cx<R> flane[kMaxPassSingles][2];
+  R dlane = 0;
+  if (POW2) {
+    const Cx<R> *fl = reinterpret_cast<const Cx<R> *>(lane);
+#pragma unroll
+    for (int s2 = 0; s2 < kMaxPassSingles; s2++) {
+      flane[s2][0] = fl[(s2 * 2 + 0) * 256 + t];
+      flane[s2][1] = fl[(s2 * 2 + 1) * 256 + t];
+    }
+    dlane = reinterpret_cast<const R *>(fl + kMaxPassSingles * 2 * 256)[t];
+  }
+  R mlane[kLowBits];
+#pragma unroll
+  for (int a = 0; a < kLowBits; a++) mlane[a] = ((t >> a) & 1) ? R(0.5) : R(-0.5);
+
+  const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v);
+  Cx<R> *wout = reinterpret_cast<Cx<R> *>(P.w);
+  double red[3][1] = {{0.0}, {0.0}, {0.0}};
+
+  for (uint32_t wid = blockIdx.x; wid < D.nwin; wid += gridDim.x) {
+    const uint32_t base = bases[wid];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; q++) {
+      const uint32_t r = (uint32_t)(t + kBlock * q);
+      if (r < ws) win[r] = v[(size_t)(base + gof[q]) * K + c0];
+    }
+    for (int i = t; i < L::kLen; i += kBlock) s_rec[i] = rec[(size_t)wid * L::kLen + i];
+    __syncthreads();
+    const Cx<R> *s_fq = reinterpret_cast<const Cx<R> *>(s_rec + L::kFq);
+
+    Cx<R> acc[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; q++) acc[q] = Cx<R>{0, 0};
+    if (D.first) {
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+        const uint32_t r = (uint32_t)(t + kBlock * q);
+        if (r >= ws) continue;
+        R dg;
+        if (POW2) {
+          dg = dlane + s_rec[L::kDq + q];
+          for (int a = 0; a < na && a < kLowBits; a++) dg = fma(mlane[a], s_rec[L::kPhi + a * RPT + q], dg);
+        } else {
+          dg = s_rec[L::kDq];
+          for (int a = 0; a < na; a++) {
+            const uint32_t da = digit(q, a);
+            dg += s_hd[a * 16 + da];
+            R zs = s_rec[L::kPhi + a];
+            for (int a2 = a + 1; a2 < na; a2++) zs = fma(tb.zz[D.act[a] * n + D.act[a2]], s_m[a2 * 16 + digit(q, a2)], zs);
+            dg = fma(s_m[a * 16 + da], zs, dg);
+          }
+        }
+        const Cx<R> x = win[r];
+        acc[q] = Cx<R>{dg * x.re, dg * x.im};
+      }
+    }
+    // single flips
+    for (int s2 = 0; s2 < D.nsing; s2++) {
+      const int a = D.sing[s2], k = D.act[a];
+      const int rk = D.wrad[a];
+      const uint32_t st = D.wst[a];
+      Cx<R> fl0{0, 0}, fl1{0, 0};
+#pragma unroll
+      for (int s3 = 0; s3 < kMaxPassSingles; s3++)
+        if (s3 == s2) {
+          fl0 = flane[s3][0];
+          fl1 = flane[s3][1];
+        }
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+        const uint32_t r = (uint32_t)(t + kBlock * q);
+        if (r >= ws) continue;
+        const int d = (int)digit(q, a);
+        R fpr = 0, fpi = 0, fmr = 0, fmi = 0;
+        if (g.has_z) {
+          if (POW2) {
+            const Cx<R> u0 = s_fq[(s2 * 2 + 0) * RPT + q], u1 = s_fq[(s2 * 2 + 1) * RPT + q];
+            fmr = fl0.re + u0.re;
+            fmi = fl0.im + u0.im;
+            fpr = fl1.re + u1.re;
+            fpi = fl1.im + u1.im;
+          } else {
+            fmr = s_fq[s2 * 2].re;
+            fmi = s_fq[s2 * 2].im;
+            fpr = s_fq[s2 * 2 + 1].re;
+            fpi = s_fq[s2 * 2 + 1].im;
+            for (int a2 = 0; a2 < na; a2++) {
+              if (a2 == a) continue;
+              const R m2 = s_m[a2 * 16 + digit(q, a2)];
+              const Cx<R> cm = tb.czm[k * n + D.act[a2]], cp = tb.czp[k * n + D.act[a2]];
+              fmr = fma(cm.re, m2, fmr);
+              fmi = fma(cm.im, m2, fmi);
+              fpr = fma(cp.re, m2, fpr);
+              fpi = fma(cp.im, m2, fpi);
+            }
+          }
+        }
+#pragma unroll
+        for (int di = 0; di < 4; di++) {
+          const int Dl = (di < 2) ? di - 2 : di - 1;
+          const int nd = d + Dl;
+          if (nd < 0 || nd >= rk) continue;
+          Cx<R> c = s_hoff[(s2 * 4 + di) * 16 + d];
+          if (Dl == -1) {
+            const R gg = s_gp[a * 16 + d];
+            c.re = fma(gg, fpr, c.re);
+            c.im = fma(gg, fpi, c.im);
+          } else if (Dl == 1) {
+            const R gg = s_gm[a * 16 + d];
+            c.re = fma(gg, fmr, c.re);
+            c.im = fma(gg, fmi, c.im);
+          }
+          const Cx<R> x = win[r + (uint32_t)Dl * st];
+          acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+          acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+        }
+      }
+    }
+    // pair flips
+    if (POW2) {
+      for (int e = 0; e < npp; e++) {
+        const int4 pi = s_pi[e];
+        const Cx<R> *cp = s_pc + 4 * e;
+#pragma unroll
+        for (int q = 0; q < RPT; q++) {
+          const uint32_t r = (uint32_t)(t + kBlock * q);
+          if (r >= ws) continue;
+          const int type = (int)((((r >> pi.x) & 1u) << 1) | ((r >> pi.y) & 1u));
+          const Cx<R> c = cp[type];
+          const Cx<R> x = win[r ^ (uint32_t)pi.z];
+          acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+          acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+        }
+      }
+    } else {
+      for (int e = 0; e < npp; e++) {
+        const int4 pi = s_pi[e];
+        const int ri = D.wrad[pi.x], rj = D.wrad[pi.y];
+        Cx<R> cq[4];
+#pragma unroll
+        for (int ty = 0; ty < 4; ty++) cq[ty] = s_pc[4 * e + ty];
+#pragma unroll
+        for (int q = 0; q < RPT; q++) {
+          const uint32_t r = (uint32_t)(t + kBlock * q);
+          if (r >= ws) continue;
+          const int di = (int)digit(q, pi.x), dj = (int)digit(q, pi.y);
+          const R gpi = s_gp[pi.x * 16 + di], gmi = s_gm[pi.x * 16 + di];
+          const R gpj = s_gp[pi.y * 16 + dj], gmj = s_gm[pi.y * 16 + dj];
+#pragma unroll
+          for (int ty = 0; ty < 4; ty++) {
+            const bool im_ = (ty >> 1) != 0, jm = (ty & 1) != 0;
+            const bool vi = im_ ? (di <= ri - 2) : (di >= 1);
+            const bool vj = jm ? (dj <= rj - 2) : (dj >= 1);
+            if (!(vi && vj) || (cq[ty].re == R(0) && cq[ty].im == R(0))) continue;
+            const R f = (im_ ? gmi : gpi) * (jm ? gmj : gpj);
+            const uint32_t pr = r + (im_ ? (uint32_t)pi.z : (uint32_t)(-pi.z)) + (jm ? (uint32_t)pi.w : (uint32_t)(-pi.w));
+            const Cx<R> x = win[pr];
+            const R cr = cq[ty].re * f, ci = cq[ty].im * f;
+            acc[q].re = fma(cr, x.re, fma(-ci, x.im, acc[q].re));
+            acc[q].im = fma(cr, x.im, fma(ci, x.re, acc[q].im));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; q++) {
+      const uint32_t r = (uint32_t)(t + kBlock * q);
+      if (r >= ws) continue;
+      const uint32_t gi = base + gof[q];
+      Cx<R> *wp = wout + (size_t)gi * K + c0;
+      Cx<R> a = acc[q];
+      if (!D.first) {
+        const Cx<R> o = *wp;
+        a.re += o.re;
+        a.im += o.im;
+      }
+      if (!D.last) {
+        *wp = a;
+      } else {
+        Acc<R, 1> a1;
+        a1.re[0] = a.re;
+        a1.im[0] = a.im;
+        hv_epilogue<R, 1>(P, gi, c0, a1, &win[r], red);
+      }
+    }
+  }
+  if (D.last) hv_finish<1>(P, red);
 }
 
 // General mixed-radix systems (any 2 s_i <= 15, N <= 32).
@@ -387,6 +1033,151 @@ __global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, HvP
   hv_finish<KC>(P, red);
 }
 
+static bool use_tile(const HamGeom &g, int K) { return g.spin_half && g.n >= kTileBits && K == 1; }
+
+// Windowed passes pay off once the vector leaves the caches.
+static bool use_passes(const HamGeom &g, int K, int variant) {
+  if (variant == 1 || variant == 3) return false;
+  if (variant == 2) return K == 1;
+  return K == 1 && g.dim >= (1u << 20) && !use_tile(g, K);
+}
+
+template <typename R>
+static constexpr int pass_rpt() { return sizeof(R) == 8 ? 16 : 32; }
+
+static bool pass_pow2(const PassDesc &D) { return D.pow2 && D.na >= kLowBits && D.na - kLowBits <= 5; }
+
+template <typename R>
+static size_t pass_rec_len(const PassDesc &D) {
+  return pass_pow2(D) ? PassRec<R, true, pass_rpt<R>()>::kLen : PassRec<R, false, pass_rpt<R>()>::kLen;
+}
+
+template <typename R>
+static size_t pass_smem(const PassDesc &D) {
+  return sizeof(Cx<R>) * ((size_t)D.wsize + 4 * (size_t)D.npp + kMaxPassSingles * 64) +
+         sizeof(R) * (pass_rec_len<R>(D) + 64 * (size_t)D.na) + sizeof(int4) * (size_t)D.npp;
+}
+
+template <typename R, bool POW2>
+static void launch_pass_t(const DevHam &dh, const DevTables<R> &tb, const PassPlan &plan, size_t ps,
+                          const HvParams &P, dim3 grid, size_t sm, hipStream_t s) {
+  constexpr int RPT = pass_rpt<R>();
+  static size_t granted = 0;
+  if (sm > granted) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_pass<R, POW2, RPT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    granted = sm;
+  }
+  const unsigned char *blk = reinterpret_cast<const unsigned char *>(plan.rec_block);
+  hipLaunchKernelGGL((hv_pass<R, POW2, RPT>), grid, dim3(kBlock), sm, s, dh.geom, tb, plan.passes[ps],
+                     plan.d_pairs, reinterpret_cast<const R *>(blk + plan.rec_off[ps]),
+                     reinterpret_cast<const uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps], P);
+}
+
+template <typename R>
+static int launch_passes(const DevHam &dh, const DevTables<R> &tb, const PassPlan &plan,
+                         const HvParams &P, int gy, int cap, hipStream_t s) {
+  if (!plan.rec_block) return FTLM_EINVAL;
+  for (size_t ps = 0; ps < plan.passes.size(); ps++) {
+    const PassDesc &D = plan.passes[ps];
+    if (D.wsize > (uint32_t)(kBlock * pass_rpt<R>()) || D.nsing > kMaxPassSingles) return FTLM_ERANGE;
+    const size_t sm = pass_smem<R>(D);
+    if (sm > 160 * 1024) return FTLM_ERANGE;
+    const int gx = (int)(D.nwin < (uint32_t)cap ? D.nwin : (uint32_t)cap);
+    HvParams Pp = P;
+    if (!D.last) Pp.lanczos = 0;
+    if (pass_pow2(D)) launch_pass_t<R, true>(dh, tb, plan, ps, Pp, dim3(gx, gy), sm, s);
+    else launch_pass_t<R, false>(dh, tb, plan, ps, Pp, dim3(gx, gy), sm, s);
+  }
+  return FTLM_OK;
+}
+
+template <typename R>
+static int build_records_t(DevHam &dh, const DevTables<R> &tb, PassPlan &plan) {
+  constexpr int RPT = pass_rpt<R>();
+  unsigned char *blk = reinterpret_cast<unsigned char *>(plan.rec_block);
+  for (size_t ps = 0; ps < plan.passes.size(); ps++) {
+    const PassDesc &D = plan.passes[ps];
+    const uint32_t gx = D.nwin < 65536u ? D.nwin : 65536u;
+    if (pass_pow2(D))
+      hipLaunchKernelGGL((pass_record_kernel<R, true, RPT>), dim3(gx), dim3(kBlock), 0, 0, dh.geom, tb, D,
+                         reinterpret_cast<R *>(blk + plan.rec_off[ps]),
+                         reinterpret_cast<uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps]);
+    else
+      hipLaunchKernelGGL((pass_record_kernel<R, false, RPT>), dim3(gx), dim3(kBlock), 0, 0, dh.geom, tb, D,
+                         reinterpret_cast<R *>(blk + plan.rec_off[ps]),
+                         reinterpret_cast<uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps]);
+    if (hipGetLastError() != hipSuccess) return FTLM_EHIP;
+  }
+  return FTLM_OK;
+}
+
+template <typename R>
+static size_t layout_records(PassPlan &plan) {
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    const size_t o = (off + 255) & ~size_t(255);
+    off = o + n;
+    return o;
+  };
+  plan.rec_off.assign(plan.passes.size(), 0);
+  plan.base_off.assign(plan.passes.size(), 0);
+  plan.lane_off.assign(plan.passes.size(), 0);
+  for (size_t ps = 0; ps < plan.passes.size(); ps++) {
+    const PassDesc &D = plan.passes[ps];
+    plan.rec_off[ps] = take(sizeof(R) * pass_rec_len<R>(D) * (size_t)D.nwin);
+    plan.base_off[ps] = take(sizeof(uint32_t) * (size_t)D.nwin);
+    plan.lane_off[ps] = take(sizeof(Cx<R>) * kMaxPassSingles * 2 * 256 + sizeof(R) * 256);
+  }
+  return (off + 255) & ~size_t(255);
+}
+
+void free_pass_records(DevHam &dh) {
+  for (PassPlan *pl : {&dh.plan64, &dh.plan32}) {
+    if (pl->rec_block) (void)hipFree(pl->rec_block);
+    pl->rec_block = nullptr;
+    pl->rec_bytes = 0;
+  }
+}
+
+int build_pass_records(DevHam &dh, std::string &err) {
+  struct Item {
+    PassPlan *pl;
+    bool f32;
+  } items[2] = {{&dh.plan64, false}, {&dh.plan32, true}};
+  for (auto &it : items) {
+    const size_t bytes = it.f32 ? layout_records<float>(*it.pl) : layout_records<double>(*it.pl);
+    if (it.pl->rec_block && it.pl->rec_bytes != bytes) {
+      (void)hipFree(it.pl->rec_block);
+      it.pl->rec_block = nullptr;
+    }
+    if (!it.pl->rec_block) {
+      if (hipMalloc(&it.pl->rec_block, bytes) != hipSuccess) {
+        it.pl->rec_block = nullptr;
+        err = "hipMalloc of pass records failed";
+        return FTLM_ENOMEM;
+      }
+      it.pl->rec_bytes = bytes;
+    }
+    const int rc = it.f32 ? build_records_t<float>(dh, dh.t32, *it.pl) : build_records_t<double>(dh, dh.t64, *it.pl);
+    if (rc) {
+      err = "pass record kernel launch failed";
+      return rc;
+    }
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    err = "pass record kernels failed";
+    return FTLM_EHIP;
+  }
+  return FTLM_OK;
+}
+
+template <typename R>
+static size_t hv_tile_smem(const HamGeom &g) {
+  return sizeof(Cx<R>) * (2 * (size_t)kTileRows + 4 * (size_t)g.n_ll + 2 * kRowsPerThread * g.n + 2 * g.n) +
+         sizeof(R) * (2 * g.n + kRowsPerThread + 8 * kRowsPerThread + 32 * kRowsPerThread);
+}
+
 template <typename R>
 static size_t hv_smem(const HamGeom &g) {
   if (g.spin_half && g.n >= kLowBits)
@@ -407,6 +1198,10 @@ int hv_grid_blocks(const DevHam &dh, const HvLaunch &L, int *gx, int *gy, int *k
   int k = pick_kc(L.K, want);
   uint32_t ntile = (g.spin_half && g.n >= kLowBits) ? (g.dim >> kLowBits)
                                                      : (uint32_t)(((uint64_t)g.dim + kBlock - 1) / kBlock);
+  if (use_tile(g, L.K)) {
+    ntile = g.dim >> kTileBits;
+    k = 1;
+  }
   int cap = L.grid_cap > 0 ? L.grid_cap : 2048;
   if (L.lz) cap = cap < 2048 ? cap : 2048;  // partials buffer holds 2048 slots per column block
   *gx = (int)(ntile < (uint32_t)cap ? ntile : (uint32_t)cap);
@@ -429,6 +1224,17 @@ static void launch_hv_t(const DevHam &dh, const DevTables<R> &tb, const HvParams
 template <typename R>
 static void launch_hv_r(const DevHam &dh, const DevTables<R> &tb, const HvParams &P, dim3 grid,
                         int kc, hipStream_t s) {
+  if (use_tile(dh.geom, P.K)) {
+    const size_t sm = hv_tile_smem<R>(dh.geom);
+    static size_t granted = 0;  // per instantiation: largest dynamic LDS size requested so far
+    if (sm > granted) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_tile<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+      granted = sm;
+    }
+    hipLaunchKernelGGL((hv_tile<R>), grid, dim3(kBlock), sm, s, dh.geom, tb, P);
+    return;
+  }
   switch (kc) {
     case 8: launch_hv_t<R, 8>(dh, tb, P, grid, s); break;
     case 4: launch_hv_t<R, 4>(dh, tb, P, grid, s); break;
@@ -460,6 +1266,18 @@ int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s) {
     P.alpha_out = L.lz->alpha_out;
     P.yre_out = L.lz->yre_out;
     P.yim_out = L.lz->yim_out;
+  }
+  int variant = L.variant;
+  if (!variant) {
+    const char *e = std::getenv("FTLM_HV_VARIANT");
+    variant = e ? std::atoi(e) : 0;
+  }
+  if (use_passes(dh.geom, L.K, variant)) {
+    const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
+    int rc = (L.precision == FTLM_C64) ? launch_passes<float>(dh, dh.t32, dh.plan32, P, L.K, cap, s)
+                                       : launch_passes<double>(dh, dh.t64, dh.plan64, P, L.K, cap, s);
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
   }
   dim3 grid(gx, gy);
   if (L.precision == FTLM_C64) launch_hv_r<float>(dh, dh.t32, P, grid, kc, s);

@@ -64,7 +64,9 @@ void make_plan(const ftlm_hamiltonian *h, const ftlm_run_params *p, RunPlan &pl)
   pl.nF = p->fields ? p->n_fields : 1;
   pl.prec = p->precision;
   pl.es = p->precision == FTLM_C64 ? 8 : 16;
-  pl.K = p->columns > 0 ? p->columns : std::min(p->R, 16);
+  // columns = 0: one vector per wave once the vectors leave the caches (the tile
+  // and pass kernels stage one column), else up to 16 columns per gather
+  pl.K = p->columns > 0 ? p->columns : (h->host.dim >= (1ull << 20) ? 1 : std::min(p->R, 16));
   pl.K = std::min(pl.K, p->R);
   pl.dim = h->host.dim;
   Carve c;
@@ -105,7 +107,8 @@ T *at(void *ws, size_t off) {
 }
 
 // Issues the N_L Lanczos steps for a wave of K columns on stream s.
-int issue_lanczos(const ftlm_hamiltonian *h, const RunPlan &pl, void *ws, int K, hipStream_t s) {
+int issue_lanczos(const ftlm_hamiltonian *h, const RunPlan &pl, void *ws, int K, hipStream_t s,
+                  hipEvent_t *ev = nullptr) {
   for (int j = 0; j < pl.NL; j++) {
     EpiLanczos lz{};
     void *cur = at<char>(ws, pl.buf[j % 3]);
@@ -126,8 +129,10 @@ int issue_lanczos(const ftlm_hamiltonian *h, const RunPlan &pl, void *ws, int K,
     L.v = cur;
     L.w = w;
     L.lz = &lz;
+    if (ev && hipEventRecord(ev[2 * j], s) != hipSuccess) return FTLM_EHIP;
     int rc = launch_hv(h->dev, L, s);
     if (rc) return rc;
+    if (ev && hipEventRecord(ev[2 * j + 1], s) != hipSuccess) return FTLM_EHIP;
     UpdateArgs u{};
     u.precision = pl.prec;
     u.K = K;
@@ -194,12 +199,27 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
     set_error("copy of run inputs failed");
     return FTLM_EHIP;
   }
-  const bool use_graph = std::getenv("FTLM_NO_GRAPH") == nullptr;
+  const bool timing = out->hv_ms != nullptr;
+  const bool use_graph = std::getenv("FTLM_NO_GRAPH") == nullptr && !timing;
+  std::vector<hipEvent_t> events;
+  double hv_ms = 0.0;
+  int hv_launches = 0;
+  if (timing) {
+    events.resize(2 * (size_t)pl.NL, nullptr);
+    for (auto &e : events)
+      if (hipEventCreate(&e) != hipSuccess) {
+        set_error("hipEventCreate failed");
+        for (auto &x : events) if (x) (void)hipEventDestroy(x);
+        return FTLM_EHIP;
+      }
+  }
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   hipStream_t cap = nullptr;
   int exec_K = 0;
   auto cleanup = [&]() {
+    for (auto &x : events) if (x) (void)hipEventDestroy(x);
+    events.clear();
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
@@ -257,8 +277,18 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
         }
         if (hipGraphLaunch(exec, s) != hipSuccess) return fail(FTLM_EHIP, "graph launch failed");
       } else {
-        rc = issue_lanczos(h, pl, ws, K, s);
+        rc = issue_lanczos(h, pl, ws, K, s, timing ? events.data() : nullptr);
         if (rc) return fail(rc, "Lanczos launch failed");
+        if (timing) {
+          if (hipStreamSynchronize(s) != hipSuccess) return fail(FTLM_EHIP, "synchronise failed");
+          for (int j = 0; j < pl.NL; j++) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, events[2 * j], events[2 * j + 1]) != hipSuccess)
+              return fail(FTLM_EHIP, "event timing failed");
+            hv_ms += ms;
+            hv_launches++;
+          }
+        }
       }
       (void)exec_K;
       rc = launch_tridiag(K, pl.NL, at<int>(ws, pl.nused), 1, pl.K, at<double>(ws, pl.alpha),
@@ -306,6 +336,10 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
                      hipMemcpyDeviceToHost, s) != hipSuccess)
     return fail(FTLM_EHIP, "copy of n_used failed");
   if (hipStreamSynchronize(s) != hipSuccess) return fail(FTLM_EHIP, "stream synchronise failed");
+  if (timing) {
+    *out->hv_ms = hv_ms;
+    if (out->hv_launches) *out->hv_launches = hv_launches;
+  }
   cleanup();
   if (p->fields) {
     rc = ftlm_hamiltonian_set_field(h, saved_B);

@@ -73,3 +73,28 @@ def test_apply_and_run_reject_null(libftlm):
     assert libftlm.ftlm_apply(None, 0, 1, None, None, None) == -1
     assert libftlm.ftlm_run(None, None, None, 0, None, None) == -1
     assert libftlm.ftlm_gaussian_vectors(1, 0, 0, 0, 0, 10, None, None) == -1
+
+
+@pytest.mark.parametrize("wl", ["cfg1", "cfg2", "cfg2_hb", "cfg4", "cfg4_hb"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pass_plan_covers_every_pair_once(libftlm, wl, prec):
+    """Host logic of the windowed H*v: every interacting pair is applied by
+    exactly one pass, every window fits the LDS budget, and pass counts stay
+    bounded."""
+    import numpy as np
+    import ftlm_workloads as W
+    import paper_2607_25585_amd as F
+    sysm, _ = W.WORKLOADS[wl]()
+    d = F.describe_passes(sysm, prec)
+    n = sysm.n_sites
+    pairs = set()
+    for i in range(n):
+        for j in range(i + 1, n):
+            if (sysm.J is not None and sysm.J[i, j] != 0) or sysm.pos is not None:
+                pairs.add((i, j))
+    got = [tuple(sorted(p)) for p in d["pair_sites"].tolist()]
+    assert len(got) == len(set(got)) == len(pairs)
+    assert set(got) == pairs
+    es = 16 if prec == 0 else 8
+    assert np.all(d["window_rows"].astype(np.int64) * es <= 64 * 1024)
+    assert len(d["window_rows"]) <= 16

@@ -69,7 +69,8 @@ def test_hv_columns_c128(K):
         assert rel_max(w[:, c], oh.apply(v[:, c])) < 1e-12
 
 
-@pytest.mark.parametrize("n,K", [(8, 1), (9, 4), (11, 2), (13, 8), (10, 3)])
+@pytest.mark.parametrize("n,K", [(8, 1), (9, 4), (11, 2), (13, 8), (10, 3), (11, 1), (12, 1),
+                                 (15, 1)])
 def test_hv_spin_half_path(n, K):
     """Spin-1/2 tiles (N >= 8): dipolar pairs with s+- s^z pieces, tilted field."""
     rng = np.random.default_rng(n * 10 + K)
@@ -230,6 +231,19 @@ def test_run_spin_half_tiles_matches_oracle():
         assert curve_err(got[key][0], ref[key]) < 1e-8, key
 
 
+def test_run_tile_path_matches_oracle():
+    """One column per wave on a 13-site spin-1/2 system: the LDS-tile H*v kernel."""
+    rng = np.random.default_rng(18)
+    sysm = W.random_small_system(rng, 13, max_two_s=1)
+    sysm.two_s[:] = 1
+    T = W.t_grid(30)
+    for prec, tol in ((F().FTLM_C128, 1e-8), (F().FTLM_C64, 1e-3)):
+        ham, got = _run_pair(sysm, 2, 50, T, 6, columns=1, precision=prec)
+        ref = of.ftlm(sysm, 2, 50, T, seed=6)[0]
+        for key in ("lnZ", "E", "C", "M"):
+            assert curve_err(got[key][0], ref[key]) < tol, (prec, key)
+
+
 def test_run_fields_ragged_waves_and_r_init():
     rng = np.random.default_rng(12)
     sysm = W.random_small_system(rng, 4, max_two_s=2)
@@ -312,6 +326,8 @@ def _sampled_rows_check(sysm, K, prec, tol, n_rows=3000):
 def test_cfg2_full_size_sampled_rows():
     sysm, spec = W.cfg2()
     _sampled_rows_check(sysm, spec.R, F().FTLM_C128, 1e-12)
+    _sampled_rows_check(sysm, 1, F().FTLM_C128, 1e-12)
+    _sampled_rows_check(sysm, 1, F().FTLM_C64, 2e-5)
 
 
 def test_cfg4_full_size_sampled_rows():

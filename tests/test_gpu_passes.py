@@ -1,0 +1,79 @@
+"""GPU parity of the windowed-pass H*v (forced on small systems with tiny windows,
+so that many passes and ragged windows are exercised) against the CPU oracle."""
+import numpy as np
+import pytest
+
+import ftlm_workloads as W
+from oracle import ftlm as of
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _force_passes(monkeypatch):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    monkeypatch.setenv("FTLM_HV_VARIANT", "2")
+    monkeypatch.setenv("FTLM_WINDOW_KB", "4")
+
+
+def F():
+    import paper_2607_25585_amd as F
+    return F
+
+
+def rel_max(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("seed,n,max_two_s,half", [(0, 6, 3, False), (1, 5, 4, False),
+                                                   (2, 12, 1, True), (3, 10, 1, True),
+                                                   (4, 4, 5, False), (5, 9, 2, False)])
+def test_pass_hv_matches_oracle(seed, n, max_two_s, half):
+    rng = np.random.default_rng(900 + seed)
+    sysm = W.random_small_system(rng, n, max_two_s=max_two_s)
+    if half:
+        sysm.two_s[:] = 1
+    plan = F().describe_passes(sysm)
+    print("case passes seed", seed, "two_s", sysm.two_s.tolist(), "passes", len(plan["window_rows"]),
+          flush=True)
+    ham = F().Hamiltonian(sysm)
+    v = rng.standard_normal(ham.dim) + 1j * rng.standard_normal(ham.dim)
+    oh = of.Ham(sysm)
+    ref = oh.apply(v)
+    w = ham.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+    assert rel_max(w, ref) < 1e-12
+    w32 = ham.apply(torch.as_tensor(v, device="cuda", dtype=torch.complex64)).cpu().numpy()
+    ref32 = oh.apply(v.astype(np.complex64).astype(np.complex128))
+    assert rel_max(w32, ref32) < 2e-5
+
+
+def test_pass_run_matches_oracle():
+    rng = np.random.default_rng(77)
+    sysm = W.random_small_system(rng, 6, max_two_s=2)
+    T = W.t_grid(30)
+    ham = F().Hamiltonian(sysm)
+    got = F().run(ham, 3, 40, T, seed=4, columns=1)
+    ref = of.ftlm(sysm, 3, 40, T, seed=4)[0]
+    for key in ("lnZ", "E", "C", "M"):
+        r = np.asarray(ref[key])
+        err = np.max(np.abs(got[key][0] - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max()))
+        assert err < 1e-8, key
+
+
+@pytest.mark.parametrize("n", [14, 16])
+def test_pass_hv_full_windows_spin_half(n, monkeypatch):
+    """Default 64 KiB windows: 4096 (c128) / 8192 (c64) rows, so every thread
+    owns 16 / 32 rows and the row-slot bits 8..12 enter the uniform parts."""
+    monkeypatch.setenv("FTLM_WINDOW_KB", "64")
+    rng = np.random.default_rng(1000 + n)
+    sysm = W.random_small_system(rng, n, max_two_s=1)
+    sysm.two_s[:] = 1
+    ham = F().Hamiltonian(sysm)
+    v = rng.standard_normal(ham.dim) + 1j * rng.standard_normal(ham.dim)
+    oh = of.Ham(sysm)
+    w = ham.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+    assert rel_max(w, oh.apply(v)) < 1e-12
+    w32 = ham.apply(torch.as_tensor(v, device="cuda", dtype=torch.complex64)).cpu().numpy()
+    assert rel_max(w32, oh.apply(v.astype(np.complex64).astype(np.complex128))) < 2e-5
