@@ -224,7 +224,8 @@ def run(ham: Hamiltonian, R: int, n_lanczos: int, T, seed: int = 0, fields=None,
 
 
 def run_batched(hams, R: int, n_lanczos: int, T, fields_per_inst, seed: int = 0,
-                precision: int = FTLM_C64, workspace=None):
+                precision: int = FTLM_C64, workspace=None, columns: int = 0,
+                workspace_bytes: Optional[int] = None):
     """Batched FTLM over many instances and field directions (one persistent
     launch per Lanczos step).  fields_per_inst[k] is an [n_dirs, 3] array.
     Returns a list of result dicts like :func:`run`."""
@@ -233,16 +234,17 @@ def run_batched(hams, R: int, n_lanczos: int, T, fields_per_inst, seed: int = 0,
     ps = (_ffi.FtlmRunParams * n)()
     keep = []
     for k in range(n):
-        p, kp = _params(R, n_lanczos, T, seed, fields_per_inst[k], precision, R, None, k)
+        p, kp = _params(R, n_lanczos, T, seed, fields_per_inst[k], precision, columns, None, k)
         ps[k] = p
         keep.append(kp)
     hs = (ctypes.c_void_p * n)(*[h.handle for h in hams])
     nbytes = ctypes.c_size_t()
     check(_ffi.lib().ftlm_run_batched_workspace_size(hs, n, ps, ctypes.byref(nbytes)),
           "ftlm_run_batched_workspace_size")
+    need = int(nbytes.value) if workspace_bytes is None else int(workspace_bytes)
     ws = workspace
-    if ws is None or ws.numel() < nbytes.value:
-        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     outs = []
     resarr = (_ffi.FtlmResult * n)()
     for k in range(n):
@@ -255,7 +257,7 @@ def run_batched(hams, R: int, n_lanczos: int, T, fields_per_inst, seed: int = 0,
                                     _dptr(o["E_min"]), None, None, None, None)
         outs.append(o)
     check(_ffi.lib().ftlm_run_batched(hs, n, ps, ctypes.c_void_p(ws.data_ptr()),
-                                      ctypes.c_size_t(ws.numel()), _stream(), resarr),
+                                      ctypes.c_size_t(need), _stream(), resarr),
           "ftlm_run_batched")
     del keep
     return outs

@@ -1,0 +1,1000 @@
+// Batched FTLM (ftlm_run_batched): many Hamiltonian instances of uneven
+// dimension and their field directions run together.  A wave holds items =
+// (instance, field, group of K random vectors); every Lanczos step is ONE
+// persistent H*v launch over a work queue of (item, row chunk) units for all
+// items of the wave, followed by one persistent update launch; both are
+// replayed from a captured HIP graph.  Reductions are per item and fixed-order:
+// each unit writes its partial sums, and the last unit of an item to finish sums
+// the item's partials in unit order.
+//
+// Vectors of an item are column-interleaved [dim][K], so a gather of one partner
+// row reads K contiguous complex numbers and every coefficient serves K columns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ftlm_internal.hpp"
+
+namespace ftlm {
+
+constexpr uint32_t kUnitRows = 16384;  // rows per work unit (64 tiles of 256)
+
+template <typename R>
+struct BItem {
+  DevTables<R> tb;   // instance pair tables + this field's one-site tables
+  DevTables<R> tbo;  // moment operator (one-site tables only)
+  int n, npair, has_z, half;
+  uint32_t dim;
+  uint32_t unit0, nunit;  // work units [unit0, unit0 + nunit)
+  int col0;               // first column of the item in the wave's scalar arrays
+  uint32_t rng_inst, rng_field, rng_r0;
+  Cx<R> *x[3];            // rotating Lanczos buffers [dim][K]
+  Cx<R> *ov1;             // O v_1
+  int radix[kMaxSites];
+  uint32_t stride[kMaxSites];
+};
+
+struct BStep {
+  int K, step, n_lanczos, mode;  // mode 0: O v_1 (plain, scaled); 1: Lanczos H*v
+  uint32_t n_units;
+  uint64_t seed;
+  double *alpha, *beta, *yre, *yim;   // [K*n_items] slices for this step
+  double *sx_cur, *sx_prev, *beta_prev, *sx_next;
+  double *smax;
+  int *done, *nused;
+  double *part;                        // [n_units][3][K]
+  unsigned *counter;                   // [n_items]
+  const int *unit_item;                // [n_units]
+};
+
+template <typename R, int KC>
+struct BAcc {
+  R re[KC], im[KC];
+};
+
+template <typename R, int KC>
+__device__ __forceinline__ void bmac(BAcc<R, KC> &a, R cr, R ci, const Cx<R> *__restrict__ x) {
+  Cx<R> xv[KC];
+#pragma unroll
+  for (int q = 0; q < KC; q++) xv[q] = x[q];
+#pragma unroll
+  for (int q = 0; q < KC; q++) {
+    a.re[q] = fma(cr, xv[q].re, fma(-ci, xv[q].im, a.re[q]));
+    a.im[q] = fma(cr, xv[q].im, fma(ci, xv[q].re, a.im[q]));
+  }
+}
+
+// One row of H v (or O v) for KC columns.  ops selects the operator's tables.
+template <typename R, int KC>
+__device__ __forceinline__ void brow(const BItem<R> &it, bool moment, uint32_t row,
+                                     const Cx<R> *__restrict__ v, BAcc<R, KC> &acc) {
+  const DevTables<R> &tb = moment ? it.tbo : it.tb;
+  const int n = it.n;
+  const int npair = moment ? 0 : it.npair;
+  const bool has_z = !moment && it.has_z;
+#pragma unroll
+  for (int q = 0; q < KC; q++) acc.re[q] = acc.im[q] = R(0);
+  if (it.half) {
+    R diag = 0;
+    for (int k = 0; k < n; k++) diag += tb.hdiag[k * 16 + ((row >> k) & 1)];
+    for (int p = 0; p < npair; p++) {
+      const int2 ij = tb.pij[p];
+      diag = fma(tb.pzz[p], (((row >> ij.x) ^ (row >> ij.y)) & 1) ? R(-0.25) : R(0.25), diag);
+    }
+    {
+      const Cx<R> *x = v + (size_t)row * KC;
+#pragma unroll
+      for (int q = 0; q < KC; q++) {
+        acc.re[q] = diag * x[q].re;
+        acc.im[q] = diag * x[q].im;
+      }
+    }
+    for (int k = 0; k < n; k++) {
+      const int b = (row >> k) & 1;
+      Cx<R> c = tb.hflip[2 * k + b];
+      if (has_z) {
+        R f0r = 0, f0i = 0, f1r = 0, f1i = 0;
+        for (int l = 0; l < n; l++) {
+          if (l == k) continue;
+          const R ml = ((row >> l) & 1) ? R(0.5) : R(-0.5);
+          const Cx<R> cm = tb.czm[k * n + l], cp = tb.czp[k * n + l];
+          f0r = fma(cm.re, ml, f0r);
+          f0i = fma(cm.im, ml, f0i);
+          f1r = fma(cp.re, ml, f1r);
+          f1i = fma(cp.im, ml, f1i);
+        }
+        c.re += b ? f1r : f0r;
+        c.im += b ? f1i : f0i;
+      }
+      bmac<R, KC>(acc, c.re, c.im, v + (size_t)(row ^ (1u << k)) * KC);
+    }
+    for (int p = 0; p < npair; p++) {
+      const int2 ij = tb.pij[p];
+      const int type = (((row >> ij.x) & 1) << 1) | ((row >> ij.y) & 1);
+      const Cx<R> c = tb.pc_half[4 * p + type];
+      bmac<R, KC>(acc, c.re, c.im, v + (size_t)(row ^ ((1u << ij.x) | (1u << ij.y))) * KC);
+    }
+    return;
+  }
+  uint64_t dlo = 0, dhi = 0;
+  {
+    uint32_t rem = row;
+    for (int k = 0; k < n; k++) {
+      const uint32_t r = (uint32_t)it.radix[k], qq = rem / r;
+      const uint64_t dk = rem - qq * r;
+      rem = qq;
+      if (k < 16) dlo |= dk << (4 * k);
+      else dhi |= dk << (4 * (k - 16));
+    }
+  }
+  auto digit = [&](int k) -> int {
+    return (int)(((k < 16) ? (dlo >> (4 * k)) : (dhi >> (4 * (k - 16)))) & 15u);
+  };
+  R diag = 0;
+  for (int k = 0; k < n; k++) diag += tb.hdiag[k * 16 + digit(k)];
+  for (int p = 0; p < npair; p++) {
+    const int2 ij = tb.pij[p];
+    diag = fma(tb.pzz[p], tb.mval[ij.x * 16 + digit(ij.x)] * tb.mval[ij.y * 16 + digit(ij.y)], diag);
+  }
+  {
+    const Cx<R> *x = v + (size_t)row * KC;
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      acc.re[q] = diag * x[q].re;
+      acc.im[q] = diag * x[q].im;
+    }
+  }
+  for (int k = 0; k < n; k++) {
+    const int dk = digit(k), rk = it.radix[k];
+    const uint32_t st = it.stride[k];
+    R fpr = 0, fpi = 0, fmr = 0, fmi = 0;
+    if (has_z)
+      for (int l = 0; l < n; l++) {
+        if (l == k) continue;
+        const R ml = tb.mval[l * 16 + digit(l)];
+        const Cx<R> cp = tb.czp[k * n + l], cm = tb.czm[k * n + l];
+        fpr = fma(cp.re, ml, fpr);
+        fpi = fma(cp.im, ml, fpi);
+        fmr = fma(cm.re, ml, fmr);
+        fmi = fma(cm.im, ml, fmi);
+      }
+#pragma unroll
+    for (int di = 0; di < 4; di++) {
+      const int D = (di < 2) ? di - 2 : di - 1;
+      const int nd = dk + D;
+      if (nd < 0 || nd >= rk) continue;
+      Cx<R> c = tb.hoff[(k * 4 + di) * 16 + dk];
+      if (D == -1) {
+        const R gg = tb.gp[k * 16 + dk];
+        c.re = fma(gg, fpr, c.re);
+        c.im = fma(gg, fpi, c.im);
+      } else if (D == 1) {
+        const R gg = tb.gm[k * 16 + dk];
+        c.re = fma(gg, fmr, c.re);
+        c.im = fma(gg, fmi, c.im);
+      }
+      bmac<R, KC>(acc, c.re, c.im, v + (size_t)(row + (uint32_t)(D * (int)st)) * KC);
+    }
+  }
+  for (int p = 0; p < npair; p++) {
+    const int2 ij = tb.pij[p];
+    const int di = digit(ij.x), dj = digit(ij.y);
+    const int ri = it.radix[ij.x], rj = it.radix[ij.y];
+    const uint32_t si = it.stride[ij.x], sj = it.stride[ij.y];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const Cx<R> cq = tb.pc[4 * p + q];
+      if (cq.re == R(0) && cq.im == R(0)) continue;
+      const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;
+      const bool vi = im_ ? (di <= ri - 2) : (di >= 1);
+      const bool vj = jm ? (dj <= rj - 2) : (dj >= 1);
+      if (!(vi && vj)) continue;
+      const R f = (im_ ? tb.gm[ij.x * 16 + di] : tb.gp[ij.x * 16 + di]) *
+                  (jm ? tb.gm[ij.y * 16 + dj] : tb.gp[ij.y * 16 + dj]);
+      const uint32_t partner = row + (im_ ? si : (uint32_t)(-(int)si)) + (jm ? sj : (uint32_t)(-(int)sj));
+      bmac<R, KC>(acc, cq.re * f, cq.im * f, v + (size_t)partner * KC);
+    }
+  }
+}
+
+__device__ __forceinline__ double bwave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-reduces NV*KC values, writes them to part[u], and returns true on the
+// block that completes the last unit of its item (that block then reduces).
+template <int NV, int KC>
+__device__ __forceinline__ bool bunit_partials(const double (&val)[NV][KC], double *part, uint32_t u,
+                                               unsigned *counter, unsigned nunit) {
+  __shared__ double red[kBlock / 64][NV * KC];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NV; a++)
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      const double s = bwave_sum(val[a][q]);
+      if (lane == 0) red[wv][a * KC + q] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < NV * KC) {
+    double s = 0;
+    for (int w2 = 0; w2 < kBlock / 64; w2++) s += red[w2][threadIdx.x];
+    part[(size_t)u * NV * KC + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == nunit - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  const bool out = last;
+  __syncthreads();
+  return out;
+}
+
+// ------------------------------------------------------------------ kernels
+template <typename R, int KC>
+__global__ __launch_bounds__(kBlock) void bstart_kernel(const BItem<R> *__restrict__ items, BStep S) {
+  for (uint32_t u = blockIdx.x; u < S.n_units; u += gridDim.x) {
+    const int ii = S.unit_item[u];
+    const BItem<R> &it = items[ii];
+    const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
+    double red[1][KC];
+#pragma unroll
+    for (int q = 0; q < KC; q++) red[0][q] = 0.0;
+    Cx<R> *x = it.x[0];
+    for (uint32_t row = r0 + threadIdx.x; row < r1; row += kBlock) {
+#pragma unroll
+      for (int q = 0; q < KC; q++) {
+        uint32_t c[4] = {row, it.rng_r0 + (uint32_t)q, it.rng_field, it.rng_inst};
+        // Philox4x32-10 + Box-Muller, as in the plain start-vector kernel
+        uint32_t k0 = (uint32_t)S.seed, k1 = (uint32_t)(S.seed >> 32);
+#pragma unroll
+        for (int rr = 0; rr < 10; rr++) {
+          const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+          const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+          const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+          c[0] = n0;
+          c[1] = lo1;
+          c[2] = n2;
+          c[3] = lo0;
+          k0 += 0x9E3779B9u;
+          k1 += 0xBB67AE85u;
+        }
+        const uint64_t a = ((uint64_t)(c[0] >> 5) << 26) | (c[1] >> 6);
+        const uint64_t b = ((uint64_t)(c[2] >> 5) << 26) | (c[3] >> 6);
+        const double u1 = (double)(a + 1) * 0x1.0p-53, u2 = (double)b * 0x1.0p-53;
+        const double rad = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos(2.0 * M_PI * u2, &sn, &cs);
+        const Cx<R> z{(R)(rad * cs), (R)(rad * sn)};
+        x[(size_t)row * KC + q] = z;
+        red[0][q] += (double)z.re * (double)z.re + (double)z.im * (double)z.im;
+      }
+    }
+    if (bunit_partials<1, KC>(red, S.part, u, S.counter + ii, it.nunit)) {
+      for (int q = threadIdx.x; q < KC; q += kBlock) {
+        double s = 0;
+        for (uint32_t v2 = 0; v2 < it.nunit; v2++) s += S.part[(size_t)(it.unit0 + v2) * KC + q];
+        S.sx_cur[it.col0 + q] = s > 0 ? 1.0 / sqrt(s) : 0.0;
+      }
+      if (threadIdx.x == 0) S.counter[ii] = 0u;
+    }
+  }
+}
+
+template <typename R, int KC>
+__global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict__ items, BStep S) {
+  const int j = S.step;
+  for (uint32_t u = blockIdx.x; u < S.n_units; u += gridDim.x) {
+    const int ii = S.unit_item[u];
+    const BItem<R> &it = items[ii];
+    const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
+    const bool moment = S.mode == 0;
+    const Cx<R> *v = moment ? it.x[0] : it.x[j % 3];
+    Cx<R> *w = moment ? it.ov1 : it.x[(j + 1) % 3];
+    const Cx<R> *xp = (!moment && j > 0) ? it.x[(j + 2) % 3] : nullptr;
+    double sx[KC], bp[KC];
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      sx[q] = S.sx_cur[it.col0 + q];
+      bp[q] = xp ? S.beta_prev[it.col0 + q] * S.sx_prev[it.col0 + q] : 0.0;
+    }
+    double red[3][KC];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int q = 0; q < KC; q++) red[a][q] = 0.0;
+    for (uint32_t row = r0 + threadIdx.x; row < r1; row += kBlock) {
+      BAcc<R, KC> acc;
+      brow<R, KC>(it, moment, row, v, acc);
+      const size_t o = (size_t)row * KC;
+#pragma unroll
+      for (int q = 0; q < KC; q++) {
+        double wr = (double)acc.re[q] * sx[q], wi = (double)acc.im[q] * sx[q];
+        if (xp) {
+          const Cx<R> a = xp[o + q];
+          wr -= bp[q] * (double)a.re;
+          wi -= bp[q] * (double)a.im;
+        }
+        const Cx<R> out{(R)wr, (R)wi};
+        w[o + q] = out;
+        if (!moment) {
+          const Cx<R> xo = v[o + q];
+          const Cx<R> ov = it.ov1[o + q];
+          red[0][q] += (double)xo.re * (double)out.re + (double)xo.im * (double)out.im;
+          red[1][q] += (double)ov.re * (double)xo.re + (double)ov.im * (double)xo.im;
+          red[2][q] += (double)ov.re * (double)xo.im - (double)ov.im * (double)xo.re;
+        }
+      }
+    }
+    if (moment) continue;  // uniform over the launch
+    if (bunit_partials<3, KC>(red, S.part, u, S.counter + ii, it.nunit)) {
+      for (int idx = threadIdx.x; idx < 3 * KC; idx += kBlock) {
+        const int a = idx / KC, q = idx % KC;
+        double s = 0;
+        for (uint32_t v2 = 0; v2 < it.nunit; v2++) s += S.part[((size_t)(it.unit0 + v2) * 3 + a) * KC + q];
+        s *= sx[q];
+        if (a == 0) S.alpha[it.col0 + q] = s;
+        else if (a == 1) S.yre[it.col0 + q] = s;
+        else S.yim[it.col0 + q] = s;
+      }
+      if (threadIdx.x == 0) S.counter[ii] = 0u;
+    }
+  }
+}
+
+template <typename R, int KC>
+__global__ __launch_bounds__(kBlock) void bupdate_kernel(const BItem<R> *__restrict__ items, BStep S) {
+  const int j = S.step;
+  for (uint32_t u = blockIdx.x; u < S.n_units; u += gridDim.x) {
+    const int ii = S.unit_item[u];
+    const BItem<R> &it = items[ii];
+    const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
+    Cx<R> *w = it.x[(j + 1) % 3];
+    const Cx<R> *x = it.x[j % 3];
+    double coef[KC], red[1][KC];
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      coef[q] = S.alpha[it.col0 + q] * S.sx_cur[it.col0 + q];
+      red[0][q] = 0.0;
+    }
+    for (uint32_t row = r0 + threadIdx.x; row < r1; row += kBlock) {
+      const size_t o = (size_t)row * KC;
+#pragma unroll
+      for (int q = 0; q < KC; q++) {
+        const Cx<R> a = w[o + q], b = x[o + q];
+        const Cx<R> uu{(R)((double)a.re - coef[q] * (double)b.re), (R)((double)a.im - coef[q] * (double)b.im)};
+        w[o + q] = uu;
+        red[0][q] += (double)uu.re * (double)uu.re + (double)uu.im * (double)uu.im;
+      }
+    }
+    if (bunit_partials<1, KC>(red, S.part, u, S.counter + ii, it.nunit)) {
+      for (int q = threadIdx.x; q < KC; q += kBlock) {
+        const int c = it.col0 + q;
+        double s = 0;
+        for (uint32_t v2 = 0; v2 < it.nunit; v2++) s += S.part[(size_t)(it.unit0 + v2) * KC + q];
+        const double b = sqrt(s);
+        double sm = S.smax[c];
+        const double al = fabs(S.alpha[c]);
+        if (al > sm) sm = al;
+        if (S.done[c]) {
+          S.beta[c] = 0.0;
+          S.sx_next[c] = 0.0;
+        } else {
+          S.nused[c] = j + 1;
+          const bool breakdown = (j + 1 < S.n_lanczos) && !(b > 1e-12 * sm);
+          S.beta[c] = b;
+          if (breakdown) {
+            S.done[c] = 1;
+            S.sx_next[c] = 0.0;
+          } else {
+            S.sx_next[c] = b > 0 ? 1.0 / b : 0.0;
+          }
+          if (b > sm) sm = b;
+        }
+        S.smax[c] = sm;
+      }
+      if (threadIdx.x == 0) S.counter[ii] = 0u;
+    }
+  }
+}
+
+__global__ void bzero_kernel(double *smax, int *done, int *nused, unsigned *counter, int ncol, int nitems) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncol) {
+    smax[i] = 0.0;
+    done[i] = 0;
+    nused[i] = 0;
+  }
+  if (i < nitems) counter[i] = 0u;
+}
+
+// ------------------------------------------------------------------ host driver
+namespace {
+
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t n) {
+    const size_t o = (off + 255) & ~size_t(255);
+    off = o + n;
+    return o;
+  }
+};
+
+int pick_batch_k(int R, int requested) {
+  const int opts[5] = {16, 8, 4, 2, 1};
+  if (requested > 0) {
+    for (int o : opts)
+      if (o == requested && R % o == 0) return o;
+    return -1;
+  }
+  for (int o : opts)
+    if (R % o == 0) return o;
+  return 1;
+}
+
+template <typename R>
+size_t site_block_bytes(int maxn) {
+  return (((size_t)maxn * 16 * sizeof(R) + (size_t)maxn * 66 * sizeof(Cx<R>)) + 255) & ~size_t(255);
+}
+
+struct CurveInfo {
+  int inst, field;
+  double B[3];
+};
+
+struct PlanB {
+  int K, R, NL, nT, prec, n_inst;
+  size_t es;
+  std::vector<CurveInfo> curves;
+  std::vector<int> curve0;       // first curve of each instance
+  size_t fixed = 0;              // bytes of the fixed part
+  // fixed-part offsets
+  size_t site_tabs, eps, q1, qy, nused_all, T, dims, lnZ, E, C, M, emin, tri;
+  size_t site_bytes_per_curve = 0;
+  size_t max_vec_bytes = 0;      // largest single item
+  size_t all_vec_bytes = 0;      // every item at once
+};
+
+int validate_batched(const ftlm_hamiltonian *const *hs, int n_inst, const ftlm_run_params *pp,
+                     std::string &err) {
+  if (!hs || !pp || n_inst < 1) {
+    err = "hs, per_inst and n_inst >= 1 are required";
+    return FTLM_EINVAL;
+  }
+  for (int k = 0; k < n_inst; k++) {
+    if (!hs[k]) {
+      err = "NULL Hamiltonian";
+      return FTLM_EINVAL;
+    }
+    const ftlm_run_params &p = pp[k];
+    if (p.R < 1 || p.n_lanczos < 1 || p.n_lanczos > 1024 || p.n_T < 1 || !p.T) {
+      err = "bad R, n_lanczos or temperature grid";
+      return FTLM_EINVAL;
+    }
+    if (p.precision != FTLM_C128 && p.precision != FTLM_C64) {
+      err = "bad precision";
+      return FTLM_EINVAL;
+    }
+    if (p.r_init) {
+      err = "r_init is not supported by the batched run";
+      return FTLM_EINVAL;
+    }
+    if (p.fields && p.n_fields < 1) {
+      err = "n_fields must be >= 1";
+      return FTLM_EINVAL;
+    }
+    if (!p.fields && p.n_fields > 1) {
+      err = "n_fields > 1 needs a fields array";
+      return FTLM_EINVAL;
+    }
+    for (int i = 0; i < p.n_T; i++)
+      if (!(p.T[i] > 0)) {
+        err = "temperatures must be positive";
+        return FTLM_EINVAL;
+      }
+    if (p.R != pp[0].R || p.n_lanczos != pp[0].n_lanczos || p.n_T != pp[0].n_T ||
+        p.precision != pp[0].precision || p.columns != pp[0].columns) {
+      err = "R, n_lanczos, n_T, precision and columns must agree across instances";
+      return FTLM_EINVAL;
+    }
+    for (int i = 0; i < p.n_T; i++)
+      if (p.T[i] != pp[0].T[i]) {
+        err = "temperature grids must agree across instances";
+        return FTLM_EINVAL;
+      }
+  }
+  if (pick_batch_k(pp[0].R, pp[0].columns) < 0) {
+    err = "columns must be one of 1, 2, 4, 8, 16 and divide R";
+    return FTLM_EINVAL;
+  }
+  return FTLM_OK;
+}
+
+void make_plan_b(const ftlm_hamiltonian *const *hs, int n_inst, const ftlm_run_params *pp, PlanB &pl) {
+  pl.K = pick_batch_k(pp[0].R, pp[0].columns);
+  pl.R = pp[0].R;
+  pl.NL = pp[0].n_lanczos;
+  pl.nT = pp[0].n_T;
+  pl.prec = pp[0].precision;
+  pl.es = pl.prec == FTLM_C64 ? 8 : 16;
+  pl.n_inst = n_inst;
+  pl.curves.clear();
+  pl.curve0.assign(n_inst, 0);
+  int maxn = 1;
+  for (int k = 0; k < n_inst; k++) {
+    pl.curve0[k] = (int)pl.curves.size();
+    const int nf = pp[k].fields ? pp[k].n_fields : 1;
+    for (int f = 0; f < nf; f++) {
+      CurveInfo c;
+      c.inst = k;
+      c.field = f;
+      for (int a = 0; a < 3; a++) c.B[a] = pp[k].fields ? pp[k].fields[3 * f + a] : hs[k]->host.B[a];
+      pl.curves.push_back(c);
+    }
+    maxn = std::max(maxn, hs[k]->host.n);
+  }
+  // one-site tables per curve: for each precision hdiag [n][16] R, hoff [n][64] Cx,
+  // hflip [n][2] Cx -- for H and for O
+  pl.site_bytes_per_curve = 2 * site_block_bytes<double>(maxn) + 2 * site_block_bytes<float>(maxn);
+  const size_t ncurve = pl.curves.size(), ncol_all = ncurve * pl.R;
+  Carve c;
+  pl.site_tabs = c.take(pl.site_bytes_per_curve * ncurve);
+  pl.eps = c.take(sizeof(double) * pl.NL * ncol_all);
+  pl.q1 = c.take(sizeof(double) * pl.NL * ncol_all);
+  pl.qy = c.take(sizeof(double) * pl.NL * ncol_all);
+  pl.nused_all = c.take(sizeof(int) * ncol_all);
+  pl.T = c.take(sizeof(double) * pl.nT);
+  pl.dims = c.take(sizeof(double) * ncurve);
+  pl.lnZ = c.take(sizeof(double) * pl.nT * ncurve);
+  pl.E = c.take(sizeof(double) * pl.nT * ncurve);
+  pl.C = c.take(sizeof(double) * pl.nT * ncurve);
+  pl.M = c.take(sizeof(double) * pl.nT * ncurve);
+  pl.emin = c.take(sizeof(double) * ncurve);
+  pl.fixed = (c.off + 255) & ~size_t(255);
+  pl.max_vec_bytes = 0;
+  pl.all_vec_bytes = 0;
+  for (size_t ci = 0; ci < ncurve; ci++) {
+    const uint64_t dim = hs[pl.curves[ci].inst]->host.dim;
+    const size_t per_item = 4 * (size_t)dim * pl.K * pl.es + 4 * 256;
+    pl.max_vec_bytes = std::max(pl.max_vec_bytes, per_item);
+    pl.all_vec_bytes += per_item * (size_t)(pl.R / pl.K);
+  }
+}
+
+// per-wave dynamic part: item array, unit map, scalars, partials, counters, tridiag scratch
+size_t wave_meta_bytes(size_t n_items, size_t n_units, int K, int NL) {
+  const size_t ncol = n_items * (size_t)K;
+  Carve c;
+  c.take(sizeof(BItem<double>) * n_items);
+  c.take(sizeof(int) * n_units);
+  c.take(sizeof(double) * ncol * NL * 4);       // alpha, beta, yre, yim
+  c.take(sizeof(double) * ncol * (NL + 1));     // sx
+  c.take(sizeof(double) * ncol);                // smax
+  c.take(sizeof(int) * ncol * 2);               // done, nused
+  c.take(sizeof(double) * n_units * 3 * K);     // partials
+  c.take(sizeof(unsigned) * n_items);           // counters
+  c.take(sizeof(double) * 4 * NL * ncol);       // tridiagonal scratch
+  return (c.off + 255) & ~size_t(255);
+}
+
+template <typename R>
+void pack_site(const HostHam &hh, unsigned char *dst, int maxn, DevTables<R> &tb_rel) {
+  // layout: hdiag [maxn][16] R, hoff [maxn][64] Cx, hflip [maxn][2] Cx
+  R *hd = reinterpret_cast<R *>(dst);
+  Cx<R> *ho = reinterpret_cast<Cx<R> *>(hd + (size_t)maxn * 16);
+  Cx<R> *hf = ho + (size_t)maxn * 64;
+  std::memset(dst, 0, (size_t)maxn * 16 * sizeof(R) + (size_t)maxn * 66 * sizeof(Cx<R>));
+  for (int k = 0; k < hh.n; k++) {
+    const int r = hh.radix[k];
+    for (int d = 0; d < r; d++) {
+      hd[k * 16 + d] = (R)hh.h[(size_t)k * 256 + d * 16 + d].re;
+      const int Ds[4] = {-2, -1, 1, 2};
+      for (int di = 0; di < 4; di++) {
+        const int nd = d + Ds[di];
+        if (nd < 0 || nd >= r) continue;
+        const Cx<double> c = hh.h[(size_t)k * 256 + d * 16 + nd];
+        ho[(k * 4 + di) * 16 + d] = Cx<R>{(R)c.re, (R)c.im};
+      }
+    }
+    if (r == 2) {
+      const Cx<double> a = hh.h[(size_t)k * 256 + 1], c = hh.h[(size_t)k * 256 + 16];
+      hf[2 * k] = Cx<R>{(R)a.re, (R)a.im};
+      hf[2 * k + 1] = Cx<R>{(R)c.re, (R)c.im};
+    }
+  }
+  // offsets relative to dst, resolved against the device address later
+  tb_rel.hdiag = reinterpret_cast<const R *>((uintptr_t)0);
+  tb_rel.hoff = reinterpret_cast<const Cx<R> *>((uintptr_t)((unsigned char *)ho - dst));
+  tb_rel.hflip = reinterpret_cast<const Cx<R> *>((uintptr_t)((unsigned char *)hf - dst));
+}
+
+template <typename R, int KC>
+void launch_b(int kind, dim3 grid, const BItem<R> *items, const BStep &S, hipStream_t s) {
+  if (kind == 0) hipLaunchKernelGGL((bstart_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
+  else if (kind == 1) hipLaunchKernelGGL((bhv_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
+  else hipLaunchKernelGGL((bupdate_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
+}
+
+template <typename R>
+void launch_bk(int kind, int K, dim3 grid, const void *items, const BStep &S, hipStream_t s) {
+  const BItem<R> *it = reinterpret_cast<const BItem<R> *>(items);
+  switch (K) {
+    case 16: launch_b<R, 16>(kind, grid, it, S, s); break;
+    case 8: launch_b<R, 8>(kind, grid, it, S, s); break;
+    case 4: launch_b<R, 4>(kind, grid, it, S, s); break;
+    case 2: launch_b<R, 2>(kind, grid, it, S, s); break;
+    default: launch_b<R, 1>(kind, grid, it, S, s); break;
+  }
+}
+
+}  // namespace
+
+}  // namespace ftlm
+
+using namespace ftlm;
+
+extern "C" {
+
+int ftlm_run_batched_workspace_size(const ftlm_hamiltonian *const *hs, int32_t n_inst,
+                                    const ftlm_run_params *per_inst, size_t *bytes) {
+  std::string err;
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return FTLM_EINVAL;
+  }
+  int rc = validate_batched(hs, n_inst, per_inst, err);
+  if (rc) {
+    set_error(err);
+    return rc;
+  }
+  PlanB pl;
+  make_plan_b(hs, n_inst, per_inst, pl);
+  // all items at once if that is below 160 GiB, else a budget of 160 GiB of vectors
+  const size_t budget = (size_t)160 << 30;
+  size_t vec = std::min(pl.all_vec_bytes, std::max(budget, pl.max_vec_bytes));
+  size_t n_items = 0, n_units = 0;
+  for (const CurveInfo &c : pl.curves) {
+    n_items += pl.R / pl.K;
+    n_units += (size_t)(pl.R / pl.K) * ((hs[c.inst]->host.dim + kUnitRows - 1) / kUnitRows);
+  }
+  *bytes = pl.fixed + vec + wave_meta_bytes(n_items, n_units, pl.K, pl.NL);
+  return FTLM_OK;
+}
+
+int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ftlm_run_params *pp,
+                     void *ws, size_t bytes, void *stream_, ftlm_result *out) {
+  std::string err;
+  if (!ws || !out) {
+    set_error("NULL argument");
+    return FTLM_EINVAL;
+  }
+  int rc = validate_batched(hs, n_inst, pp, err);
+  if (rc) {
+    set_error(err);
+    return rc;
+  }
+  PlanB pl;
+  make_plan_b(hs, n_inst, pp, pl);
+  if (bytes < pl.fixed + pl.max_vec_bytes) {
+    set_error("workspace too small");
+    return FTLM_ENOMEM;
+  }
+  hipStream_t s = (hipStream_t)stream_;
+  unsigned char *base = reinterpret_cast<unsigned char *>(ws);
+  const int K = pl.K, NL = pl.NL, R = pl.R;
+  const size_t ncurve = pl.curves.size();
+  const bool f32 = pl.prec == FTLM_C64;
+  int maxn = 1;
+  for (int k = 0; k < n_inst; k++) maxn = std::max(maxn, hs[k]->host.n);
+
+  // one-site tables of H and O for every curve, both precisions
+  const size_t sb64 = site_block_bytes<double>(maxn), sb32 = site_block_bytes<float>(maxn);
+  std::vector<unsigned char> host_sites(pl.site_bytes_per_curve * ncurve, 0);
+  std::vector<double> dims(ncurve);
+  for (size_t ci = 0; ci < ncurve; ci++) {
+    const CurveInfo &c = pl.curves[ci];
+    HostHam hh = hs[c.inst]->host;
+    for (int a = 0; a < 3; a++) hh.B[a] = c.B[a];
+    compile_site_terms(hh);
+    HostHam ho;
+    {
+      double bh[3], beff[3];
+      const double nb = std::sqrt(c.B[0] * c.B[0] + c.B[1] * c.B[1] + c.B[2] * c.B[2]);
+      for (int a = 0; a < 3; a++) bh[a] = nb > 0 ? c.B[a] / nb : (a == 2 ? 1.0 : 0.0);
+      for (int a = 0; a < 3; a++) beff[a] = -bh[a] / kMuB;
+      ftlm_system so{};
+      so.n_sites = hh.n;
+      so.two_s = hh.two_s;
+      so.g = hh.g.data();
+      so.B = beff;
+      if (compile_hamiltonian(&so, ho, err)) {
+        set_error(err);
+        return FTLM_EINVAL;
+      }
+    }
+    unsigned char *dst = host_sites.data() + pl.site_bytes_per_curve * ci;
+    DevTables<double> d64;
+    DevTables<float> d32;
+    pack_site<double>(hh, dst, maxn, d64);
+    pack_site<double>(ho, dst + sb64, maxn, d64);
+    pack_site<float>(hh, dst + 2 * sb64, maxn, d32);
+    pack_site<float>(ho, dst + 2 * sb64 + sb32, maxn, d32);
+    dims[ci] = (double)hh.dim;
+  }
+  if (hipMemcpy(base + pl.site_tabs, host_sites.data(), host_sites.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(base + pl.T, pp[0].T, sizeof(double) * pl.nT, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(base + pl.dims, dims.data(), sizeof(double) * ncurve, hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("copy of batched inputs failed");
+    return FTLM_EHIP;
+  }
+  // device pointers of one curve's one-site tables (precision R, operator H or O)
+  auto site_ptrs = [&](size_t ci, bool single, bool moment, const void **hd, const void **ho, const void **hf) {
+    unsigned char *blk = base + pl.site_tabs + pl.site_bytes_per_curve * ci;
+    size_t off = single ? 2 * sb64 + (moment ? sb32 : 0) : (moment ? sb64 : 0);
+    const size_t rs = single ? 4 : 8;
+    *hd = blk + off;
+    *ho = blk + off + (size_t)maxn * 16 * rs;
+    *hf = blk + off + (size_t)maxn * 16 * rs + (size_t)maxn * 64 * 2 * rs;
+  };
+
+  // items in curve order: (curve, group)
+  struct Item {
+    size_t curve;
+    int group;
+  };
+  std::vector<Item> items;
+  for (size_t ci = 0; ci < ncurve; ci++)
+    for (int g = 0; g < R / K; g++) items.push_back({ci, g});
+  const size_t avail = bytes - pl.fixed;
+  const bool use_graph = std::getenv("FTLM_NO_GRAPH") == nullptr;
+  size_t next = 0;
+  while (next < items.size()) {
+    // greedy wave: as many items as fit with their metadata
+    size_t end = next, vec = 0, units = 0;
+    while (end < items.size()) {
+      const uint64_t dim = hs[pl.curves[items[end].curve].inst]->host.dim;
+      const size_t iv = 4 * (((size_t)dim * K * pl.es + 255) & ~size_t(255));
+      const size_t iu = (dim + kUnitRows - 1) / kUnitRows;
+      const size_t meta = wave_meta_bytes(end + 1 - next, units + iu, K, NL);
+      if (vec + iv + meta > avail && end > next) break;
+      vec += iv;
+      units += iu;
+      end++;
+    }
+    const size_t nit = end - next, ncol = nit * K;
+    Carve c;
+    const size_t o_items = c.take(sizeof(BItem<double>) * nit);
+    const size_t o_umap = c.take(sizeof(int) * units);
+    const size_t o_alpha = c.take(sizeof(double) * ncol * NL);
+    const size_t o_beta = c.take(sizeof(double) * ncol * NL);
+    const size_t o_yre = c.take(sizeof(double) * ncol * NL);
+    const size_t o_yim = c.take(sizeof(double) * ncol * NL);
+    const size_t o_sx = c.take(sizeof(double) * ncol * (NL + 1));
+    const size_t o_smax = c.take(sizeof(double) * ncol);
+    const size_t o_done = c.take(sizeof(int) * ncol);
+    const size_t o_nused = c.take(sizeof(int) * ncol);
+    const size_t o_part = c.take(sizeof(double) * units * 3 * K);
+    const size_t o_cnt = c.take(sizeof(unsigned) * nit);
+    const size_t o_tri = c.take(sizeof(double) * 4 * NL * ncol);
+    const size_t meta_end = (c.off + 255) & ~size_t(255);
+    unsigned char *wbase = base + pl.fixed;
+    unsigned char *vbase = wbase + meta_end;
+    // item descriptors
+    std::vector<unsigned char> hitems(sizeof(BItem<double>) * nit);
+    std::vector<int> umap(units);
+    size_t voff = 0;
+    uint32_t u0 = 0;
+    for (size_t i = 0; i < nit; i++) {
+      const Item &itm = items[next + i];
+      const CurveInfo &cv = pl.curves[itm.curve];
+      const ftlm_hamiltonian *h = hs[cv.inst];
+      const uint32_t dim = (uint32_t)h->host.dim;
+      const uint32_t nunit = (dim + kUnitRows - 1) / kUnitRows;
+      const size_t vb = ((size_t)dim * K * pl.es + 255) & ~size_t(255);
+      auto fill = [&](auto tag) {
+        using R = decltype(tag);
+        BItem<R> bi;
+        std::memset(&bi, 0, sizeof(bi));
+        const DevTables<R> &src = f32 ? *reinterpret_cast<const DevTables<R> *>(&h->dev.t32)
+                                      : *reinterpret_cast<const DevTables<R> *>(&h->dev.t64);
+        bi.tb = src;
+        bi.tbo = src;
+        const void *hd, *ho, *hf;
+        site_ptrs(itm.curve, f32, false, &hd, &ho, &hf);
+        bi.tb.hdiag = reinterpret_cast<const R *>(hd);
+        bi.tb.hoff = reinterpret_cast<const Cx<R> *>(ho);
+        bi.tb.hflip = reinterpret_cast<const Cx<R> *>(hf);
+        site_ptrs(itm.curve, f32, true, &hd, &ho, &hf);
+        bi.tbo.hdiag = reinterpret_cast<const R *>(hd);
+        bi.tbo.hoff = reinterpret_cast<const Cx<R> *>(ho);
+        bi.tbo.hflip = reinterpret_cast<const Cx<R> *>(hf);
+        bi.n = h->host.n;
+        bi.npair = h->host.npair;
+        bi.has_z = h->host.has_z;
+        bi.half = h->host.spin_half;
+        bi.dim = dim;
+        bi.unit0 = u0;
+        bi.nunit = nunit;
+        bi.col0 = (int)(i * K);
+        bi.rng_inst = pp[cv.inst].instance;
+        bi.rng_field = (uint32_t)cv.field;
+        bi.rng_r0 = (uint32_t)(itm.group * K);
+        for (int q = 0; q < 3; q++) bi.x[q] = reinterpret_cast<Cx<R> *>(vbase + voff + q * vb);
+        bi.ov1 = reinterpret_cast<Cx<R> *>(vbase + voff + 3 * vb);
+        for (int k = 0; k < h->host.n; k++) {
+          bi.radix[k] = h->host.radix[k];
+          bi.stride[k] = h->host.stride[k];
+        }
+        std::memcpy(hitems.data() + i * sizeof(BItem<double>), &bi, sizeof(bi));
+      };
+      if (f32) fill(float(0));
+      else fill(double(0));
+      for (uint32_t v2 = 0; v2 < nunit; v2++) umap[u0 + v2] = (int)i;
+      u0 += nunit;
+      voff += 4 * vb;
+    }
+    if (hipMemcpy(wbase + o_items, hitems.data(), hitems.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(wbase + o_umap, umap.data(), sizeof(int) * units, hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("copy of wave descriptors failed");
+      return FTLM_EHIP;
+    }
+    const uint32_t gx = (uint32_t)std::min<size_t>(units, 4096);
+    BStep S{};
+    S.K = K;
+    S.n_lanczos = NL;
+    S.n_units = (uint32_t)units;
+    S.seed = pp[0].seed;
+    S.part = reinterpret_cast<double *>(wbase + o_part);
+    S.counter = reinterpret_cast<unsigned *>(wbase + o_cnt);
+    S.unit_item = reinterpret_cast<const int *>(wbase + o_umap);
+    S.smax = reinterpret_cast<double *>(wbase + o_smax);
+    S.done = reinterpret_cast<int *>(wbase + o_done);
+    S.nused = reinterpret_cast<int *>(wbase + o_nused);
+    double *alpha = reinterpret_cast<double *>(wbase + o_alpha);
+    double *beta = reinterpret_cast<double *>(wbase + o_beta);
+    double *yre = reinterpret_cast<double *>(wbase + o_yre);
+    double *yim = reinterpret_cast<double *>(wbase + o_yim);
+    double *sx = reinterpret_cast<double *>(wbase + o_sx);
+    const void *ditems = wbase + o_items;
+    hipLaunchKernelGGL(bzero_kernel, dim3((std::max(ncol, nit) + 255) / 256), dim3(256), 0, s, S.smax, S.done,
+                       S.nused, S.counter, (int)ncol, (int)nit);
+    // start vectors (norms -> sx[0]) and O v_1
+    BStep S0 = S;
+    S0.sx_cur = sx;
+    S0.step = 0;
+    S0.mode = 0;
+    if (f32) {
+      launch_bk<float>(0, K, dim3(gx), ditems, S0, s);
+      launch_bk<float>(1, K, dim3(gx), ditems, S0, s);
+    } else {
+      launch_bk<double>(0, K, dim3(gx), ditems, S0, s);
+      launch_bk<double>(1, K, dim3(gx), ditems, S0, s);
+    }
+    if (hipGetLastError() != hipSuccess) {
+      set_error("batched start launch failed");
+      return FTLM_EHIP;
+    }
+    auto issue = [&](hipStream_t st) {
+      for (int j = 0; j < NL; j++) {
+        BStep Sj = S;
+        Sj.step = j;
+        Sj.mode = 1;
+        Sj.alpha = alpha + (size_t)j * ncol;
+        Sj.beta = beta + (size_t)j * ncol;
+        Sj.yre = yre + (size_t)j * ncol;
+        Sj.yim = yim + (size_t)j * ncol;
+        Sj.sx_cur = sx + (size_t)j * ncol;
+        Sj.sx_prev = j > 0 ? sx + (size_t)(j - 1) * ncol : nullptr;
+        Sj.beta_prev = j > 0 ? beta + (size_t)(j - 1) * ncol : nullptr;
+        Sj.sx_next = sx + (size_t)(j + 1) * ncol;
+        if (f32) {
+          launch_bk<float>(1, K, dim3(gx), ditems, Sj, st);
+          launch_bk<float>(2, K, dim3(gx), ditems, Sj, st);
+        } else {
+          launch_bk<double>(1, K, dim3(gx), ditems, Sj, st);
+          launch_bk<double>(2, K, dim3(gx), ditems, Sj, st);
+        }
+      }
+      return hipGetLastError() == hipSuccess;
+    };
+    if (use_graph) {
+      hipStream_t cap = nullptr;
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess &&
+                hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      bool issued = ok && issue(cap);
+      if (ok) ok = hipStreamEndCapture(cap, &graph) == hipSuccess && issued;
+      if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (ok) ok = hipGraphLaunch(exec, s) == hipSuccess;
+      if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (cap) (void)hipStreamDestroy(cap);
+      if (!ok) {
+        set_error("batched graph capture or launch failed");
+        return FTLM_EHIP;
+      }
+    } else if (!issue(s)) {
+      set_error("batched Lanczos launch failed");
+      return FTLM_EHIP;
+    }
+    // Krylov eigenpairs of every column of the wave, written at the columns'
+    // global positions (curve * R + group * K + c)
+    for (size_t i = 0; i < nit; i++) {
+      const Item &itm = items[next + i];
+      const int gcol = (int)(itm.curve * R + itm.group * K);
+      rc = launch_tridiag(K, NL, S.nused + i * K, 1, (int)ncol, alpha + i * K, beta + i * K, yre + i * K,
+                          reinterpret_cast<double *>(base + pl.eps), reinterpret_cast<double *>(base + pl.q1),
+                          reinterpret_cast<double *>(base + pl.qy), (int)(ncurve * R), gcol,
+                          reinterpret_cast<double *>(wbase + o_tri) + (size_t)i * 4 * NL * K, s);
+      if (rc) {
+        set_error("tridiagonal launch failed");
+        return rc;
+      }
+      if (hipMemcpyAsync(reinterpret_cast<int *>(base + pl.nused_all) + gcol, S.nused + i * K, sizeof(int) * K,
+                         hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        set_error("copy of n_used failed");
+        return FTLM_EHIP;
+      }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      set_error("batched wave failed");
+      return FTLM_EHIP;
+    }
+    next = end;
+  }
+  rc = launch_boltzmann((int)ncurve, R, NL, reinterpret_cast<int *>(base + pl.nused_all),
+                        reinterpret_cast<double *>(base + pl.eps), reinterpret_cast<double *>(base + pl.q1),
+                        reinterpret_cast<double *>(base + pl.qy), reinterpret_cast<double *>(base + pl.dims),
+                        reinterpret_cast<double *>(base + pl.T), pl.nT, reinterpret_cast<double *>(base + pl.lnZ),
+                        reinterpret_cast<double *>(base + pl.E), reinterpret_cast<double *>(base + pl.C),
+                        reinterpret_cast<double *>(base + pl.M), reinterpret_cast<double *>(base + pl.emin), s);
+  if (rc) {
+    set_error("Boltzmann launch failed");
+    return rc;
+  }
+  // results per instance
+  std::vector<double> hres(pl.nT * ncurve);
+  std::vector<int> hn(ncurve * R);
+  std::vector<double> hemin(ncurve);
+  struct { size_t off; int which; } outs[4] = {{pl.lnZ, 0}, {pl.E, 1}, {pl.C, 2}, {pl.M, 3}};
+  for (auto &o : outs) {
+    if (hipMemcpy(hres.data(), base + o.off, sizeof(double) * hres.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+      set_error("copy of results failed");
+      return FTLM_EHIP;
+    }
+    for (int k = 0; k < n_inst; k++) {
+      double *dst = o.which == 0 ? out[k].lnZ : o.which == 1 ? out[k].E : o.which == 2 ? out[k].C : out[k].M;
+      if (!dst) continue;
+      const int nf = pp[k].fields ? pp[k].n_fields : 1;
+      std::memcpy(dst, hres.data() + (size_t)pl.curve0[k] * pl.nT, sizeof(double) * nf * pl.nT);
+    }
+  }
+  if (hipMemcpy(hn.data(), base + pl.nused_all, sizeof(int) * hn.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(hemin.data(), base + pl.emin, sizeof(double) * ncurve, hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("copy of results failed");
+    return FTLM_EHIP;
+  }
+  for (int k = 0; k < n_inst; k++) {
+    const int nf = pp[k].fields ? pp[k].n_fields : 1;
+    if (out[k].n_lanczos_used)
+      std::memcpy(out[k].n_lanczos_used, hn.data() + (size_t)pl.curve0[k] * R, sizeof(int) * nf * R);
+    if (out[k].E_min) std::memcpy(out[k].E_min, hemin.data() + pl.curve0[k], sizeof(double) * nf);
+  }
+  return FTLM_OK;
+}
+
+}  // extern "C"

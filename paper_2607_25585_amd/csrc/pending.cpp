@@ -5,16 +5,6 @@ using namespace ftlm;
 
 extern "C" {
 
-int ftlm_run_batched_workspace_size(const ftlm_hamiltonian *const *, int32_t,
-                                    const ftlm_run_params *, size_t *) {
-  set_error("batched run not available in this build");
-  return FTLM_EINVAL;
-}
-int ftlm_run_batched(const ftlm_hamiltonian *const *, int32_t, const ftlm_run_params *, void *,
-                     size_t, void *, ftlm_result *) {
-  set_error("batched run not available in this build");
-  return FTLM_EINVAL;
-}
 int ftlm_mlp_workspace_size(int32_t, size_t *) { set_error("not available"); return FTLM_EINVAL; }
 int ftlm_mlp_forward(const ftlm_mlp_weights *, int32_t, const float *, float *, void *, size_t,
                      void *) { set_error("not available"); return FTLM_EINVAL; }

@@ -1,0 +1,98 @@
+"""GPU parity of the batched persistent FTLM (many instances of uneven dimension,
+several field directions each) against the plain GPU run and the CPU oracle,
+with the same seeded random vectors."""
+import numpy as np
+import pytest
+
+import ftlm_workloads as W
+from oracle import ftlm as of
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def F():
+    import paper_2607_25585_amd as F
+    return F
+
+
+def curve_err(x, ref):
+    ref = np.asarray(ref)
+    floor = 1e-3 * np.max(np.abs(ref))
+    return float(np.max(np.abs(np.asarray(x) - ref) / np.maximum(np.abs(ref), max(floor, 1e-300))))
+
+
+def _instances():
+    rng = np.random.default_rng(321)
+    systems = []
+    for n, half in ((6, True), (9, True), (4, False), (7, True)):
+        s = W.random_small_system(rng, n, max_two_s=1 if half else 3)
+        if half:
+            s.two_s[:] = 1
+        systems.append(s)
+    fields = [W.unit_vectors(rng, 2) * 0.8 for _ in systems]
+    return systems, fields
+
+
+@pytest.mark.parametrize("prec,tol,K", [(0, 1e-8, 4), (1, 1e-3, 2)])
+def test_batched_matches_oracle(prec, tol, K):
+    systems, fields = _instances()
+    T = W.t_grid(30)
+    R, NL, seed = 4, 40, 17
+    hams = [F().Hamiltonian(s) for s in systems]
+    got = F().run_batched(hams, R, NL, T, fields, seed=seed, precision=prec, columns=K)
+    for k, s in enumerate(systems):
+        ref = of.ftlm(s, R, NL, T, seed=seed, fields=fields[k], instance=k)
+        for f in range(len(fields[k])):
+            for key in ("lnZ", "E", "C", "M"):
+                assert curve_err(got[k][key][f], ref[f][key]) < tol, (k, f, key)
+            if prec == 0:
+                assert np.array_equal(got[k]["n_lanczos_used"][f], ref[f]["n_lanczos_used"])
+
+
+def test_batched_waves_give_identical_results():
+    """A workspace that holds one item at a time splits the run into many waves;
+    every reduction is fixed-order, so the curves are bitwise identical."""
+    systems, fields = _instances()
+    T = W.t_grid(20)
+    hams = [F().Hamiltonian(s) for s in systems]
+    a = F().run_batched(hams, 4, 30, T, fields, seed=3, precision=0, columns=2)
+    import ctypes
+    from paper_2607_25585_amd import _ffi
+    ps = (_ffi.FtlmRunParams * len(hams))()
+    keep = []
+    for k in range(len(hams)):
+        p, kp = F()._params(4, 30, T, 3, fields[k], 0, 2, None, k)
+        ps[k] = p
+        keep.append(kp)
+    hs = (ctypes.c_void_p * len(hams))(*[h.handle for h in hams])
+    nb = ctypes.c_size_t()
+    _ffi.check(_ffi.lib().ftlm_run_batched_workspace_size(hs, len(hams), ps, ctypes.byref(nb)))
+    # room for about two items of vectors per wave
+    items = []
+    for k, h in enumerate(hams):
+        for _f in range(len(fields[k])):
+            for _g in range(4 // 2):
+                items.append(4 * (((h.dim * 2 * 16) + 255) // 256 * 256))
+    small = int(nb.value) - sum(items) + 2 * max(items)
+    b = F().run_batched(hams, 4, 30, T, fields, seed=3, precision=0, columns=2, workspace_bytes=small)
+    for k in range(len(hams)):
+        for key in ("lnZ", "E", "C", "M"):
+            assert np.array_equal(a[k][key], b[k][key]), (k, key)
+
+
+def test_batched_matches_plain_run():
+    systems, fields = _instances()
+    T = W.t_grid(25)
+    hams = [F().Hamiltonian(s) for s in systems]
+    bat = F().run_batched(hams, 4, 35, T, fields, seed=9, precision=0, columns=4)
+    for k, h in enumerate(hams):
+        pl = F().run(h, 4, 35, T, seed=9, fields=fields[k], instance=k)
+        for key in ("lnZ", "E", "C", "M"):
+            assert np.max(np.abs(bat[k][key] - pl[key])) <= 1e-9 * np.max(np.abs(pl[key])) + 1e-12, (k, key)
