@@ -1,0 +1,269 @@
+"""Learned surrogate of FTLM thermodynamics for fast parameter scans and powder
+averages.
+
+An MLP 7 -> 256 -> 256 -> 256 -> 3 (SiLU) maps
+(J, d, anisotropy tilt, |B|, theta_B, phi_B, log10 T) of the 8-site s = 3/2 ring
+to (ln Z, M, C).  Weights are BF16 with FP32 master copies; forward, backward and
+Adam run in the library's HIP kernels (ftlm_mlp_forward / _backward,
+ftlm_adam_step); PyTorch only owns device memory and streams.  Training data
+are FTLM curves from the batched GPU path.  A gate (parameter domain and the
+disagreement of an ensemble of two networks) decides when to fall back to full
+FTLM, which also judges the surrogate's error.
+
+Encodings (readings, not from the paper):
+  inputs  -- J/3, d/5, 2 tilt/(pi/2) - 1, |B|/3.5 - 1, 2 theta/pi - 1,
+             phi/pi - 1, (log10 T + 1)/1.5 - 1
+  targets -- T (ln Z - ln dim)/20, M/10, C/5
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+from typing import Optional
+
+import numpy as np
+
+from . import _ffi
+from ._ffi import check
+
+LAYERS = (7, 256, 256, 256, 3)
+DIM_CFG5 = 4 ** 8
+PARAM_LO = np.array([-3.0, -5.0, 0.0, 0.0, 0.0, 0.0])
+PARAM_HI = np.array([3.0, 5.0, 0.5 * math.pi, 7.0, math.pi, 2 * math.pi])
+T_LO, T_HI = 0.1, 100.0
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def encode_inputs(params: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """params [P, 6] (J, d, tilt, |B|, theta, phi) x temperatures [nT] -> [P*nT, 7]."""
+    params = np.asarray(params, np.float64).reshape(-1, 6)
+    T = np.asarray(T, np.float64)
+    P, nT = len(params), len(T)
+    x = np.empty((P, nT, 7))
+    x[..., 0] = (params[:, 0] / 3.0)[:, None]
+    x[..., 1] = (params[:, 1] / 5.0)[:, None]
+    x[..., 2] = (2 * params[:, 2] / (0.5 * math.pi) - 1)[:, None]
+    x[..., 3] = (params[:, 3] / 3.5 - 1)[:, None]
+    x[..., 4] = (2 * params[:, 4] / math.pi - 1)[:, None]
+    x[..., 5] = (params[:, 5] / math.pi - 1)[:, None]
+    x[..., 6] = ((np.log10(T) + 1) / 1.5 - 1)[None, :]
+    return x.reshape(-1, 7)
+
+
+def encode_targets(lnZ, M, C, T, dim=DIM_CFG5) -> np.ndarray:
+    T = np.asarray(T, np.float64)[None, :]
+    y = np.stack([T * (np.asarray(lnZ) - math.log(dim)) / 20.0, np.asarray(M) / 10.0,
+                  np.asarray(C) / 5.0], axis=-1)
+    return y.reshape(-1, 3)
+
+
+def decode_outputs(y: np.ndarray, T: np.ndarray, dim=DIM_CFG5):
+    T = np.asarray(T, np.float64)
+    y = np.asarray(y, np.float64).reshape(-1, len(T), 3)
+    lnZ = math.log(dim) + 20.0 * y[..., 0] / T[None, :]
+    return lnZ, 10.0 * y[..., 1], 5.0 * y[..., 2]
+
+
+class MLP:
+    """BF16/FP32 MLP whose math runs in the library kernels."""
+
+    def __init__(self, seed: int = 0, device: str = "cuda"):
+        torch = _torch()
+        rng = np.random.default_rng(seed)
+        self.sizes_w = [fi * fo for fi, fo in zip(LAYERS[:-1], LAYERS[1:])]
+        self.sizes_b = list(LAYERS[1:])
+        self.nw, self.nb = sum(self.sizes_w), sum(self.sizes_b)
+        host = np.zeros(self.nw + self.nb, np.float32)
+        off = 0
+        for fi, fo in zip(LAYERS[:-1], LAYERS[1:]):
+            host[off:off + fi * fo] = (rng.standard_normal(fi * fo) * math.sqrt(2.0 / fi)).astype(np.float32)
+            off += fi * fo
+        self.p = torch.as_tensor(host, device=device)          # FP32 master [W | b]
+        self.g = torch.zeros_like(self.p)                      # gradients, same layout
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.pb = self.p[: self.nw].to(torch.bfloat16)         # BF16 weights used by the kernels
+        self.step = 0
+        self._ws = None
+        self._ws_batch = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def _views(self, base, sizes, start):
+        out, off = [], start
+        for n in sizes:
+            out.append(base.data_ptr() + off * base.element_size())
+            off += n
+        return out
+
+    def _weights(self):
+        w = _ffi.FtlmMlpWeights()
+        wp = self._views(self.pb, self.sizes_w, 0)
+        bp = self._views(self.p, self.sizes_b, self.nw)
+        for k in range(4):
+            w.W[k] = wp[k]
+            w.b[k] = bp[k]
+        return w
+
+    def _workspace(self, B):
+        torch = _torch()
+        if self._ws is None or self._ws_batch < B:
+            nb = ctypes.c_size_t()
+            check(_ffi.lib().ftlm_mlp_workspace_size(B, ctypes.byref(nb)), "ftlm_mlp_workspace_size")
+            self._ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.p.device)
+            self._ws_batch = B
+        return self._ws
+
+    def forward(self, x):
+        """x: [B, 7] float32 device tensor -> y [B, 3]."""
+        torch = _torch()
+        B = int(x.shape[0])
+        x = x.contiguous().to(torch.float32)
+        y = torch.empty((B, 3), dtype=torch.float32, device=x.device)
+        ws = self._workspace(B)
+        w = self._weights()
+        check(_ffi.lib().ftlm_mlp_forward(ctypes.byref(w), B, _vp(x), _vp(y), _vp(ws),
+                                          ctypes.c_size_t(ws.numel()), _stream()), "ftlm_mlp_forward")
+        return y
+
+    def gradients(self, x, t):
+        """Forward + backward on one batch; fills self.g and returns the loss (device)."""
+        B = int(x.shape[0])
+        self.forward(x)
+        ws = self._workspace(B)
+        w = self._weights()
+        vp4 = ctypes.c_void_p * 4
+        dW = vp4(*self._views(self.g, self.sizes_w, 0))
+        db = vp4(*self._views(self.g, self.sizes_b, self.nw))
+        check(_ffi.lib().ftlm_mlp_backward(ctypes.byref(w), B, _vp(t.contiguous()), _vp(self.loss), dW, db,
+                                           _vp(ws), ctypes.c_size_t(ws.numel()), _stream()),
+              "ftlm_mlp_backward")
+        return self.loss
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        L = _ffi.lib()
+        es = self.p.element_size()
+        pw, gw, mw, vw = (ctypes.c_void_p(t.data_ptr()) for t in (self.p, self.g, self.m, self.v))
+        check(L.ftlm_adam_step(self.nw, pw, gw, mw, vw, _vp(self.pb), lr, b1, b2, eps, self.step, _stream()),
+              "ftlm_adam_step")
+        off = self.nw * es
+        sh = lambda t: ctypes.c_void_p(t.data_ptr() + off)  # noqa: E731
+        check(L.ftlm_adam_step(self.nb, sh(self.p), sh(self.g), sh(self.m), sh(self.v), None, lr, b1, b2,
+                               eps, self.step, _stream()), "ftlm_adam_step")
+
+    def train_step(self, x, t, lr=1e-3):
+        loss = self.gradients(x, t)
+        self.adam(lr)
+        return loss
+
+    def host_params(self):
+        """FP32 master parameters as the oracle's [W0, b0, ..., W3, b3] list."""
+        p = self.p.cpu().numpy().astype(np.float64)
+        out, ow, ob = [], 0, self.nw
+        for fi, fo in zip(LAYERS[:-1], LAYERS[1:]):
+            out.append(p[ow:ow + fi * fo].reshape(fi, fo))
+            out.append(p[ob:ob + fo])
+            ow += fi * fo
+            ob += fo
+        return out
+
+
+# --------------------------------------------------------------------------- data
+def generate_dataset(params: np.ndarray, T: np.ndarray, R: int = 20, n_lanczos: int = 100,
+                     seed: int = 5000, chunk: int = 128, precision: int = 1):
+    """FTLM curves (ln Z, M, C) of the cfg5 ring for every parameter row, from the
+    batched GPU path (one instance per parameter row, its own field)."""
+    import ftlm_workloads as W  # seeded parameter generator (no method arithmetic)
+    from . import Hamiltonian, run_batched
+    P = len(params)
+    lnZ = np.zeros((P, len(T)))
+    M = np.zeros((P, len(T)))
+    C = np.zeros((P, len(T)))
+    for s0 in range(0, P, chunk):
+        rows = range(s0, min(P, s0 + chunk))
+        hams, fields = [], []
+        for i in rows:
+            sysm = W.cfg5_system(params[i])
+            hams.append(Hamiltonian(sysm))
+            fields.append(np.asarray(sysm.B, np.float64)[None, :])
+        res = run_batched(hams, R, n_lanczos, T, fields, seed=seed + s0, precision=precision)
+        for j, i in enumerate(rows):
+            lnZ[i], M[i], C[i] = res[j]["lnZ"][0], res[j]["M"][0], res[j]["C"][0]
+        for h in hams:
+            h.close()
+    return lnZ, M, C
+
+
+def train(model: MLP, x: np.ndarray, y: np.ndarray, epochs: int = 20, batch: int = 4096,
+          lr: float = 2e-3, seed: int = 0, time_budget_s: Optional[float] = None):
+    """Adam on mean squared error; cosine learning-rate decay.  Returns losses."""
+    torch = _torch()
+    X = torch.as_tensor(np.asarray(x, np.float32), device="cuda")
+    Y = torch.as_tensor(np.asarray(y, np.float32), device="cuda")
+    n = len(X)
+    rng = np.random.default_rng(seed)
+    steps_per_epoch = max(1, n // batch)
+    total = epochs * steps_per_epoch
+    losses, it, t0 = [], 0, time.time()
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(n), device="cuda")
+        ep_loss = torch.zeros((), device="cuda")
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            cur_lr = lr * 0.5 * (1 + math.cos(math.pi * it / total))
+            ep_loss = ep_loss + model.train_step(X[idx], Y[idx], cur_lr)[0]
+            it += 1
+        losses.append(float(ep_loss) / steps_per_epoch)
+        if time_budget_s is not None and time.time() - t0 > time_budget_s:
+            break
+    return losses
+
+
+class Surrogate:
+    """Ensemble of two MLPs with a gate and FTLM fallback."""
+
+    def __init__(self, models, disagreement: float = 0.05):
+        self.models = list(models)
+        self.disagreement = disagreement
+
+    def predict(self, params: np.ndarray, T: np.ndarray):
+        """Mean prediction and the ensemble spread (normalised units)."""
+        torch = _torch()
+        x = torch.as_tensor(encode_inputs(params, T).astype(np.float32), device="cuda")
+        ys = [m.forward(x).cpu().numpy().astype(np.float64) for m in self.models]
+        y = np.mean(ys, axis=0)
+        spread = np.max(np.abs(ys[0] - ys[-1]).reshape(-1, len(T), 3), axis=(1, 2))
+        lnZ, M, C = decode_outputs(y, T)
+        return lnZ, M, C, spread
+
+    def in_domain(self, params: np.ndarray, T: np.ndarray):
+        p = np.asarray(params, np.float64).reshape(-1, 6)
+        ok = np.all((p >= PARAM_LO - 1e-12) & (p <= PARAM_HI + 1e-12), axis=1)
+        T = np.asarray(T)
+        return ok & bool(np.all((T >= T_LO - 1e-12) & (T <= T_HI + 1e-12)))
+
+    def predict_or_fallback(self, params: np.ndarray, T: np.ndarray, R: int = 20, n_lanczos: int = 100,
+                            seed: int = 7):
+        """Surrogate where the gate accepts, full FTLM (GPU) elsewhere.  Returns
+        lnZ, M, C [P, nT] and the boolean fallback mask."""
+        params = np.asarray(params, np.float64).reshape(-1, 6)
+        lnZ, M, C, spread = self.predict(params, T)
+        fb = ~self.in_domain(params, T) | (spread > self.disagreement)
+        if np.any(fb):
+            idx = np.nonzero(fb)[0]
+            l2, m2, c2 = generate_dataset(params[idx], T, R, n_lanczos, seed=seed, precision=0)
+            lnZ[idx], M[idx], C[idx] = l2, m2, c2
+        return lnZ, M, C, fb
