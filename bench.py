@@ -80,6 +80,52 @@ def cpu_baseline(sysm, spec, budget_s=12.0):
                                                                spec.R * spec.n_lanczos)}
 
 
+def curve_err(x, ref):
+    import numpy as np
+    ref = np.asarray(ref)
+    floor = 1e-3 * np.max(np.abs(ref))
+    return float(np.max(np.abs(np.asarray(x) - ref) / np.maximum(np.abs(ref), max(floor, 1e-300))))
+
+
+def batched_vs_plain(n_inst=8, n_dirs=4):
+    """Batched FP32-storage FTLM against plain FP64 FTLM on the same curves: the
+    first n_inst instances of the 64-instance batched workload, n_dirs of its 50
+    field directions each, R = 16, N_L = 120, same seeded random vectors."""
+    import numpy as np
+    import torch
+
+    import ftlm_workloads as W
+    import paper_2607_25585_amd as F
+    systems, spec, fields = W.cfg3()
+    systems = systems[:n_inst]
+    fl = [fields[k][:n_dirs] for k in range(n_inst)]
+    hams = [F.Hamiltonian(s) for s in systems]
+    # warm-up on a tiny run (kernel loading), outside the timed region
+    F.run_batched(hams[:1], spec.R, 4, spec.T, [fl[0][:1]], seed=spec.seed, precision=F.FTLM_C64)
+    F.run(hams[0], spec.R, 4, spec.T, seed=spec.seed, fields=fl[0][:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bat = F.run_batched(hams, spec.R, spec.n_lanczos, spec.T, fl, seed=spec.seed, precision=F.FTLM_C64)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    print("batched fp32 subset done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plain = [F.run(h, spec.R, spec.n_lanczos, spec.T, seed=spec.seed, fields=fl[k], instance=k)
+             for k, h in enumerate(hams)]
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    print("plain fp64 subset done", file=sys.stderr, flush=True)
+    n_curves = n_inst * n_dirs
+    err_c = max(curve_err(bat[k]["C"][f], plain[k]["C"][f]) for k in range(n_inst) for f in range(n_dirs))
+    err_m = max(curve_err(bat[k]["M"][f], plain[k]["M"][f]) for k in range(n_inst) for f in range(n_dirs))
+    return {"curves": n_curves, "subset": "instances 0..%d (N=%s) x %d field directions, R=%d, N_L=%d"
+            % (n_inst - 1, [s.n_sites for s in systems], n_dirs, spec.R, spec.n_lanczos),
+            "batched_fp32_curves_per_s": round(n_curves / t_b, 4),
+            "plain_fp64_curves_per_s": round(n_curves / t_p, 4),
+            "speedup": round(t_p / t_b, 3), "max_C_err_vs_plain_fp64": err_c,
+            "max_M_err_vs_plain_fp64": err_m, "C_within_1e-3": bool(err_c <= 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +136,8 @@ def main():
     ap.add_argument("--columns", type=int, default=0,
                     help="random vectors iterated together (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -120,6 +168,11 @@ def main():
     nb = ctypes.c_size_t()
     _ffi.check(_ffi.lib().ftlm_run_workspace_size(ham.handle, ctypes.byref(p), ctypes.byref(nb)))
     ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    tuning = None
+    if not args.no_tune:
+        from paper_2607_25585_amd import autotune
+        tuning = autotune.tune(ham, prec, K, use_cache=False)
+        print("autotune done", tuning, file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         step()
@@ -168,7 +221,10 @@ def main():
         "hv_hbm_frac_algorithmic": round(hv_gbps / HBM_PEAK_GBPS, 4),
         "roofline": roof,
         "E_min": float(res["E_min"][0]),
+        "hv_tuning": tuning,
     }
+    if not args.no_batched:
+        out["batched_fp32_vs_plain_fp64"] = batched_vs_plain()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysm, spec)
     print(json.dumps(out), flush=True)

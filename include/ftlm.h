@@ -97,6 +97,21 @@ int ftlm_hamiltonian_set_field(ftlm_hamiltonian *h, const double B[3]);
 int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, const void *v,
                void *w, void *stream);
 
+/* Autotuner: times every admissible H*v configuration for (precision, n_cols) on
+ * the caller's device buffers v, w ([dim][n_cols], as ftlm_apply) -- variants
+ * 1 = direct gather (columns per lane 1, 2, 4, 8), 2 = windowed LDS passes,
+ * 3 = LDS tile (spin 1/2, N >= 11), each at 512, 1024, 2048 and 4096 blocks --
+ * with HIP events on the stream (blocking), and stores the fastest in the handle
+ * for later ftlm_apply / ftlm_run launches of the same shape.  Outputs (may be
+ * NULL): the chosen variant, grid size, columns per lane and its mean time. */
+int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, const void *v,
+                              void *w, void *stream, int32_t *variant, int32_t *grid_cap,
+                              int32_t *kc, float *best_ms);
+/* Sets the H*v configuration for (precision, n_cols) directly (e.g. from a cache
+ * of earlier autotune results); variant 0 restores the built-in heuristic. */
+int ftlm_hamiltonian_set_tuning(ftlm_hamiltonian *h, int32_t precision, int32_t n_cols,
+                                int32_t variant, int32_t grid_cap, int32_t kc);
+
 /* Start vectors of Eqs. (E-1-1), (E-1-2): out[nu*n_cols + c] = x + i y with x, y
  * independent standard normals for random vector r = r0 + c.  The bits come from
  * Philox4x32-10 (Salmon et al., SC'11) with key (seed low 32, seed high 32) and

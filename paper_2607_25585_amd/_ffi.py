@@ -89,6 +89,11 @@ def lib():
                                            ctypes.c_int32, c_int32_p,
                                            ctypes.POINTER(ctypes.c_uint32), c_int32_p, c_int32_p,
                                            c_int32_p, c_int32_p, c_double_p]
+        L.ftlm_hamiltonian_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
+                                                c_int32_p, c_int32_p, c_int32_p,
+                                                ctypes.POINTER(ctypes.c_float)]
+        L.ftlm_hamiltonian_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_int32, ctypes.c_int32]
         _lib = L
     return _lib
 

@@ -136,8 +136,15 @@ struct PassPlan {
   size_t rec_bytes = 0;
 };
 
+struct HvTuning {
+  int variant = 0;   // 0 = heuristic, 1 = direct gather, 2 = windowed passes, 3 = LDS tile
+  int grid_cap = 0;  // 0 = default
+  int kc = 0;        // columns per lane of the direct kernels (0 = widest dividing K)
+};
+
 struct DevHam {
   HamGeom geom;
+  HvTuning tune[2][65];  // [precision][columns]
   DevTables<double> t64;
   DevTables<float> t32;
   PassPlan plan64, plan32;  // windowed-pass plans for complex128 / complex64

@@ -1033,13 +1033,15 @@ __global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, HvP
   hv_finish<KC>(P, red);
 }
 
-static bool use_tile(const HamGeom &g, int K) { return g.spin_half && g.n >= kTileBits && K == 1; }
+static bool tile_ok(const HamGeom &g, int K) { return g.spin_half && g.n >= kTileBits && K == 1; }
+static thread_local int g_variant = 0;  // variant of the launch in progress (0 = heuristic)
+static bool use_tile(const HamGeom &g, int K) { return tile_ok(g, K) && (g_variant == 0 || g_variant == 3); }
 
 // Windowed passes pay off once the vector leaves the caches.
 static bool use_passes(const HamGeom &g, int K, int variant) {
   if (variant == 1 || variant == 3) return false;
   if (variant == 2) return K == 1;
-  return K == 1 && g.dim >= (1u << 20) && !use_tile(g, K);
+  return K == 1 && g.dim >= (1u << 20) && !tile_ok(g, K);
 }
 
 template <typename R>
@@ -1202,6 +1204,7 @@ int hv_grid_blocks(const DevHam &dh, const HvLaunch &L, int *gx, int *gy, int *k
     ntile = g.dim >> kTileBits;
     k = 1;
   }
+  if (L.variant == 3 && !tile_ok(g, L.K)) return FTLM_EINVAL;
   int cap = L.grid_cap > 0 ? L.grid_cap : 2048;
   if (L.lz) cap = cap < 2048 ? cap : 2048;  // partials buffer holds 2048 slots per column block
   *gx = (int)(ntile < (uint32_t)cap ? ntile : (uint32_t)cap);
@@ -1243,9 +1246,22 @@ static void launch_hv_r(const DevHam &dh, const DevTables<R> &tb, const HvParams
   }
 }
 
-int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s) {
+int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
+  HvLaunch L = Lin;
+  if (L.K >= 1 && L.K <= 64 && (L.precision == 0 || L.precision == 1)) {
+    const HvTuning &tn = dh.tune[L.precision][L.K];
+    if (!L.variant) L.variant = tn.variant;
+    if (!L.grid_cap) L.grid_cap = tn.grid_cap;
+    if (!L.kc) L.kc = tn.kc;
+  }
+  if (!L.variant) {
+    const char *e = std::getenv("FTLM_HV_VARIANT");
+    L.variant = e ? std::atoi(e) : 0;
+  }
+  g_variant = L.variant;
   int gx, gy, kc;
-  hv_grid_blocks(dh, L, &gx, &gy, &kc);
+  const int rcg = hv_grid_blocks(dh, L, &gx, &gy, &kc);
+  if (rcg) return rcg;
   HvParams P{};
   P.K = L.K;
   P.ntile = (dh.geom.spin_half && dh.geom.n >= kLowBits)
@@ -1267,12 +1283,7 @@ int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s) {
     P.yre_out = L.lz->yre_out;
     P.yim_out = L.lz->yim_out;
   }
-  int variant = L.variant;
-  if (!variant) {
-    const char *e = std::getenv("FTLM_HV_VARIANT");
-    variant = e ? std::atoi(e) : 0;
-  }
-  if (use_passes(dh.geom, L.K, variant)) {
+  if (use_passes(dh.geom, L.K, L.variant)) {
     const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
     int rc = (L.precision == FTLM_C64) ? launch_passes<float>(dh, dh.t32, dh.plan32, P, L.K, cap, s)
                                        : launch_passes<double>(dh, dh.t64, dh.plan64, P, L.K, cap, s);

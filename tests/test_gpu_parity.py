@@ -334,3 +334,18 @@ def test_cfg4_full_size_sampled_rows():
     sysm, spec = W.cfg4()
     _sampled_rows_check(sysm, 1, F().FTLM_C128, 1e-12)
     _sampled_rows_check(sysm, 2, F().FTLM_C64, 2e-5)
+
+
+def test_autotune_keeps_parity(tmp_path, monkeypatch):
+    monkeypatch.setenv("FTLM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_2607_25585_amd import autotune
+    rng = np.random.default_rng(55)
+    sysm = W.random_small_system(rng, 12, max_two_s=1)
+    sysm.two_s[:] = 1
+    ham = F().Hamiltonian(sysm)
+    c1 = autotune.tune(ham, F().FTLM_C128, 1)
+    c2 = autotune.tune(ham, F().FTLM_C128, 1)
+    assert not c1["cached"] and c2["cached"] and c1["variant"] in (1, 2, 3)
+    v = _rand_v(rng, ham.dim)
+    w = ham.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+    assert rel_max(w, of.Ham(sysm).apply(v)) < 1e-12
