@@ -126,6 +126,48 @@ def batched_vs_plain(n_inst=8, n_dirs=4):
             "max_M_err_vs_plain_fp64": err_m, "C_within_1e-3": bool(err_c <= 1e-3)}
 
 
+def hv_only(args, sysm, spec, ham, prec, K):
+    """H*v throughput alone: a plain device copy of 1 GiB (the calibration
+    kernel for HBM byte counters), then args.hv_reps applications of the tuned
+    H*v, each bracketed by HIP events on the launching stream."""
+    import torch
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = torch.complex128 if args.precision == "c128" else torch.complex64
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    shape = (ham.dim,) if K == 1 else (ham.dim, K)
+    v = torch.randn(shape, dtype=dt, device="cuda", generator=g)
+    w = torch.empty_like(v)
+    ham.apply(v, w)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.hv_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ham.apply(v, w)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(sorted(times)[len(times) // 2])
+    es = 16 if args.precision == "c128" else 8
+    nnz = ham.nnz_per_row
+    gbps = 2.0 * es * ham.dim * K / (ms * 1e-3) / 1e9
+    tflops = 8.0 * nnz * ham.dim * K / (ms * 1e-3) / 1e12
+    return {"metric": "H*v algorithmic GB/s (read v + write w)", "value": round(gbps, 2),
+            "unit": "GB/s", "n_gpus": 1, "hv_reps": args.hv_reps, "hv_ms_median": round(ms, 4),
+            "hv_ms_min": round(min(times), 4), "tflops": round(tflops, 3),
+            "hbm_frac_algorithmic": round(gbps / HBM_PEAK_GBPS, 4),
+            "f64_or_f32_valu_frac": round(tflops / PEAK["f64" if es == 16 else "f32"], 4),
+            "dtype": "f64" if es == 16 else "f32", "data": "synthetic",
+            "config": {"workload": "%s: N=%d spins, dim %d, %s, %d columns" % (
+                args.workload, sysm.n_sites, ham.dim, args.precision, K),
+                "nnz_per_row": round(nnz, 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +180,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON tuning cache: reuse a stored choice instead of timing the candidates")
+    ap.add_argument("--hv-only", action="store_true",
+                    help="time the H*v product alone (GB/s line) instead of whole curves")
+    ap.add_argument("--hv-reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -164,15 +211,24 @@ def main():
     # size the workspace once, outside the timed region
     import ctypes
     from paper_2607_25585_amd import _ffi
-    p, keep = F._params(spec.R, spec.n_lanczos, spec.T, spec.seed, None, prec, K, None, 0)
-    nb = ctypes.c_size_t()
-    _ffi.check(_ffi.lib().ftlm_run_workspace_size(ham.handle, ctypes.byref(p), ctypes.byref(nb)))
-    ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    if not args.hv_only:
+        p, keep = F._params(spec.R, spec.n_lanczos, spec.T, spec.seed, None, prec, K, None, 0)
+        nb = ctypes.c_size_t()
+        _ffi.check(_ffi.lib().ftlm_run_workspace_size(ham.handle, ctypes.byref(p), ctypes.byref(nb)))
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
     tuning = None
     if not args.no_tune:
         from paper_2607_25585_amd import autotune
-        tuning = autotune.tune(ham, prec, K, use_cache=False)
+        if args.tune_cache:
+            os.environ["FTLM_TUNE_CACHE"] = args.tune_cache
+        tuning = autotune.tune(ham, prec, K, use_cache=bool(args.tune_cache))
         print("autotune done", tuning, file=sys.stderr, flush=True)
+
+    if args.hv_only:
+        out = hv_only(args, sysm, spec, ham, prec, K)
+        out["hv_tuning"] = tuning
+        print(json.dumps(out), flush=True)
+        return
 
     for _ in range(args.warmup):
         step()
