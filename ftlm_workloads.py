@@ -44,7 +44,8 @@ import numpy as np
 __all__ = [
     "System", "RunSpec", "t_grid", "ring_couplings", "unit_vectors",
     "cfg1", "cfg2", "cfg2_hb", "cfg3", "cfg4", "cfg4_hb", "cfg5_params",
-    "cfg5_system", "random_small_system", "dimension", "WORKLOADS",
+    "cfg5_system", "random_small_system", "dimension", "ring6", "mn9",
+    "dodecahedron_directions", "WORKLOADS",
 ]
 
 
@@ -238,6 +239,72 @@ def random_small_system(rng: np.random.Generator, n_sites: int, max_two_s: int =
     return System(two_s=two_s, J=J, d=d, e=e, g=g, B=B, pos=pos, name=name)
 
 
+def ring6(B: float = 0.1) -> tuple[System, RunSpec]:
+    """Anisotropic ring of Sec. 3.2: N=6, s=5/2, nearest-neighbour J=0.02 K,
+    d=-20 K, all-to-all dipolar, B along z (0.1 T or 1 T in the paper).  Readings:
+    ring radius 0.5 nm in the xy-plane; non-collinear easy axes tilted 30 deg from
+    z towards the radial directions (phi_i = 2 pi i/6); g = 2.  sFTLM with
+    time-reversed pairs (R counts vectors)."""
+    n = 6
+    ang = 2 * np.pi * np.arange(n) / n
+    pos = 0.5 * np.stack([np.cos(ang), np.sin(ang), np.zeros(n)], axis=1)
+    sysm = System(two_s=np.full(n, 5, np.int32), J=ring_couplings(n, 0.02), d=np.full(n, -20.0),
+                  e=_tilted_axes(ang, math.radians(30.0)), g=np.full(n, 2.0),
+                  B=np.array([0.0, 0.0, float(B)]), pos=pos, name="ring6")
+    return sysm, RunSpec(R=20, n_lanczos=100, seed=6000, T=t_grid())
+
+
+def dodecahedron_directions() -> np.ndarray:
+    """The 10 directions of the 20 vertices of a regular dodecahedron (one of each
+    antipodal pair), unit vectors: the powder-average grid of Sec. 3.3."""
+    ph = (1 + math.sqrt(5)) / 2
+    verts = [(x, y, z) for x in (-1, 1) for y in (-1, 1) for z in (-1, 1)]
+    for a in (-1, 1):
+        for b in (-1, 1):
+            verts += [(0, a / ph, b * ph), (a / ph, b * ph, 0), (a * ph, 0, b / ph)]
+    v = np.asarray(verts, np.float64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    keep = []
+    for x in v:
+        if not any(np.allclose(x, -y) for y in keep):
+            keep.append(x)
+    return np.asarray(keep)
+
+
+def mn9(B: float = 1.0) -> tuple[System, RunSpec]:
+    """Mn9-like centred cube of Sec. 3.3: site 0 = centre s=5/2, sites 1..8 =
+    cube vertices s=2 (dimension 6 * 5^8 = 2,343,750).  Exchange J_c (centre to
+    vertices), J_s (edges of the top and bottom squares), J_e (vertical edges);
+    easy axis D on the vertices tilted 30 deg from z at azimuth +-10 deg from x
+    (alternating).  The paper does not print J_c, J_s, J_e, D: the values here
+    (J_c = 1.0, J_s = 0.5, J_e = 0.3, D = -2 K) are synthetic readings; no
+    dipolar term; g = 2; fields: |B| times the 10 dodecahedron directions
+    (powder average)."""
+    corners = [(x, y, z) for z in (1, -1) for (x, y) in ((1, 1), (-1, 1), (-1, -1), (1, -1))]
+    n = 9
+    J = np.zeros((n, n))
+    for v in range(1, 9):
+        J[0, v] = 1.0
+    for layer in (0, 4):
+        for k in range(4):
+            a, b = 1 + layer + k, 1 + layer + (k + 1) % 4
+            J[min(a, b), max(a, b)] = 0.5
+    for k in range(4):
+        J[1 + k, 5 + k] = 0.3
+    phi = np.array([math.radians(10.0 if v % 2 else -10.0) for v in range(8)])
+    axes = np.zeros((n, 3))
+    axes[0] = (0, 0, 1)
+    axes[1:] = _tilted_axes(phi, math.radians(30.0))
+    d = np.zeros(n)
+    d[1:] = -2.0
+    two_s = np.array([5] + [4] * 8, np.int32)
+    dirs = dodecahedron_directions()
+    sysm = System(two_s=two_s, J=J, d=d, e=axes, g=np.full(n, 2.0), B=float(B) * dirs[0],
+                  pos=None, name="mn9")
+    return sysm, RunSpec(R=20, n_lanczos=100, seed=7000, T=t_grid(), fields=float(B) * dirs)
+
+
 WORKLOADS = {
     "cfg1": cfg1, "cfg2": cfg2, "cfg2_hb": cfg2_hb, "cfg4": cfg4, "cfg4_hb": cfg4_hb,
+    "ring6": ring6, "mn9": mn9,
 }

@@ -100,7 +100,8 @@ int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, con
 /* Autotuner: times every admissible H*v configuration for (precision, n_cols) on
  * the caller's device buffers v, w ([dim][n_cols], as ftlm_apply) -- variants
  * 1 = direct gather (columns per lane 1, 2, 4, 8), 2 = windowed LDS passes,
- * 3 = LDS tile (spin 1/2, N >= 11), each at 512, 1024, 2048 and 4096 blocks --
+ * 3 = LDS tile (spin 1/2, N >= 11), 4 = L2-window passes (one column), each at
+ * 512, 1024, 2048 and 4096 blocks (variant 4: at most 2048) --
  * with HIP events on the stream (blocking), and stores the fastest in the handle
  * for later ftlm_apply / ftlm_run launches of the same shape.  Outputs (may be
  * NULL): the chosen variant, grid size, columns per lane and its mean time. */
@@ -167,6 +168,38 @@ int ftlm_run_workspace_size(const ftlm_hamiltonian *h, const ftlm_run_params *p,
  * Blocks on the stream before returning (results are host arrays). */
 int ftlm_run(const ftlm_hamiltonian *h, const ftlm_run_params *p, void *workspace,
              size_t bytes, void *stream, ftlm_result *out);
+
+/* Symmetric FTLM (sFTLM), Sec. 2.2, Eqs. (E-2-G) and (E-2-H), with pairs of
+ * mutually time-reversed random vectors.  R (even) counts vectors: R/2 Gaussian
+ * vectors (Philox vector index = pair index, as ftlm_gaussian_vectors) and their
+ * time reverses (Theta x)[dim-1-nu] = (-1)^{sum_i (2 s_i - d_i(nu))} conj(x[nu]).
+ * Each vector runs N_L Lanczos steps keeping all Krylov vectors; M is the ratio
+ * sum_r <r|exp(-H/2T) O exp(-H/2T)|r> / sum_r <r|exp(-H/T)|r> with the double
+ * sum of Eq. (E-2-H) over the Krylov eigenpairs, O = -sum_i g_i s_i.B_hat; ln Z,
+ * E and C as ftlm_run.  Uses p->R, n_lanczos (<= 140), seed, instance, T, n_T,
+ * fields, n_fields, precision; columns is ignored and r_init must be NULL.
+ * Workspace: (2 N_L + 1) vectors plus O(R N_L^2) doubles; no allocation.
+ * Blocks on the stream before returning. */
+int ftlm_run_sftlm_workspace_size(const ftlm_hamiltonian *h, const ftlm_run_params *p, size_t *bytes);
+int ftlm_run_sftlm(const ftlm_hamiltonian *h, const ftlm_run_params *p, void *workspace,
+                   size_t bytes, void *stream, ftlm_result *out);
+
+/* Chebyshev (kernel polynomial) expansion of the thermal traces without a
+ * smoothing kernel, the alternative to Lanczos named in Sec. 4: the same random
+ * vectors and H*v launch, with exp(-H/T) = exp(-lo/T) sum_{n<=N} c_n(a/T)
+ * T_n((H-b)/a), c_n(x) = (2 - delta_n0) (-1)^n exp(-x) I_n(x).  Spectral bounds
+ * [lo, hi]: the extreme Krylov eigenvalues of p->n_lanczos Lanczos steps on the
+ * first random vector of each field, widened by 2 % of their spread.  Moments
+ * mu_n = Re<r|T_n|r>, nu_n = Re<O r|T_n|r> for n <= N + 2 (N + 2 H*v per
+ * vector); ln Z, E = <H>, C = (<H^2> - <H>^2)/T^2 and M = <O> as in ftlm_run.
+ * n_moments = N (2 <= N <= 1e6).  Truncation is not smoothed: N must exceed about
+ * a/T_min for the lowest temperature to converge.  E_min receives lo;
+ * bounds (host, may be NULL) receives [n_fields][lo, hi].  columns and r_init
+ * are ignored / must be NULL.  Blocks on the stream before returning. */
+int ftlm_run_kpm_workspace_size(const ftlm_hamiltonian *h, const ftlm_run_params *p, int32_t n_moments,
+                                size_t *bytes);
+int ftlm_run_kpm(const ftlm_hamiltonian *h, const ftlm_run_params *p, int32_t n_moments, void *workspace,
+                 size_t bytes, void *stream, ftlm_result *out, double *bounds);
 
 /* Batched form: many Hamiltonian instances (uneven dimensions) and their field
  * directions run together; every Lanczos step is one persistent launch over a
@@ -238,6 +271,21 @@ int ftlm_describe_passes(const ftlm_system *sys, int32_t precision, int32_t max_
                          int32_t *n_pass, uint32_t *window_rows, int32_t *n_active,
                          int32_t *n_pairs, int32_t *n_singles, int32_t *pair_sites,
                          double *nnz_per_row);
+
+/* Host-only (no device work): the L2-window plan of the one-column H*v
+ * (variant 4).  A window is the set of rows sharing the digits of every site
+ * outside window_sites; its rows fit a share of one XCD's L2, and each pass walks
+ * the windows so that all blocks of an XCD work on the same one, applying the
+ * terms whose sites all lie in the window.  window_bytes <= 0 selects the library
+ * setting ($FTLM_L2_WINDOW_KB, default 1024).  Per pass p < max_pass:
+ * window_rows[p], window_sites[p] (bit k = site k), n_pairs[p] and
+ * single_sites[p] (bit k: the pass applies the single-site flips of site k);
+ * pair_sites (may be NULL) receives the (i, j) sites of every pair term, pass by
+ * pass.  Returns FTLM_ERANGE when no plan fits the window size. */
+int ftlm_describe_windows(const ftlm_system *sys, int32_t precision, int64_t window_bytes,
+                          int32_t max_pass, int32_t *n_pass, uint32_t *window_rows,
+                          uint32_t *window_sites, int32_t *n_pairs, uint32_t *single_sites,
+                          int32_t *pair_sites);
 
 const char *ftlm_last_error(void);
 int ftlm_version(void);

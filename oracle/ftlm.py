@@ -271,3 +271,121 @@ def ftlm(system, R, n_lanczos, T, seed=0, fields=None, instance=0, start_vectors
             res["q1"] = q1_l
         out.append(res)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Symmetric FTLM with time-reversed pairs of random vectors (Sec. 2.2,
+# Eqs. (E-2-G), (E-2-H); pairs of mutually time-reversed vectors as proposed in
+# the same section).  TEST INFRASTRUCTURE ONLY.
+#
+# Readings: R counts vectors, so R/2 Gaussian vectors are drawn (Philox stream
+# index = pair index p) and each is used together with its time reverse.  The
+# time reversal of the product basis with Condon-Shortley phases is
+#     (Theta x)[nu'] = (-1)^{sum_i (2 s_i - d_i(nu))} conj(x[nu]),
+# nu' the state with every m_i -> -m_i (digits d_i -> 2 s_i - d_i, i.e.
+# nu' = dim - 1 - nu).  The Krylov eigenvectors |n(r)> = sum_a Q_an |v_a> are
+# built from the stored Lanczos vectors, and <m|O|n> = (Q^T V^H O V Q)_mn.
+# ---------------------------------------------------------------------------
+
+
+def digit_sums(two_s):
+    """sum_i d_i(nu) for every basis index nu (site 0 fastest)."""
+    two_s = np.asarray(two_s, np.int64)
+    dim = int(np.prod(two_s + 1))
+    nu = np.arange(dim, dtype=np.int64)
+    tot = np.zeros(dim, np.int64)
+    for ts in two_s:
+        tot += nu % (ts + 1)
+        nu //= ts + 1
+    return tot
+
+
+def time_reverse(two_s, x):
+    """Theta x in the product basis (see the module notes above)."""
+    x = np.asarray(x, np.complex128)
+    two_s = np.asarray(two_s, np.int64)
+    phase = np.where((int(two_s.sum()) - digit_sums(two_s)) % 2 == 0, 1.0, -1.0)
+    return (phase * np.conj(x))[::-1].copy()
+
+
+def lanczos_basis(ham, r, n_lanczos, reorth=False):
+    """Paige-order Lanczos from r/|r| keeping the basis: returns alpha, beta, V
+    ([k][dim], rows v_1..v_k) with the breakdown rule of the FTLM driver."""
+    v = np.asarray(r, np.complex128) / np.linalg.norm(r)
+    V = [v]
+    alpha, beta = [], []
+    v_prev = np.zeros_like(v)
+    b_prev = 0.0
+    scale = 0.0
+    for j in range(n_lanczos):
+        u = ham.apply(V[-1]) - b_prev * v_prev
+        a = float(np.real(np.vdot(V[-1], u)))
+        u = u - a * V[-1]
+        if reorth:
+            for q in V:
+                u = u - np.vdot(q, u) * q
+        b = float(np.linalg.norm(u))
+        alpha.append(a)
+        scale = max(scale, abs(a))
+        if j + 1 == n_lanczos:
+            beta.append(b)
+            break
+        if not b > 1e-12 * scale:
+            beta.append(b)
+            break
+        scale = max(scale, b)
+        beta.append(b)
+        v_prev = V[-1]
+        b_prev = b
+        V.append(u / b)
+    k = len(alpha)
+    return np.array(alpha), np.array(beta), np.array(V[:k])
+
+
+def sftlm(system, R, n_lanczos, T, seed=0, fields=None, instance=0, reorth=False):
+    """sFTLM curves (Eq. E-2-G for M with O = -sum_i g_i s_i.B_hat; Eq. E-2-D
+    for Z; E and C from the Ritz values as in the plain driver) for each field,
+    with R/2 time-reversed pairs of random vectors."""
+    if R % 2:
+        raise ValueError("R must be even (time-reversed pairs)")
+    if fields is None:
+        fields = np.asarray(system.B, np.float64)[None, :]
+    fields = np.asarray(fields, np.float64).reshape(-1, 3)
+    T = np.asarray(T, np.float64)
+    out = []
+    for f, B in enumerate(fields):
+        ham = Ham(system, B)
+        mom = Moment(system, field_direction(B))
+        cols = []
+        for p in range(R // 2):
+            r0 = gaussian_vector(seed, p, f, instance, ham.dim)
+            for rv in (r0, time_reverse(system.two_s, r0)):
+                a, b, V = lanczos_basis(ham, rv, n_lanczos, reorth)
+                k = len(a)
+                if k == 1:
+                    eps, Q = np.array([a[0]]), np.ones((1, 1))
+                else:
+                    eps, Q = scipy.linalg.eigh_tridiagonal(a, b[:k - 1])
+                OV = np.array([mom.apply(x) for x in V])
+                OK = np.conj(V) @ OV.T          # <v_a|O|v_b>
+                cols.append((eps, Q, OK))
+        emin = min(float(c[0].min()) for c in cols)
+        lnZ, E, C, M = [], [], [], []
+        eps_all = np.concatenate([c[0] for c in cols])
+        w1_all = np.concatenate([c[1][0, :] ** 2 for c in cols])
+        for t in T:
+            boltz = np.exp(-(eps_all - emin) / t) * w1_all
+            den = boltz.sum()
+            em = np.sum(boltz * eps_all) / den
+            num = 0.0
+            for eps, Q, OK in cols:
+                h = np.exp(-(eps - emin) / (2 * t)) * Q[0, :]   # e^{-beta(eps-Emin)/2} <n|r>
+                z = Q @ h                                        # sum_n Q_an h_n
+                num += float(np.real(z @ OK @ z))
+            lnZ.append(np.log(ham.dim / R) - emin / t + np.log(den))
+            E.append(em)
+            C.append(np.sum(boltz * (eps_all - em) ** 2) / den / t ** 2)
+            M.append(num / den)
+        out.append(dict(lnZ=np.array(lnZ), E=np.array(E), C=np.array(C), M=np.array(M),
+                        E_min=emin, n_lanczos_used=np.array([len(c[0]) for c in cols])))
+    return out

@@ -84,6 +84,27 @@ def describe_passes(system, precision: int = FTLM_C128):
                 pair_sites=ps[:2 * tot].reshape(-1, 2), nnz_per_row=nnz.value)
 
 
+def describe_windows(system, precision: int = FTLM_C128, window_bytes: int = 0):
+    """Host-only: the L2-window plan of the one-column H*v (variant 4)."""
+    s, keep = _system_struct(system)
+    npass = ctypes.c_int32()
+    check(_ffi.lib().ftlm_describe_windows(ctypes.byref(s), int(precision), int(window_bytes), 0,
+                                           ctypes.byref(npass), None, None, None, None, None),
+          "ftlm_describe_windows")
+    m = npass.value
+    u32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))  # noqa: E731
+    i32 = lambda a: a.ctypes.data_as(_ffi.c_int32_p)  # noqa: E731
+    wr, ws, ss = (np.zeros(m, np.uint32) for _ in range(3))
+    npp = np.zeros(m, np.int32)
+    ps = np.zeros(2 * 4096, np.int32)
+    check(_ffi.lib().ftlm_describe_windows(ctypes.byref(s), int(precision), int(window_bytes), m,
+                                           ctypes.byref(npass), u32(wr), u32(ws), i32(npp), u32(ss),
+                                           i32(ps)), "ftlm_describe_windows")
+    tot = int(npp.sum())
+    return dict(window_rows=wr, window_sites=ws, n_pairs=npp, single_sites=ss,
+                pair_sites=ps[:2 * tot].reshape(-1, 2))
+
+
 class Hamiltonian:
     """Compiled Hamiltonian of Eq. (mce-hamop) on the current HIP device.
 
@@ -220,6 +241,56 @@ def run(ham: Hamiltonian, R: int, n_lanczos: int, T, seed: int = 0, fields=None,
                               ctypes.c_size_t(ws.numel()), _stream(), ctypes.byref(res)),
           "ftlm_run")
     del keep
+    return out
+
+
+def run_sftlm(ham: Hamiltonian, R: int, n_lanczos: int, T, seed: int = 0, fields=None,
+              precision: int = FTLM_C128, instance: int = 0, workspace=None):
+    """Symmetric FTLM (Eqs. E-2-G, E-2-H) with R/2 time-reversed pairs of random
+    vectors.  Returns lnZ, E, C, M ([n_fields, n_T]), n_lanczos_used, E_min."""
+    torch = _torch()
+    p, keep = _params(R, n_lanczos, T, seed, fields, precision, 1, None, instance)
+    nbytes = ctypes.c_size_t()
+    check(_ffi.lib().ftlm_run_sftlm_workspace_size(ham.handle, ctypes.byref(p), ctypes.byref(nbytes)),
+          "ftlm_run_sftlm_workspace_size")
+    ws = workspace
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+    nf, nT = p.n_fields, p.n_T
+    out = {k: np.zeros((nf, nT)) for k in ("lnZ", "E", "C", "M")}
+    out["n_lanczos_used"] = np.zeros((nf, R), np.int32)
+    out["E_min"] = np.zeros(nf)
+    res = _ffi.FtlmResult(_dptr(out["lnZ"]), _dptr(out["E"]), _dptr(out["C"]), _dptr(out["M"]),
+                          out["n_lanczos_used"].ctypes.data_as(_ffi.c_int32_p),
+                          _dptr(out["E_min"]), None, None, None, None)
+    check(_ffi.lib().ftlm_run_sftlm(ham.handle, ctypes.byref(p), ctypes.c_void_p(ws.data_ptr()),
+                                    ctypes.c_size_t(ws.numel()), _stream(), ctypes.byref(res)),
+          "ftlm_run_sftlm")
+    return out
+
+
+def run_kpm(ham: Hamiltonian, R: int, n_moments: int, T, seed: int = 0, fields=None,
+            precision: int = FTLM_C128, instance: int = 0, n_bound_steps: int = 40, workspace=None):
+    """Chebyshev expansion of the thermal traces (no smoothing kernel) with the
+    FTLM random vectors.  Returns lnZ, E, C, M ([n_fields, n_T]), E_lo, E_hi."""
+    torch = _torch()
+    p, keep = _params(R, n_bound_steps, T, seed, fields, precision, 1, None, instance)
+    nbytes = ctypes.c_size_t()
+    check(_ffi.lib().ftlm_run_kpm_workspace_size(ham.handle, ctypes.byref(p), int(n_moments),
+                                                 ctypes.byref(nbytes)), "ftlm_run_kpm_workspace_size")
+    ws = workspace
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+    nf, nT = p.n_fields, p.n_T
+    out = {k: np.zeros((nf, nT)) for k in ("lnZ", "E", "C", "M")}
+    out["E_min"] = np.zeros(nf)
+    bounds = np.zeros((nf, 2))
+    res = _ffi.FtlmResult(_dptr(out["lnZ"]), _dptr(out["E"]), _dptr(out["C"]), _dptr(out["M"]),
+                          None, _dptr(out["E_min"]), None, None, None, None)
+    check(_ffi.lib().ftlm_run_kpm(ham.handle, ctypes.byref(p), int(n_moments), ctypes.c_void_p(ws.data_ptr()),
+                                  ctypes.c_size_t(ws.numel()), _stream(), ctypes.byref(res), _dptr(bounds)),
+          "ftlm_run_kpm")
+    out["E_lo"], out["E_hi"] = bounds[:, 0].copy(), bounds[:, 1].copy()
     return out
 
 

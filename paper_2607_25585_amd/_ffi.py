@@ -63,9 +63,17 @@ def lib():
         L.ftlm_gaussian_vectors.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                             ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64, vp,
                                             vp]
+        L.ftlm_run_sftlm_workspace_size.argtypes = [vp, ctypes.POINTER(FtlmRunParams),
+                                                     ctypes.POINTER(ctypes.c_size_t)]
         L.ftlm_run_workspace_size.argtypes = [vp, ctypes.POINTER(FtlmRunParams),
                                               ctypes.POINTER(ctypes.c_size_t)]
         L.ftlm_run.argtypes = [vp, ctypes.POINTER(FtlmRunParams), vp, ctypes.c_size_t, vp,
+                               ctypes.POINTER(FtlmResult)]
+        L.ftlm_run_kpm_workspace_size.argtypes = [vp, ctypes.POINTER(FtlmRunParams), ctypes.c_int32,
+                                                   ctypes.POINTER(ctypes.c_size_t)]
+        L.ftlm_run_kpm.argtypes = [vp, ctypes.POINTER(FtlmRunParams), ctypes.c_int32, vp, ctypes.c_size_t,
+                                   vp, ctypes.POINTER(FtlmResult), c_double_p]
+        L.ftlm_run_sftlm.argtypes = [vp, ctypes.POINTER(FtlmRunParams), vp, ctypes.c_size_t, vp,
                                ctypes.POINTER(FtlmResult)]
         L.ftlm_run_batched_workspace_size.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
                                                       ctypes.POINTER(FtlmRunParams),
@@ -89,6 +97,10 @@ def lib():
                                            ctypes.c_int32, c_int32_p,
                                            ctypes.POINTER(ctypes.c_uint32), c_int32_p, c_int32_p,
                                            c_int32_p, c_int32_p, c_double_p]
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.ftlm_describe_windows.argtypes = [ctypes.POINTER(FtlmSystem), ctypes.c_int32,
+                                            ctypes.c_int64, ctypes.c_int32, c_int32_p, u32p, u32p,
+                                            c_int32_p, u32p, c_int32_p]
         L.ftlm_hamiltonian_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
                                                 c_int32_p, c_int32_p, c_int32_p,
                                                 ctypes.POINTER(ctypes.c_float)]

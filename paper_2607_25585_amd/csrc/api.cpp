@@ -202,11 +202,31 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
     spj[q] = hh.pj[perm[q]];
   }
   const size_t wb = window_bytes_setting();
-  int prc = plan_passes_sorted(hh, spi, spj, wb / 16, dh.plan64);
-  if (!prc) prc = plan_passes_sorted(hh, spi, spj, wb / 8, dh.plan32);
-  if (prc) {
-    err = "no windowed-pass plan fits the window size";
-    return prc;
+  const size_t l2b = l2_window_bytes_setting();
+  // the plans depend on the pair structure (fixed per handle), on which sites
+  // have single flips (field dependent) and on the window sizes
+  uint32_t smask = 0;
+  for (int k = 0; k < n; k++)
+    if (site_has_singles(hh, k)) smask |= 1u << k;
+  const bool replan = !dh.plan_valid || dh.plan_smask != smask || dh.plan_wb != wb || dh.plan_l2b != l2b;
+  if (replan) {
+    int prc = plan_passes_sorted(hh, spi, spj, wb / 16, dh.plan64);
+    if (!prc) prc = plan_passes_sorted(hh, spi, spj, wb / 8, dh.plan32);
+    if (prc) {
+      err = "no windowed-pass plan fits the window size";
+      return prc;
+    }
+    const bool half = hh.spin_half && n >= kLowBits;
+    prc = plan_l2_windows(hh, spi, spj, l2b / 16, half, dh.win64);
+    if (!prc) prc = plan_l2_windows(hh, spi, spj, l2b / 8, half, dh.win32);
+    if (prc) {
+      err = "no L2-window plan fits the window size";
+      return prc;
+    }
+    dh.plan_valid = true;
+    dh.plan_smask = smask;
+    dh.plan_wb = wb;
+    dh.plan_l2b = l2b;
   }
   dh.plan64.window_bytes = wb;
   dh.plan32.window_bytes = wb;
@@ -219,6 +239,8 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   TableOffsets<float> o32 = pack_tables<float>(hh, perm, b);
   const size_t off_p64 = b.add(dh.plan64.pairs.data(), dh.plan64.pairs.size() * sizeof(int4));
   const size_t off_p32 = b.add(dh.plan32.pairs.data(), dh.plan32.pairs.size() * sizeof(int4));
+  const size_t off_w64 = b.add(dh.win64.plist.data(), dh.win64.plist.size() * sizeof(int4));
+  const size_t off_w32 = b.add(dh.win32.plist.data(), dh.win32.plist.size() * sizeof(int4));
   const size_t bytes = (b.bytes.size() + 255) & ~size_t(255);
   if (dh.block && dh.block_bytes != bytes) {
     (void)hipFree(dh.block);
@@ -241,6 +263,8 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   dh.t32 = resolve<float>(o32, base);
   dh.plan64.d_pairs = reinterpret_cast<const int4 *>(base + off_p64);
   dh.plan32.d_pairs = reinterpret_cast<const int4 *>(base + off_p32);
+  dh.win64.d_plist = reinterpret_cast<const int4 *>(base + off_w64);
+  dh.win32.d_plist = reinterpret_cast<const int4 *>(base + off_w32);
   HamGeom &g = dh.geom;
   std::memset(&g, 0, sizeof(g));
   g.n = n;

@@ -1,0 +1,70 @@
+// Fixed-order device reductions shared by the HIP kernels: wave butterflies,
+// then the block's waves in order, then per-block partials summed in block
+// order by the last block to finish (device-wide counter), so every dot
+// product is bitwise reproducible run to run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ftlm_internal.hpp"
+
+namespace ftlm {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sums NV*KC per-lane values over the block (fixed order) and writes them to
+// part[slot*NV*KC ...].  Returns true on the last block of the grid to get
+// there (device-wide counter), which may then read every block's partials and
+// reduce them in slot order; the caller resets the counter.
+template <int NV, int KC>
+__device__ __forceinline__ bool block_partials(const double (&val)[NV][KC], double *part,
+                                               int slot, unsigned *counter, unsigned total) {
+  __shared__ double red[kBlock / 64][NV * KC];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NV; a++)
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      double s = wave_sum(val[a][q]);
+      if (lane == 0) red[wv][a * KC + q] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < NV * KC) {
+    double s = 0;
+    for (int w2 = 0; w2 < kBlock / 64; w2++) s += red[w2][threadIdx.x];
+    part[(size_t)slot * NV * KC + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == total - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+// Sum of x[bx * stride] over bx < n by the whole block in a fixed order (thread
+// t takes bx = t, t + 256, ...; then wave butterflies and the waves in order).
+// Every thread gets the total.  Called uniformly by all threads of the block.
+__device__ __forceinline__ double block_sum_strided(const double *x, unsigned n, size_t stride) {
+  __shared__ double sh[kBlock / 64];
+  double s = 0;
+  for (unsigned bx = threadIdx.x; bx < n; bx += kBlock) s += x[(size_t)bx * stride];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double tot = 0;
+#pragma unroll
+  for (int w2 = 0; w2 < kBlock / 64; w2++) tot += sh[w2];
+  __syncthreads();
+  return tot;
+}
+
+}  // namespace ftlm

@@ -137,9 +137,41 @@ struct PassPlan {
 };
 
 struct HvTuning {
-  int variant = 0;   // 0 = heuristic, 1 = direct gather, 2 = windowed passes, 3 = LDS tile
+  int variant = 0;   // 0 = heuristic, 1 = direct gather, 2 = windowed passes, 3 = LDS tile, 4 = L2 windows
   int grid_cap = 0;  // 0 = default
   int kc = 0;        // columns per lane of the direct kernels (0 = widest dividing K)
+};
+
+// One pass of the L2-window H*v.  The rows are walked window by window: a
+// window is the set of rows that share the digits of every "outer" site; its
+// size is chosen to fit an XCD's L2, and all blocks of one XCD work on the same
+// window, so every gather of a term acting only on window sites hits L2.  The
+// pass applies the diagonal (if diag), the single flips of the sites in smask
+// and the pairs [p0, p0 + np) of the plan's pair list; passes after the first
+// add to w, the last one runs the Lanczos epilogue.
+struct WinPass {
+  int first, last, diag;
+  int p0, np;
+  int np_ll, np_lh;  // spin-1/2: the pass's pairs are ordered (both sites < 8),
+                     // (one site < 8), (both >= 8); counts of the first two classes
+  uint32_t smask;
+  uint32_t nwin;   // windows
+  uint32_t nin;    // 256-row work items per window
+  // spin-1/2 kernel: row bits 0..7 run over the lanes; emask / omask are the
+  // row bits >= 8 that vary inside a window / index the windows
+  uint32_t emask, omask;
+  // general kernel: window sites (ascending) and outer sites with radix and stride
+  uint32_t wsize;  // rows per window
+  int na, ni;
+  int act[kMaxSites], wrad[kMaxSites];
+  int inact[kMaxSites], irad[kMaxSites];
+};
+
+struct WinPlan {
+  std::vector<WinPass> passes;
+  std::vector<int4> plist;        // (pair index in device order, i, j, 0), pass by pass
+  const int4 *d_plist = nullptr;  // device copy (inside the handle's table block)
+  size_t window_rows = 0;
 };
 
 struct DevHam {
@@ -148,6 +180,11 @@ struct DevHam {
   DevTables<double> t64;
   DevTables<float> t32;
   PassPlan plan64, plan32;  // windowed-pass plans for complex128 / complex64
+  WinPlan win64, win32;     // L2-window plans for complex128 / complex64
+  // key of the plans above (recomputed only when it changes)
+  bool plan_valid = false;
+  uint32_t plan_smask = 0;
+  size_t plan_wb = 0, plan_l2b = 0;
   void *block = nullptr;  // device allocation holding every table
   size_t block_bytes = 0;
 };
@@ -157,6 +194,11 @@ bool site_has_singles(const HostHam &hh, int k);
 int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
                        size_t window_rows, PassPlan &plan);
 size_t window_bytes_setting();
+// L2-window plan for windows of at most window_rows rows (spin_half: the
+// kernel's lanes run over row bits 0..7, which every window holds).
+int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
+                    size_t window_rows, bool spin_half, WinPlan &plan);
+size_t l2_window_bytes_setting();
 void sort_pairs(const HostHam &hh, std::vector<int> &perm, int &n_ll, int &n_lh,
                 int mx_off[kMaxSites + 1]);
 
@@ -201,7 +243,7 @@ struct HvLaunch {
   const EpiLanczos *lz;  // nullptr = plain product
   int grid_cap;        // max blocks along x (0 = default)
   int kc;              // columns per lane (0 = auto)
-  int variant;         // 0 auto, 1 direct kernels, 2 windowed passes
+  int variant;         // 0 auto, 1 direct kernels, 2 windowed passes, 3 LDS tile, 4 L2 windows
 };
 
 int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s);

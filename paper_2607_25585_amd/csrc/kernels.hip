@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdlib>
 
+#include "device_reduce.hpp"
 #include "ftlm_internal.hpp"
 
 namespace ftlm {
@@ -59,47 +60,6 @@ __device__ __forceinline__ void mac_real(Acc<R, KC> &a, R c, const Cx<R> *__rest
     a.re[q] = fma(c, xv.re, a.re[q]);
     a.im[q] = fma(c, xv.im, a.im[q]);
   }
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sums NV*KC per-lane values over the block (fixed order) and writes them to
-// part[slot*NV*KC ...].  Then the last block to finish (device-wide) reduces
-// all nslots partials in slot order and calls fin(idx, value) for idx in
-// [0, NV*KC*ncb) where the partial arrays of the ncb column blocks are
-// contiguous.  Returns nothing; fin runs on the last block only.
-template <int NV, int KC>
-__device__ __forceinline__ bool block_partials(const double (&val)[NV][KC], double *part,
-                                               int slot, unsigned *counter, unsigned total) {
-  __shared__ double red[kBlock / 64][NV * KC];
-  __shared__ bool last;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int a = 0; a < NV; a++)
-#pragma unroll
-    for (int q = 0; q < KC; q++) {
-      double s = wave_sum(val[a][q]);
-      if (lane == 0) red[wv][a * KC + q] = s;
-    }
-  __syncthreads();
-  if (threadIdx.x < NV * KC) {
-    double s = 0;
-    for (int w2 = 0; w2 < kBlock / 64; w2++) s += red[w2][threadIdx.x];
-    part[(size_t)slot * NV * KC + threadIdx.x] = s;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == total - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
 }
 
 // ------------------------------------------------------------------ H*v
@@ -166,16 +126,17 @@ __device__ __forceinline__ void hv_finish(const HvParams &P, double (&red)[3][KC
   if (block_partials<3, KC>(red, P.part, slot, P.counter, total)) {
     // columns c = cb*KC + q; partial layout [cb][bx][3][KC]
     const int ncol = gridDim.y * KC;
-    for (int idx = threadIdx.x; idx < 3 * ncol; idx += blockDim.x) {
+    for (int idx = 0; idx < 3 * ncol; idx++) {
       const int c = idx / 3, a = idx % 3;
       const int cb = c / KC, q = c % KC;
-      double s = 0;
-      for (unsigned bx = 0; bx < gridDim.x; bx++)
-        s += P.part[((size_t)(cb * gridDim.x + bx) * 3 + a) * KC + q];
+      double s = block_sum_strided(P.part + ((size_t)cb * gridDim.x * 3 + a) * KC + q, gridDim.x,
+                                   (size_t)3 * KC);
       s *= P.scale[c];
-      if (a == 0) P.alpha_out[c] = s;
-      else if (a == 1) { if (P.ov1) P.yre_out[c] = s; }
-      else { if (P.ov1) P.yim_out[c] = s; }
+      if (threadIdx.x == 0) {
+        if (a == 0) P.alpha_out[c] = s;
+        else if (a == 1) { if (P.ov1) P.yre_out[c] = s; }
+        else { if (P.ov1) P.yim_out[c] = s; }
+      }
     }
     if (threadIdx.x == 0) *P.counter = 0u;
   }
@@ -1033,6 +994,308 @@ __global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, HvP
   hv_finish<KC>(P, red);
 }
 
+// ------------------------------------------------------------------ L2-window passes
+// Scatters the low bits of x to the set bits of mask (ascending).
+__device__ __forceinline__ uint32_t scatter_bits(uint32_t x, uint32_t mask) {
+  uint32_t r = 0;
+  while (mask) {
+    const uint32_t low = mask & (0u - mask);
+    if (x & 1u) r |= low;
+    x >>= 1;
+    mask &= mask - 1u;
+  }
+  return r;
+}
+
+// Work-item walk of one L2-window pass.  With at least 8 windows and a grid that
+// is a multiple of 8, block b runs on XCD b % 8 (workgroups are dispatched to the
+// XCDs round robin); XCD x owns windows x, x+8, ... and its blocks walk the
+// items of those windows in order, so the windows an XCD works on at any time
+// are consecutive in its list and their rows stay in that XCD's L2 (as many
+// windows are in flight as the XCD's blocks cover: nb / nin).  Otherwise the
+// items are walked flat.  body(win, item) is called for every item of the pass.
+template <typename F>
+__device__ __forceinline__ void win_walk(const WinPass &W, F &&body) {
+  const bool xcd = W.nwin >= 8 && (gridDim.x & 7u) == 0;
+  const uint32_t x = xcd ? (blockIdx.x & 7u) : 0u;
+  const uint64_t nwx = xcd ? (uint64_t)((W.nwin - x + 7u) >> 3) : (uint64_t)W.nwin;
+  const uint64_t jn = nwx * W.nin;
+  const uint64_t jstart = xcd ? (blockIdx.x >> 3) : blockIdx.x;
+  const uint64_t jstep = xcd ? (gridDim.x >> 3) : gridDim.x;
+  for (uint64_t j = jstart; j < jn; j += jstep) {
+    const uint32_t wl = (uint32_t)(j / W.nin);
+    const uint32_t item = (uint32_t)(j - (uint64_t)wl * W.nin);
+    body(xcd ? x + 8u * wl : wl, item);
+  }
+}
+
+// Adds the earlier passes' partial sum, then stores the raw partial (not the
+// last pass) or runs the epilogue (last pass).
+template <typename R>
+__device__ __forceinline__ void win_store(const WinPass &W, const HvParams &P, uint32_t row, int c0,
+                                          Acc<R, 1> &acc, const Cx<R> *own, double (&red)[3][1]) {
+  Cx<R> *wp = reinterpret_cast<Cx<R> *>(P.w) + (size_t)row * P.K + c0;
+  if (!W.first) {
+    const Cx<R> o = *wp;
+    acc.re[0] += o.re;
+    acc.im[0] += o.im;
+  }
+  if (W.last) hv_epilogue<R, 1>(P, row, c0, acc, own, red);
+  else *wp = Cx<R>{acc.re[0], acc.im[0]};
+}
+
+// Spin-1/2, N >= 8: one 256-row tile per item (row bits 0..7 over the lanes,
+// bits >= 8 from the window and item indices), terms as in hv_half restricted
+// to the pass.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void hv_half_win(HamGeom g, DevTables<R> tb, WinPass W,
+                                                      const int4 *__restrict__ plist, HvParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = g.n, np = W.np;
+  Cx<R> *s_pc = reinterpret_cast<Cx<R> *>(smem);   // [np][4]
+  Cx<R> *s_hf = s_pc + 4 * np;                     // [n][2]
+  Cx<R> *s_fh = s_hf + 2 * n;                      // [n][2] high part of F (per tile)
+  R *s_hd = reinterpret_cast<R *>(s_fh + 2 * n);   // [n][2]
+  R *s_phi = s_hd + 2 * n;                         // [8]
+  R *s_dt = s_phi + 8;                             // [n]
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.y;
+  const int4 *pl = plist + W.p0;
+  for (int i = t; i < 4 * np; i += kBlock) s_pc[i] = tb.pc_half[4 * pl[i >> 2].x + (i & 3)];
+  for (int i = t; i < 2 * n; i += kBlock) {
+    s_hf[i] = tb.hflip[i];
+    s_hd[i] = tb.hdiag[(i >> 1) * 16 + (i & 1)];
+  }
+  __syncthreads();
+  R dlow = 0;
+  if (W.diag) {
+    for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((t >> k) & 1)];
+    for (int p = 0; p < g.npair; p++) {
+      const int2 ij = tb.pij[p];
+      if (ij.y >= kLowBits) continue;
+      const R mm = (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25);
+      dlow = fma(tb.pzz[p], mm, dlow);
+    }
+  }
+  const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v) + c0;
+  double red[3][1] = {{0.0}, {0.0}, {0.0}};
+  const bool zf = g.has_z && W.smask != 0u;
+
+  win_walk(W, [&](uint32_t win, uint32_t item) {
+    // uniform over the block: keep it (and everything derived) in scalar registers
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(scatter_bits(item, W.emask) | scatter_bits(win, W.omask));
+    __syncthreads();
+    if (t < 2 * n) {
+      if (zf) {
+        const int k = t >> 1, sel = t & 1;
+        R fr = 0, fi = 0;
+        for (int l = kLowBits; l < n; l++) {
+          if (l == k) continue;
+          const R ml = ((hi >> l) & 1) ? R(0.5) : R(-0.5);
+          const Cx<R> c = tb.cz_half[(k * n + l) * 2 + sel];
+          fr = fma(c.re, ml, fr);
+          fi = fma(c.im, ml, fi);
+        }
+        s_fh[t] = Cx<R>{fr, fi};
+      } else {
+        s_fh[t] = Cx<R>{0, 0};
+      }
+    } else if (W.diag && t >= 64 && t < 64 + kLowBits) {
+      const int i = t - 64;
+      R ph = 0;
+      for (int j = kLowBits; j < n; j++) ph = fma(tb.zz[i * n + j], ((hi >> j) & 1) ? R(0.5) : R(-0.5), ph);
+      s_phi[i] = ph;
+    } else if (W.diag && t >= 128 && t < 128 + n - kLowBits) {
+      const int k = kLowBits + (t - 128);
+      const R mk = ((hi >> k) & 1) ? R(0.5) : R(-0.5);
+      R acc = s_hd[2 * k + ((hi >> k) & 1)];
+      for (int j = k + 1; j < n; j++) acc = fma(tb.zz[k * n + j] * mk, ((hi >> j) & 1) ? R(0.5) : R(-0.5), acc);
+      s_dt[k - kLowBits] = acc;
+    }
+    __syncthreads();
+    const uint32_t row = hi | (uint32_t)t;
+    Acc<R, 1> acc;
+    acc_zero(acc);
+    const Cx<R> *own = v + (size_t)row * P.K;
+    if (W.diag) {
+      R diag = dlow;
+      for (int k = 0; k < n - kLowBits; k++) diag += s_dt[k];
+#pragma unroll
+      for (int i = 0; i < kLowBits; i++) diag = fma(((t >> i) & 1) ? R(0.5) : R(-0.5), s_phi[i], diag);
+      mac_real(acc, diag, own);
+    }
+    for (uint32_t sm = W.smask; sm; sm &= sm - 1u) {
+      const int k = __builtin_ctz(sm);
+      const int b = (row >> k) & 1;
+      const Cx<R> a1 = s_hf[2 * k + b], a2 = s_fh[2 * k + b];
+      const Cx<R> a3 = tb.lowf[(k * 2 + b) * 256 + t];
+      const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
+      mac(acc, c, v + (size_t)(row ^ (1u << k)) * P.K);
+    }
+    // pairs inside the lanes' bits: coefficient and partner lane from t
+    const size_t tk = (size_t)t * P.K;
+    const Cx<R> *vt = v + (size_t)hi * P.K;  // this tile (uniform)
+#pragma unroll 4
+    for (int e = 0; e < W.np_ll; e++) {
+      const int4 q = pl[e];
+      const int2 ij = make_int2(q.y, q.z);
+      const int type = (((t >> ij.x) & 1) << 1) | ((t >> ij.y) & 1);
+      mac(acc, s_pc[4 * e + type], vt + (size_t)(t ^ ((1 << ij.x) | (1 << ij.y))) * P.K);
+    }
+    // one lane bit i, one tile bit j: partner tile hi ^ 2^j (uniform), lane t ^ 2^i
+    const int e1 = W.np_ll + W.np_lh;
+#pragma unroll 4
+    for (int e = W.np_ll; e < e1; e++) {
+      const int4 q = pl[e];
+      const int2 ij = make_int2(q.y, q.z);
+      const uint32_t bj = (hi >> ij.y) & 1u;
+      const int type = (((t >> ij.x) & 1) << 1) | (int)bj;
+      const Cx<R> *vp = v + (size_t)(hi ^ (1u << ij.y)) * P.K;
+      mac(acc, s_pc[4 * e + type], vp + (size_t)(t ^ (1 << ij.x)) * P.K);
+    }
+    // both tile bits: the coefficient and the partner tile are uniform
+#pragma unroll 4
+    for (int e = e1; e < np; e++) {
+      const int4 q = pl[e];
+      const int2 ij = make_int2(q.y, q.z);
+      const int type = (int)((((hi >> ij.x) & 1u) << 1) | ((hi >> ij.y) & 1u));
+      const Cx<R> c = s_pc[4 * e + type];  // same address in every lane (broadcast)
+      const Cx<R> *vp = v + (size_t)(hi ^ ((1u << ij.x) | (1u << ij.y))) * P.K;
+      mac(acc, c, vp + tk);
+    }
+    win_store<R>(W, P, row, c0, acc, own, red);
+  });
+  if (W.last) hv_finish<1>(P, red);
+}
+
+// General mixed radix: one 256-row slice of a window per item; the window's
+// rows are enumerated with the window sites' digits (lowest site fastest), the
+// outer digits come from the window index.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb, WinPass W,
+                                                     const int4 *__restrict__ plist, HvParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = g.n;
+  Cx<R> *s_hoff = reinterpret_cast<Cx<R> *>(smem);  // [n][4][16]
+  R *s_hd = reinterpret_cast<R *>(s_hoff + n * 64);  // [n][16]
+  R *s_gp = s_hd + n * 16;
+  R *s_gm = s_gp + n * 16;
+  R *s_m = s_gm + n * 16;
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.y;
+  for (int i = t; i < n * 64; i += kBlock) s_hoff[i] = tb.hoff[i];
+  for (int i = t; i < n * 16; i += kBlock) {
+    s_hd[i] = tb.hdiag[i];
+    s_gp[i] = tb.gp[i];
+    s_gm[i] = tb.gm[i];
+    s_m[i] = tb.mval[i];
+  }
+  __syncthreads();
+  const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v) + c0;
+  const int4 *pl = plist + W.p0;
+  double red[3][1] = {{0.0}, {0.0}, {0.0}};
+
+  win_walk(W, [&](uint32_t win, uint32_t item) {
+    const uint32_t iw = item * kBlock + (uint32_t)t;
+    if (iw >= W.wsize) return;
+    // outer digits from the window index (uniform), window digits from iw
+    uint64_t dlo = 0, dhi = 0;
+    uint32_t row = 0;
+    auto put = [&](int k, uint32_t d) {
+      row += d * g.stride[k];
+      if (k < 16) dlo |= (uint64_t)d << (4 * k);
+      else dhi |= (uint64_t)d << (4 * (k - 16));
+    };
+    {
+      uint32_t rem = win;
+      for (int i = 0; i < W.ni; i++) {
+        const uint32_t r = (uint32_t)W.irad[i], q = rem / r;
+        put(W.inact[i], rem - q * r);
+        rem = q;
+      }
+      rem = iw;
+      for (int a = 0; a < W.na; a++) {
+        const uint32_t r = (uint32_t)W.wrad[a], q = rem / r;
+        put(W.act[a], rem - q * r);
+        rem = q;
+      }
+    }
+    auto digit = [&](int k) -> int {
+      return (int)(((k < 16) ? (dlo >> (4 * k)) : (dhi >> (4 * (k - 16)))) & 15u);
+    };
+    Acc<R, 1> acc;
+    acc_zero(acc);
+    const Cx<R> *own = v + (size_t)row * P.K;
+    if (W.diag) {
+      R diag = 0;
+      for (int k = 0; k < n; k++) diag += s_hd[k * 16 + digit(k)];
+      for (int p = 0; p < g.npair; p++) {
+        const int2 ij = tb.pij[p];
+        diag = fma(tb.pzz[p], s_m[ij.x * 16 + digit(ij.x)] * s_m[ij.y * 16 + digit(ij.y)], diag);
+      }
+      mac_real(acc, diag, own);
+    }
+    for (uint32_t sm = W.smask; sm; sm &= sm - 1u) {
+      const int k = __builtin_ctz(sm);
+      const int dk = digit(k), rk = g.radix[k];
+      const uint32_t st = g.stride[k];
+      R fpr = 0, fpi = 0, fmr = 0, fmi = 0;
+      if (g.has_z) {
+        for (int l = 0; l < n; l++) {
+          if (l == k) continue;
+          const R ml = s_m[l * 16 + digit(l)];
+          const Cx<R> cp = tb.czp[k * n + l], cm = tb.czm[k * n + l];
+          fpr = fma(cp.re, ml, fpr);
+          fpi = fma(cp.im, ml, fpi);
+          fmr = fma(cm.re, ml, fmr);
+          fmi = fma(cm.im, ml, fmi);
+        }
+      }
+#pragma unroll
+      for (int di = 0; di < 4; di++) {
+        const int D = (di < 2) ? di - 2 : di - 1;  // -2,-1,+1,+2
+        const int nd = dk + D;
+        if (nd < 0 || nd >= rk) continue;
+        Cx<R> c = s_hoff[(k * 4 + di) * 16 + dk];
+        if (D == -1) {
+          const R gg = s_gp[k * 16 + dk];
+          c.re = fma(gg, fpr, c.re);
+          c.im = fma(gg, fpi, c.im);
+        } else if (D == 1) {
+          const R gg = s_gm[k * 16 + dk];
+          c.re = fma(gg, fmr, c.re);
+          c.im = fma(gg, fmi, c.im);
+        }
+        mac(acc, c, v + (size_t)(row + (uint32_t)(D * (int)st)) * P.K);
+      }
+    }
+    for (int e = 0; e < W.np; e++) {
+      const int4 pe = pl[e];
+      const int pi_ = pe.y, pj_ = pe.z;
+      const int di = digit(pi_), dj = digit(pj_);
+      const int ri = g.radix[pi_], rj = g.radix[pj_];
+      const uint32_t si = g.stride[pi_], sj = g.stride[pj_];
+      const R gpi = s_gp[pi_ * 16 + di], gmi = s_gm[pi_ * 16 + di];
+      const R gpj = s_gp[pj_ * 16 + dj], gmj = s_gm[pj_ * 16 + dj];
+      const Cx<R> *pc = tb.pc + 4 * pe.x;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const Cx<R> cq = pc[q];
+        if (cq.re == R(0) && cq.im == R(0)) continue;
+        const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;  // '-' ladder on site i / j
+        const bool vi = im_ ? (di <= ri - 2) : (di >= 1);
+        const bool vj = jm ? (dj <= rj - 2) : (dj >= 1);
+        if (!(vi && vj)) continue;
+        const R f = (im_ ? gmi : gpi) * (jm ? gmj : gpj);
+        const uint32_t partner = row + (im_ ? si : (uint32_t)(-(int)si)) + (jm ? sj : (uint32_t)(-(int)sj));
+        mac(acc, Cx<R>{cq.re * f, cq.im * f}, v + (size_t)partner * P.K);
+      }
+    }
+    win_store<R>(W, P, row, c0, acc, own, red);
+  });
+  if (W.last) hv_finish<1>(P, red);
+}
+
 static bool tile_ok(const HamGeom &g, int K) { return g.spin_half && g.n >= kTileBits && K == 1; }
 static thread_local int g_variant = 0;  // variant of the launch in progress (0 = heuristic)
 static bool use_tile(const HamGeom &g, int K) { return tile_ok(g, K) && (g_variant == 0 || g_variant == 3); }
@@ -1246,6 +1509,30 @@ static void launch_hv_r(const DevHam &dh, const DevTables<R> &tb, const HvParams
   }
 }
 
+template <typename R>
+static int launch_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &plan, const HvParams &P,
+                      int cap, hipStream_t s) {
+  const HamGeom &g = dh.geom;
+  if (!plan.d_plist || plan.passes.empty()) return FTLM_EINVAL;
+  for (const WinPass &W : plan.passes) {
+    const uint64_t items = (uint64_t)W.nwin * W.nin;
+    uint32_t gx = (uint32_t)(items < (uint64_t)cap ? items : (uint64_t)cap);
+    if (W.nwin >= 8 && gx >= 8) gx &= ~7u;
+    HvParams Pp = P;
+    if (!W.last) Pp.lanczos = 0;
+    const dim3 grid(gx, P.K);
+    if (g.spin_half) {
+      const size_t sm = sizeof(Cx<R>) * (4 * (size_t)W.np + 4 * g.n) + sizeof(R) * (3 * g.n + 8);
+      if (sm > 64 * 1024) return FTLM_ERANGE;
+      hipLaunchKernelGGL((hv_half_win<R>), grid, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp);
+    } else {
+      const size_t sm = sizeof(Cx<R>) * 64 * (size_t)g.n + sizeof(R) * 64 * g.n;
+      hipLaunchKernelGGL((hv_gen_win<R>), grid, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp);
+    }
+  }
+  return FTLM_OK;
+}
+
 int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
   HvLaunch L = Lin;
   if (L.K >= 1 && L.K <= 64 && (L.precision == 0 || L.precision == 1)) {
@@ -1282,6 +1569,13 @@ int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
     P.alpha_out = L.lz->alpha_out;
     P.yre_out = L.lz->yre_out;
     P.yim_out = L.lz->yim_out;
+  }
+  if (L.variant == 4) {
+    const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
+    int rc = (L.precision == FTLM_C64) ? launch_win<float>(dh, dh.t32, dh.win32, P, cap, s)
+                                       : launch_win<double>(dh, dh.t64, dh.win64, P, cap, s);
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
   }
   if (use_passes(dh.geom, L.K, L.variant)) {
     const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
@@ -1369,11 +1663,10 @@ __global__ __launch_bounds__(kBlock) void start_kernel(StartParams S) {
   const unsigned total = gridDim.x * gridDim.y;
   if (block_partials<1, KC>(red, S.part, blockIdx.y * gridDim.x + blockIdx.x, S.counter, total)) {
     const int ncol = gridDim.y * KC;
-    for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    for (int c = 0; c < ncol; c++) {
       const int cb = c / KC, q = c % KC;
-      double s = 0;
-      for (unsigned bx = 0; bx < gridDim.x; bx++) s += S.part[(size_t)(cb * gridDim.x + bx) * KC + q];
-      S.sx0[c] = s > 0 ? 1.0 / sqrt(s) : 0.0;
+      const double s = block_sum_strided(S.part + (size_t)cb * gridDim.x * KC + q, gridDim.x, KC);
+      if (threadIdx.x == 0) S.sx0[c] = s > 0 ? 1.0 / sqrt(s) : 0.0;
     }
     if (threadIdx.x == 0) *S.counter = 0u;
   }
@@ -1443,7 +1736,31 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs A) {
   }
   Cx<R> *w = reinterpret_cast<Cx<R> *>(A.w);
   const Cx<R> *x = reinterpret_cast<const Cx<R> *>(A.x);
-  for (uint32_t row = blockIdx.x * kBlock + threadIdx.x; row < A.dim; row += gridDim.x * kBlock) {
+  // four rows per thread per trip keep eight loads in flight
+  const uint64_t gstride = (uint64_t)gridDim.x * kBlock;
+  uint64_t row = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (; row + 3 * gstride < A.dim; row += 4 * gstride) {
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      Cx<R> a[4], b[4];
+#pragma unroll
+      for (int u4 = 0; u4 < 4; u4++) {
+        const size_t o = (size_t)(row + (uint64_t)u4 * gstride) * A.K + c0 + q;
+        a[u4] = w[o];
+        b[u4] = x[o];
+      }
+#pragma unroll
+      for (int u4 = 0; u4 < 4; u4++) {
+        const size_t o = (size_t)(row + (uint64_t)u4 * gstride) * A.K + c0 + q;
+        const double ur = (double)a[u4].re - coef[q] * (double)b[u4].re;
+        const double ui = (double)a[u4].im - coef[q] * (double)b[u4].im;
+        const Cx<R> u{(R)ur, (R)ui};
+        w[o] = u;
+        red[0][q] += (double)u.re * (double)u.re + (double)u.im * (double)u.im;
+      }
+    }
+  }
+  for (; row < A.dim; row += gstride) {
 #pragma unroll
     for (int q = 0; q < KC; q++) {
       const size_t o = (size_t)row * A.K + c0 + q;
@@ -1458,10 +1775,10 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs A) {
   const unsigned total = gridDim.x * gridDim.y;
   if (block_partials<1, KC>(red, A.part, blockIdx.y * gridDim.x + blockIdx.x, A.counter, total)) {
     const int ncol = gridDim.y * KC;
-    for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    for (int c = 0; c < ncol; c++) {
       const int cb = c / KC, q = c % KC;
-      double s = 0;
-      for (unsigned bx = 0; bx < gridDim.x; bx++) s += A.part[(size_t)(cb * gridDim.x + bx) * KC + q];
+      const double s = block_sum_strided(A.part + (size_t)cb * gridDim.x * KC + q, gridDim.x, KC);
+      if (threadIdx.x != 0) continue;
       double b = sqrt(s);
       const double al = fabs(A.alpha[c]);
       double sm = A.scale_max[c];
@@ -1538,18 +1855,23 @@ int launch_zero_state(double *scale_max, int *done, int *n_used, unsigned *count
 // thread per column; Z = product of the plane rotations, of which only the rows
 // e_1^T Z (-> Q_1n) and y^T Z (-> sum_a y_a Q_an) are carried along.
 // Scratch layout [4][n_lanczos][n_cols].
+// LDS: the four work arrays of the block's columns live in LDS ([4][nl][blockDim]),
+// else in the global scratch ([4][nl][n_cols]).
+template <bool LDS>
 __global__ void tridiag_kernel(int n_cols, int nl, const int *n_used, int used_stride,
                                int in_stride, const double *alpha, const double *beta, const double *y,
                                double *eps, double *q1, double *qy, int out_stride, int out_col0,
                                double *scratch) {
+  extern __shared__ double tri_sh[];
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= n_cols) return;
   const int n = n_used ? n_used[col * used_stride] : nl;
-  const size_t S = (size_t)n_cols;
-  double *d = scratch + col;
-  double *e = scratch + (size_t)nl * S + col;
-  double *z1 = scratch + 2 * (size_t)nl * S + col;
-  double *zy = scratch + 3 * (size_t)nl * S + col;
+  const size_t S = LDS ? (size_t)blockDim.x : (size_t)n_cols;
+  double *base = LDS ? tri_sh + threadIdx.x : scratch + col;
+  double *d = base;
+  double *e = base + (size_t)nl * S;
+  double *z1 = base + 2 * (size_t)nl * S;
+  double *zy = base + 3 * (size_t)nl * S;
 #define AT(p, i) (p)[(size_t)(i)*S]
   for (int i = 0; i < n; i++) {
     AT(d, i) = alpha[(size_t)i * in_stride + col];
@@ -1617,9 +1939,19 @@ int launch_tridiag(int n_cols, int n_lanczos, const int *n_used, int used_stride
                    const double *alpha, const double *beta, const double *y, double *eps,
                    double *q1, double *qy, int out_stride, int out_col0, double *scratch,
                    hipStream_t s) {
-  hipLaunchKernelGGL(tridiag_kernel, dim3((n_cols + 63) / 64), dim3(64), 0, s, n_cols, n_lanczos,
-                     n_used, used_stride, in_stride, alpha, beta, y, eps, q1, qy, out_stride, out_col0,
-                     scratch);
+  // 64 KB of LDS per block: as many columns as fit (at most 64), else global scratch
+  const int per_col = 32 * n_lanczos;  // bytes of the four work arrays
+  int cpb = per_col > 0 ? 65536 / per_col : 0;
+  if (cpb > 64) cpb = 64;
+  if (cpb >= 1) {
+    hipLaunchKernelGGL(tridiag_kernel<true>, dim3((n_cols + cpb - 1) / cpb), dim3(cpb),
+                       (size_t)cpb * per_col, s, n_cols, n_lanczos, n_used, used_stride, in_stride,
+                       alpha, beta, y, eps, q1, qy, out_stride, out_col0, scratch);
+  } else {
+    hipLaunchKernelGGL(tridiag_kernel<false>, dim3((n_cols + 63) / 64), dim3(64), 0, s, n_cols,
+                       n_lanczos, n_used, used_stride, in_stride, alpha, beta, y, eps, q1, qy,
+                       out_stride, out_col0, scratch);
+  }
   return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
 }
 

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <random>
 #include <set>
 #include <vector>
 
@@ -44,8 +45,10 @@ struct Cover {
 };
 
 // Greedy cover for chunk size c; returns false if some pair cannot be placed.
+// With rng, the seed pair and ties between equal gains are drawn at random
+// (restarts of the greedy search); without it the lowest index wins.
 bool greedy_cover(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj, int c,
-                  uint64_t cap_extra, int max_extra, Cover &out) {
+                  uint64_t cap_extra, int max_extra, Cover &out, std::mt19937 *rng = nullptr) {
   const int n = hh.n, np = (int)pi.size();
   std::vector<char> covered(np, 0);
   int left = np;
@@ -64,13 +67,19 @@ bool greedy_cover(const HostHam &hh, const std::vector<int> &pi, const std::vect
       return true;
     };
     int seed = -1;
-    for (int p = 0; p < np; p++)
-      if (!covered[p]) { seed = p; break; }
+    if (rng && left > 0) {
+      int pick = (int)((*rng)() % (uint32_t)left);
+      for (int p = 0; p < np; p++)
+        if (!covered[p] && pick-- == 0) { seed = p; break; }
+    } else {
+      for (int p = 0; p < np; p++)
+        if (!covered[p]) { seed = p; break; }
+    }
     if (seed >= 0) {
       if (!add(pi[seed]) || !add(pj[seed])) return false;
     }
     while (true) {
-      int best = -1, best_gain = 0;
+      int best = -1, best_gain = 0, n_tie = 0;
       for (int k = c; k < n; k++) {
         if (inS[k] || prod * (uint64_t)hh.radix[k] > cap_extra || (int)S.size() >= max_extra) continue;
         int gain = 0;
@@ -82,6 +91,9 @@ bool greedy_cover(const HostHam &hh, const std::vector<int> &pi, const std::vect
         if (gain > best_gain) {
           best_gain = gain;
           best = k;
+          n_tie = 1;
+        } else if (rng && gain == best_gain && gain > 0 && ((*rng)() % (uint32_t)(++n_tie)) == 0) {
+          best = k;  // reservoir choice among equal gains
         }
       }
       if (best < 0) break;
@@ -253,6 +265,151 @@ int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std:
   return FTLM_OK;
 }
 
+// L2-window plan.  The window budget is an XCD's share of L2 (a few MB), three
+// orders of magnitude above the LDS windows, so a pass covers far more pairs:
+// the lowest sites are always in the window (contiguous runs), the greedy
+// cover picks the others.
+constexpr int kRestarts = 64;  // randomised greedy restarts of the L2-window cover
+
+int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
+                    size_t window_rows, bool spin_half, WinPlan &plan) {
+  plan = WinPlan();
+  plan.window_rows = window_rows;
+  const int n = hh.n, np = (int)pi.size();
+  std::vector<char> need_single(n);
+  for (int k = 0; k < n; k++) need_single[k] = site_has_singles(hh, k);
+  Cover best;
+  int best_c = -1;
+  if (hh.dim <= window_rows) {
+    best_c = n;
+    best.extra.assign(1, {});
+    std::vector<int> all(np);
+    for (int p = 0; p < np; p++) all[p] = p;
+    best.pairs.assign(1, all);
+  } else if (spin_half) {
+    int ebits = 0;
+    while (((uint64_t)1 << (kLowBits + ebits + 1)) <= window_rows) ebits++;
+    if (ebits < 1) return FTLM_ERANGE;
+    if (!greedy_cover(hh, pi, pj, kLowBits, (uint64_t)1 << ebits, ebits, best)) return FTLM_ERANGE;
+    best_c = kLowBits;
+    std::mt19937 rng(12345u);
+    for (int rs = 0; rs < kRestarts; rs++) {
+      Cover cv;
+      if (greedy_cover(hh, pi, pj, kLowBits, (uint64_t)1 << ebits, ebits, cv, &rng) &&
+          cv.extra.size() < best.extra.size())
+        best = cv;
+    }
+  } else {
+    double best_cost = 1e300;
+    std::mt19937 rng(12345u);
+    for (int c = 1; c < n; c++) {
+      const uint64_t chunk = hh.stride[c];
+      if (chunk > window_rows) break;
+      const double bytes = (double)chunk * 16.0;
+      const double eff = bytes >= 128.0 ? 1.0 : bytes / 128.0;
+      for (int rs = 0; rs <= kRestarts; rs++) {
+        Cover cv;
+        if (!greedy_cover(hh, pi, pj, c, window_rows / chunk, n, cv, rs ? &rng : nullptr)) break;
+        const double cost = (double)cv.extra.size() * (32.0 + 16.0 / eff);
+        if (cost < best_cost) {
+          best_cost = cost;
+          best = cv;
+          best_c = c;
+        }
+      }
+    }
+    if (best_c < 0) return FTLM_ERANGE;
+  }
+  const int c = std::min(best_c, n);
+  const uint64_t chunk = c < n ? hh.stride[c] : hh.dim;
+  auto holds = [&](size_t ps, int k) {
+    return k < c || std::find(best.extra[ps].begin(), best.extra[ps].end(), k) != best.extra[ps].end();
+  };
+  // single flips of site k: the first pass whose window holds k (else a new pass)
+  std::vector<int> owner(n, -1);
+  for (int k = 0; k < n; k++) {
+    if (!need_single[k]) continue;
+    for (size_t ps = 0; ps < best.extra.size() && owner[k] < 0; ps++)
+      if (holds(ps, k)) owner[k] = (int)ps;
+    if (owner[k] >= 0) continue;
+    std::vector<int> S{k};
+    uint64_t prod = hh.radix[k];
+    const uint64_t cap = window_rows / chunk;
+    for (int x = c; x < n; x++) {
+      const int max_extra = spin_half ? 31 : n;
+      if (x != k && prod * (uint64_t)hh.radix[x] <= cap && (int)S.size() < max_extra) {
+        S.push_back(x);
+        prod *= hh.radix[x];
+      }
+    }
+    std::sort(S.begin(), S.end());
+    best.extra.push_back(S);
+    best.pairs.push_back({});
+    owner[k] = (int)best.extra.size() - 1;
+  }
+  const int npass = (int)best.extra.size();
+  for (int ps = 0; ps < npass; ps++) {
+    WinPass W;
+    std::memset(&W, 0, sizeof(W));
+    W.first = ps == 0;
+    W.last = ps == npass - 1;
+    W.diag = ps == 0;
+    W.p0 = (int)plan.plist.size();
+    {
+      // order by the number of sites >= 8 (spin-1/2 kernel: lane / tile classes)
+      std::vector<int> prs = best.pairs[ps];
+      auto cls = [&](int p) { return (pi[p] >= kLowBits) + (pj[p] >= kLowBits); };
+      std::stable_sort(prs.begin(), prs.end(), [&](int a, int b) { return cls(a) < cls(b); });
+      for (int p : prs) {
+        plan.plist.push_back(make_int4(p, pi[p], pj[p], 0));
+        if (cls(p) == 0) W.np_ll++;
+        else if (cls(p) == 1) W.np_lh++;
+      }
+    }
+    W.np = (int)plan.plist.size() - W.p0;
+    for (int k = 0; k < n; k++)
+      if (owner[k] == ps) W.smask |= 1u << k;
+    std::vector<char> inw(n, 0);
+    for (int k = 0; k < c; k++) inw[k] = 1;
+    for (int k : best.extra[ps]) inw[k] = 1;
+    uint64_t ws = 1;
+    for (int k = 0; k < n; k++) {
+      if (inw[k]) {
+        W.act[W.na] = k;
+        W.wrad[W.na] = hh.radix[k];
+        W.na++;
+        ws *= (uint64_t)hh.radix[k];
+      } else {
+        W.inact[W.ni] = k;
+        W.irad[W.ni] = hh.radix[k];
+        W.ni++;
+      }
+    }
+    W.wsize = (uint32_t)ws;
+    W.nwin = (uint32_t)(hh.dim / ws);
+    if (spin_half) {
+      for (int k = kLowBits; k < n; k++) {
+        if (inw[k]) W.emask |= 1u << k;
+        else W.omask |= 1u << k;
+      }
+      W.nin = (uint32_t)(ws >> kLowBits);
+    } else {
+      W.nin = (uint32_t)((ws + kBlock - 1) / kBlock);
+    }
+    plan.passes.push_back(W);
+  }
+  if (plan.plist.empty()) plan.plist.push_back(make_int4(0, 0, 0, 0));
+  return FTLM_OK;
+}
+
+size_t l2_window_bytes_setting() {
+  const char *e = std::getenv("FTLM_L2_WINDOW_KB");
+  long kb = e ? std::atol(e) : 1024;
+  if (kb < 4) kb = 4;
+  if (kb > 65536) kb = 65536;
+  return (size_t)kb * 1024;
+}
+
 }  // namespace ftlm
 
 using namespace ftlm;
@@ -305,6 +462,61 @@ extern "C" int ftlm_describe_passes(const ftlm_system *sys, int32_t precision, i
         const int4 e = plan.pairs[D.pp_off + q];
         pair_sites[w++] = D.act[e.y];
         pair_sites[w++] = D.act[e.z];
+      }
+  }
+  return FTLM_OK;
+}
+
+extern "C" int ftlm_describe_windows(const ftlm_system *sys, int32_t precision, int64_t window_bytes,
+                                     int32_t max_pass, int32_t *n_pass, uint32_t *window_rows,
+                                     uint32_t *window_sites, int32_t *n_pairs, uint32_t *single_sites,
+                                     int32_t *pair_sites) {
+  if (!n_pass || (max_pass > 0 && (!window_rows || !window_sites || !n_pairs || !single_sites))) {
+    set_error("NULL argument");
+    return FTLM_EINVAL;
+  }
+  if (precision != FTLM_C128 && precision != FTLM_C64) {
+    set_error("bad precision");
+    return FTLM_EINVAL;
+  }
+  HostHam hh;
+  std::string err;
+  int rc = compile_hamiltonian(sys, hh, err);
+  if (rc) {
+    set_error(err);
+    return rc;
+  }
+  std::vector<int> perm;
+  int n_ll, n_lh, mx_off[kMaxSites + 1];
+  sort_pairs(hh, perm, n_ll, n_lh, mx_off);
+  std::vector<int> spi(hh.npair), spj(hh.npair);
+  for (int q = 0; q < hh.npair; q++) {
+    spi[q] = hh.pi[perm[q]];
+    spj[q] = hh.pj[perm[q]];
+  }
+  const size_t wb = window_bytes > 0 ? (size_t)window_bytes : l2_window_bytes_setting();
+  WinPlan plan;
+  rc = plan_l2_windows(hh, spi, spj, wb / (precision == FTLM_C64 ? 8 : 16),
+                       hh.spin_half && hh.n >= kLowBits, plan);
+  if (rc) {
+    set_error("no L2-window plan fits the window size");
+    return rc;
+  }
+  *n_pass = (int32_t)plan.passes.size();
+  int w = 0;
+  for (int ps = 0; ps < (int)plan.passes.size() && ps < max_pass; ps++) {
+    const WinPass &W = plan.passes[ps];
+    window_rows[ps] = W.wsize;
+    uint32_t m = 0;
+    for (int a = 0; a < W.na; a++) m |= 1u << W.act[a];
+    window_sites[ps] = m;
+    n_pairs[ps] = W.np;
+    single_sites[ps] = W.smask;
+    if (pair_sites)
+      for (int q = 0; q < W.np; q++) {
+        const int4 e = plan.plist[W.p0 + q];
+        pair_sites[w++] = e.y;
+        pair_sites[w++] = e.z;
       }
   }
   return FTLM_OK;

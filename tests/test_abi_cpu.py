@@ -98,3 +98,61 @@ def test_pass_plan_covers_every_pair_once(libftlm, wl, prec):
     es = 16 if prec == 0 else 8
     assert np.all(d["window_rows"].astype(np.int64) * es <= 64 * 1024)
     assert len(d["window_rows"]) <= 16
+
+
+def _interacting_pairs(sysm):
+    n = sysm.n_sites
+    return {(i, j) for i in range(n) for j in range(i + 1, n)
+            if (sysm.J is not None and sysm.J[i, j] != 0) or sysm.pos is not None}
+
+
+def _check_window_plan(sysm, prec, wbytes, max_pass=16):
+    import numpy as np
+    import paper_2607_25585_amd as F
+    d = F.describe_windows(sysm, prec, wbytes)
+    n = sysm.n_sites
+    got = [tuple(sorted(p)) for p in d["pair_sites"].tolist()]
+    assert len(got) == len(set(got)) and set(got) == _interacting_pairs(sysm)
+    # every pair lies inside the window of the pass that applies it
+    k = 0
+    for ps, npp in enumerate(d["n_pairs"].tolist()):
+        for (i, j) in got[k:k + npp]:
+            assert (d["window_sites"][ps] >> i) & 1 and (d["window_sites"][ps] >> j) & 1
+        k += npp
+    # single flips: disjoint over passes, inside the window, same sites as the LDS plan
+    ss = d["single_sites"].astype(np.int64)
+    assert all((int(a) & int(b)) == 0 for x, a in enumerate(ss) for b in ss[x + 1:])
+    assert all((int(s) & ~int(w)) == 0 for s, w in zip(ss, d["window_sites"]))
+    n_single = sum(bin(int(s)).count("1") for s in ss)
+    assert n_single == int(F.describe_passes(sysm, prec)["n_singles"].sum())
+    es = 16 if prec == 0 else 8
+    dim = int(np.prod(np.asarray(sysm.two_s) + 1))
+    wr = d["window_rows"].astype(np.int64)
+    assert np.all((wr * es <= wbytes) | (wr == dim))
+    assert np.all(dim % wr == 0)
+    assert len(d["window_rows"]) <= max_pass and n <= 32
+
+
+@pytest.mark.parametrize("wl", ["cfg1", "cfg2", "cfg2_hb", "cfg4", "cfg4_hb"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_window_plan_covers_every_pair_once(libftlm, wl, prec):
+    """Host logic of the L2-window H*v: pairs applied once, inside their
+    window; single flips placed once; windows within the byte budget."""
+    import ftlm_workloads as W
+    sysm, _ = W.WORKLOADS[wl]()
+    _check_window_plan(sysm, prec, 1 << 20)
+
+
+@pytest.mark.parametrize("seed,n,max_two_s,half", [(0, 6, 3, False), (1, 5, 4, False),
+                                                   (2, 12, 1, True), (3, 16, 1, True),
+                                                   (4, 4, 5, False), (5, 9, 2, False),
+                                                   (6, 14, 1, True), (7, 7, 3, False)])
+def test_window_plan_small_windows(libftlm, seed, n, max_two_s, half):
+    import numpy as np
+    import ftlm_workloads as W
+    rng = np.random.default_rng(1900 + seed)
+    sysm = W.random_small_system(rng, n, max_two_s=max_two_s)
+    if half:
+        sysm.two_s[:] = 1
+    for prec in (0, 1):
+        _check_window_plan(sysm, prec, 16 * 1024, max_pass=64)

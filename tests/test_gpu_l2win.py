@@ -1,0 +1,94 @@
+"""GPU parity of the L2-window H*v passes (XCD-aware window walk) against the CPU
+oracle: small systems with tiny windows, so that many passes, both window walks
+(per-XCD and flat) and ragged windows are exercised; a Lanczos run through the
+multi-pass epilogue; sampled rows at the full cfg2 and cfg4 sizes."""
+import numpy as np
+import pytest
+
+import ftlm_workloads as W
+from oracle import ftlm as of
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _force_l2win(monkeypatch):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    monkeypatch.setenv("FTLM_HV_VARIANT", "4")
+    monkeypatch.setenv("FTLM_L2_WINDOW_KB", "16")
+
+
+def F():
+    import paper_2607_25585_amd as F
+    return F
+
+
+def rel_max(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("seed,n,max_two_s,half", [(0, 6, 3, False), (1, 5, 4, False),
+                                                   (2, 12, 1, True), (3, 16, 1, True),
+                                                   (4, 4, 5, False), (5, 9, 2, False),
+                                                   (6, 14, 1, True), (7, 7, 3, False)])
+def test_l2win_hv_matches_oracle(seed, n, max_two_s, half):
+    rng = np.random.default_rng(1900 + seed)
+    sysm = W.random_small_system(rng, n, max_two_s=max_two_s)
+    if half:
+        sysm.two_s[:] = 1
+    print("case l2win seed", seed, "two_s", sysm.two_s.tolist(), flush=True)
+    ham = F().Hamiltonian(sysm)
+    v = rng.standard_normal(ham.dim) + 1j * rng.standard_normal(ham.dim)
+    oh = of.Ham(sysm)
+    ref = oh.apply(v)
+    w = ham.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+    assert rel_max(w, ref) < 1e-12
+    w32 = ham.apply(torch.as_tensor(v, device="cuda", dtype=torch.complex64)).cpu().numpy()
+    ref32 = oh.apply(v.astype(np.complex64).astype(np.complex128))
+    assert rel_max(w32, ref32) < 2e-5
+
+
+@pytest.mark.parametrize("n,half", [(6, False), (14, True)])
+def test_l2win_run_matches_oracle(n, half):
+    rng = np.random.default_rng(177 + n)
+    sysm = W.random_small_system(rng, n, max_two_s=1 if half else 2)
+    if half:
+        sysm.two_s[:] = 1
+    T = W.t_grid(30)
+    ham = F().Hamiltonian(sysm)
+    got = F().run(ham, 3, 40, T, seed=4, columns=1)
+    ref = of.ftlm(sysm, 3, 40, T, seed=4)[0]
+    for key in ("lnZ", "E", "C", "M"):
+        r = np.asarray(ref[key])
+        err = np.max(np.abs(got[key][0] - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max()))
+        assert err < 1e-8, key
+
+
+def _sampled(sysm, prec, tol, n_rows=2000):
+    ham = F().Hamiltonian(sysm)
+    dim = ham.dim
+    print("case l2win full-size", sysm.name, "dim", dim, "prec", prec, flush=True)
+    v = F().gaussian_vectors(4243, 0, 0, 0, 1, dim).reshape(-1)
+    if prec == F().FTLM_C64:
+        v = v.to(torch.complex64)
+    w = ham.apply(v)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([rng.integers(0, dim, n_rows), [0, dim - 1, dim // 3]]))
+    ri = torch.as_tensor(rows, device="cuda")
+    w_s = w[ri].cpu().numpy().astype(np.complex128)
+    vc = v.cpu().numpy().astype(np.complex128)
+    ref = of.Ham(sysm).apply_rows(vc, rows)
+    assert rel_max(w_s, ref) < tol
+    del v, w
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("wl", ["cfg2", "cfg4", "cfg4_hb"])
+def test_l2win_full_size_sampled_rows(wl, monkeypatch):
+    monkeypatch.setenv("FTLM_L2_WINDOW_KB", "1024")
+    sysm, _ = W.WORKLOADS[wl]()
+    _sampled(sysm, F().FTLM_C128, 1e-12)
+    _sampled(sysm, F().FTLM_C64, 2e-5)

@@ -420,3 +420,145 @@ def test_adam_first_step_closed_form():
     g = [np.array([0.3, -2.0, 1e-3])]
     p, m, v = mlp.adam_step([np.zeros(3)], g, [np.zeros(3)], [np.zeros(3)], 1, lr=0.01)
     assert np.allclose(p[0], -0.01 * g[0] / (np.abs(g[0]) + 1e-8), rtol=1e-12)
+
+
+# ------------------------------------------------ next row: sFTLM, time reversal
+def test_oracle_time_reverse_maps_h_b_to_h_minus_b():
+    """The oracle's Theta (used for the random-vector pairs) satisfies
+    Theta H(B) Theta^-1 = H(-B) on the C oracle's H (brute-force products) and
+    Theta^2 = (-1)^{2 S_tot} (Kramers)."""
+    rng = np.random.default_rng(31)
+    sysm = W.random_small_system(rng, 4, max_two_s=3)
+    ham_p, ham_m = of.Ham(sysm), of.Ham(sysm, -np.asarray(sysm.B))
+    x = rng.standard_normal(ham_p.dim) + 1j * rng.standard_normal(ham_p.dim)
+    lhs = of.time_reverse(sysm.two_s, ham_p.apply(x))
+    rhs = ham_m.apply(of.time_reverse(sysm.two_s, x))
+    assert np.max(np.abs(lhs - rhs)) < 1e-12 * np.max(np.abs(lhs))
+    tt = of.time_reverse(sysm.two_s, of.time_reverse(sysm.two_s, x))
+    sign = (-1.0) ** int(np.sum(sysm.two_s))
+    assert np.max(np.abs(tt - sign * x)) < 1e-15 * np.max(np.abs(x))
+
+
+def test_sftlm_invariant_subspace_is_exact():
+    """dim <= N_L with re-orthogonalisation: the double sum of Eq. (E-2-H)
+    equals <r|exp(-H/2T) O exp(-H/2T)|r> from the dense matrices, so sFTLM over
+    the pairs equals the dense ratio of Eq. (E-2-G)."""
+    rng = np.random.default_rng(12)
+    sysm = W.random_small_system(rng, 3, max_two_s=2)
+    H = dense.hamiltonian_dense(sysm)
+    O = dense.moment_operator(sysm).toarray()
+    dim = H.shape[0]
+    T = np.array([0.4, 3.0, 30.0])
+    R = 4
+    res = of.sftlm(sysm, R, dim + 3, T, seed=5, reorth=True)[0]
+    vs = []
+    for p in range(R // 2):
+        r0 = of.gaussian_vector(5, p, 0, 0, dim)
+        for rv in (r0, of.time_reverse(sysm.two_s, r0)):
+            vs.append(rv / np.linalg.norm(rv))
+    ev, U = np.linalg.eigh(H)
+    for k, t in enumerate(T):
+        half = (U * np.exp(-(ev - ev[0]) / (2 * t))) @ U.conj().T
+        num = sum(np.vdot(half @ v, O @ (half @ v)).real for v in vs)
+        den = sum(np.vdot(half @ v, half @ v).real for v in vs)
+        assert abs(res["M"][k] - num / den) < 1e-10 * max(1.0, abs(num / den))
+        z = den * dim / R * np.exp(-ev[0] / t)
+        assert abs(res["lnZ"][k] - np.log(z)) < 1e-10
+
+
+def test_sftlm_pairs_zero_field_and_field_reversal():
+    """With time-reversed pairs, M(B=0) vanishes and the moment along the field
+    is the same for B and -B, each to rounding (H(-B) = Theta H(B) Theta^-1, and
+    Theta maps the vector set onto itself); a single unpaired vector does not
+    share either property."""
+    rng = np.random.default_rng(8)
+    sysm = W.random_small_system(rng, 4, max_two_s=3)
+    T = W.t_grid(12)
+    zero = of.sftlm(sysm, 4, 30, T, seed=2, fields=[[0.0, 0.0, 0.0]])[0]
+    assert np.max(np.abs(zero["M"])) < 1e-10
+    B = np.asarray(sysm.B, float)
+    pm = [of.sftlm(sysm, 4, 30, T, seed=2, fields=[b])[0] for b in (B, -B)]  # same vectors
+    assert np.max(np.abs(pm[0]["M"] - pm[1]["M"])) < 1e-9 * np.max(np.abs(pm[0]["M"]))
+    assert np.max(np.abs(pm[0]["C"] - pm[1]["C"])) < 1e-9 * np.max(np.abs(pm[0]["C"]))
+    plain = of.ftlm(sysm, 1, 30, T, seed=2, fields=[[0.0, 0.0, 0.0]])[0]
+    assert np.max(np.abs(plain["M"])) > 1e-6
+
+
+def test_dodecahedron_powder_grid():
+    """The 10 directions (one per antipodal vertex pair of a regular
+    dodecahedron, Sec. 3.3): the 20 vertices each have exactly 3 nearest
+    neighbours at one distance (regular solid), and the directions average any
+    quadratic form to its isotropic value tr(A)/3 (powder average exact for
+    rank-2 responses)."""
+    d = W.dodecahedron_directions()
+    assert d.shape == (10, 3)
+    v = np.concatenate([d, -d])
+    dist = np.linalg.norm(v[:, None] - v[None], axis=2)
+    np.fill_diagonal(dist, np.inf)
+    dmin = dist.min()
+    assert np.all(np.sum(np.abs(dist - dmin) < 1e-12, axis=1) == 3)
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((3, 3))
+    A = A + A.T
+    avg = np.mean([x @ A @ x for x in d])
+    assert abs(avg - np.trace(A) / 3) < 1e-14
+
+
+# ------------------------------------------------------- next row: Chebyshev (KPM)
+from oracle import kpm as okpm  # noqa: E402
+
+
+def test_chebyshev_expansion_coefficients():
+    """sum_n c_n(x) T_n(t) = exp(-x (1 + t)) on [-1, 1] (generating function of
+    the modified Bessel functions); pins the sign and the factor 2."""
+    for x in (0.3, 4.0, 25.0):
+        c = okpm.expansion_coefficients(x, 200)
+        for t in (-1.0, -0.3, 0.2, 0.9, 1.0):
+            tn = np.cos(np.arange(201) * np.arccos(t))
+            assert abs(c @ tn - math.exp(-x * (1 + t))) < 1e-13 * max(1.0, math.exp(-x * (1 + t)))
+
+
+def test_chebyshev_moments_match_spectral_definition():
+    """mu_n = sum_k |<k|r>|^2 T_n((E_k - b)/a) from the dense eigenpairs."""
+    rng = np.random.default_rng(40)
+    sysm = W.random_small_system(rng, 4, max_two_s=2)
+    H = dense.hamiltonian_dense(sysm)
+    O = dense.moment_operator(sysm).toarray()
+    ev, U = np.linalg.eigh(H)
+    lo, hi = ev[0] - 0.1, ev[-1] + 0.1
+    a, b = 0.5 * (hi - lo), 0.5 * (hi + lo)
+    ham, mom = of.Ham(sysm), of.Moment(sysm, of.field_direction(sysm.B))
+    r = of.gaussian_vector(9, 0, 0, 0, ham.dim)
+    mu, nu = okpm.chebyshev_moments(ham, mom, r, a, b, 30)
+    rh = r / np.linalg.norm(r)
+    w = np.abs(U.conj().T @ rh) ** 2
+    th = np.arccos((ev - b) / a)
+    for n in range(33):
+        assert abs(mu[n] - w @ np.cos(n * th)) < 1e-12
+        Tn = (U * np.cos(n * th)) @ U.conj().T
+        assert abs(nu[n] - np.vdot(O @ rh, Tn @ rh).real) < 1e-11
+
+
+def test_kpm_per_vector_traces_are_exact():
+    """With enough moments the expansion reproduces <r|exp(-H/T)|r>,
+    <r|H exp(-H/T)|r>, <r|H^2 exp(-H/T)|r> and Re<r|O exp(-H/T)|r> from the
+    dense matrices, i.e. ln Z, E, C and M of R = 1 to rounding."""
+    rng = np.random.default_rng(41)
+    sysm = W.random_small_system(rng, 4, max_two_s=2)
+    H = dense.hamiltonian_dense(sysm)
+    O = dense.moment_operator(sysm).toarray()
+    dim = H.shape[0]
+    T = np.array([1.5, 6.0, 40.0])
+    res = okpm.kpm(sysm, 1, 400, T, seed=2, n_bound=dim + 5)[0]
+    r = of.gaussian_vector(2, 0, 0, 0, dim)
+    r = r / np.linalg.norm(r)
+    ev, U = np.linalg.eigh(H)
+    for k, t in enumerate(T):
+        E = (U * np.exp(-(ev - ev[0]) / t)) @ U.conj().T
+        z = np.vdot(r, E @ r).real
+        e1 = np.vdot(r, H @ E @ r).real / z
+        e2 = np.vdot(r, H @ H @ E @ r).real / z
+        assert abs(res["lnZ"][k] - (np.log(dim * z) - ev[0] / t)) < 1e-10
+        assert abs(res["E"][k] - e1) < 1e-9 * max(1, abs(e1))
+        assert abs(res["C"][k] - (e2 - e1 * e1) / t ** 2) < 1e-8 * max(1, abs(e2 / t ** 2))
+        assert abs(res["M"][k] - np.vdot(r, O @ E @ r).real / z) < 1e-9
