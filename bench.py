@@ -168,12 +168,72 @@ def hv_only(args, sysm, spec, ham, prec, K):
                 "nnz_per_row": round(nnz, 3)}}
 
 
+def surrogate_report(n_train, n_test, train_s):
+    """The learned surrogate on the 8-spin s=3/2 ring data: FTLM training curves
+    (batched FP32 path, R=20, N_L=100, 200 temperatures), an ensemble of two MLPs
+    trained by the library's BF16/FP32 kernels, held-out errors against plain FP64
+    FTLM curves of the same parameters, and curves/s of both."""
+    import numpy as np
+    import torch
+
+    import ftlm_workloads as W
+    from paper_2607_25585_amd import surrogate as S
+    T = W.t_grid()
+    spec = W.cfg5_runspec()
+    ptrain = W.cfg5_params(n_train, seed=5000)
+    ptest = W.cfg5_params(n_test, seed=5001)
+    t0 = time.perf_counter()
+    lz, mm, cc = S.generate_dataset(ptrain, T, spec.R, spec.n_lanczos, seed=spec.seed, chunk=256)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    print("surrogate: %d training curves in %.1f s" % (n_train, t_gen), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    lzt, mmt, cct = S.generate_dataset(ptest, T, spec.R, spec.n_lanczos, seed=spec.seed + 999, chunk=256,
+                                       precision=0)
+    torch.cuda.synchronize()
+    t_ftlm64 = time.perf_counter() - t0
+    x = S.encode_inputs(ptrain, T)
+    y = S.encode_targets(lz, mm, cc, T)
+    models, losses = [], []
+    t0 = time.perf_counter()
+    for seed in (0, 1):
+        m = S.MLP(seed=seed)
+        losses.append(S.train(m, x, y, epochs=400, batch=4096, lr=2e-3, seed=seed, time_budget_s=train_s)[-1])
+        models.append(m)
+    t_train = time.perf_counter() - t0
+    print("surrogate: trained in %.1f s" % t_train, file=sys.stderr, flush=True)
+    ens = S.Surrogate(models, disagreement=0.05)
+    plz, pm, pc, spread = ens.predict(ptest, T)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ens.predict(ptest, T)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / reps
+
+    def rel(a, b):
+        floor = 1e-3 * np.max(np.abs(b), axis=1, keepdims=True)
+        return np.max(np.abs(a - b) / np.maximum(np.abs(b), np.maximum(floor, 1e-12)), axis=1)
+    eC, eM = rel(pc, cct), np.max(np.abs(pm - mmt), axis=1)
+    eZ = np.max(np.abs(plz - lzt), axis=1)
+    q = lambda a: {"median": float(np.median(a)), "p90": float(np.quantile(a, 0.9)), "max": float(np.max(a))}  # noqa: E731
+    return {"train_sets": n_train, "test_sets": n_test, "T_points": len(T),
+            "ftlm_fp32_batched_curves_per_s": round(n_train / t_gen, 3),
+            "ftlm_fp64_batched_curves_per_s": round(n_test / t_ftlm64, 3),
+            "surrogate_curves_per_s": round(n_test / t_sur, 1),
+            "speedup_vs_fp64_ftlm": round((n_test / t_sur) / (n_test / t_ftlm64), 1),
+            "train_s": round(t_train, 1), "final_losses": [float(v) for v in losses],
+            "heldout_C_relerr_A12": q(eC), "heldout_M_abserr_muB": q(eM), "heldout_lnZ_abserr": q(eZ),
+            "gate_accepts": float(np.mean(spread <= ens.disagreement))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg2_hb", "cfg4", "cfg4_hb"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg2_hb", "cfg4", "cfg4_hb", "ring6", "mn9"])
     ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
     ap.add_argument("--columns", type=int, default=0,
                     help="random vectors iterated together (0 = library default)")
@@ -185,6 +245,11 @@ def main():
     ap.add_argument("--hv-only", action="store_true",
                     help="time the H*v product alone (GB/s line) instead of whole curves")
     ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--surrogate", action="store_true",
+                    help="surrogate report on the s=3/2 ring data instead of the FTLM curve bench")
+    ap.add_argument("--surrogate-train", type=int, default=2000)
+    ap.add_argument("--surrogate-test", type=int, default=200)
+    ap.add_argument("--surrogate-train-s", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -198,6 +263,12 @@ def main():
     import paper_2607_25585_amd as F
 
     torch.cuda.set_device(0)
+    if args.surrogate:
+        out = {"metric": "surrogate curves/s vs FTLM at held-out accuracy", "n_gpus": 1, "data": "synthetic",
+               "config": {"workload": "8-spin s=3/2 ring, MLP 7-256-256-256-3 (bf16 weights, fp32 accumulate)"}}
+        out.update(surrogate_report(args.surrogate_train, args.surrogate_test, args.surrogate_train_s))
+        print(json.dumps(out), flush=True)
+        return
     sysm, spec = W.WORKLOADS[args.workload]()
     prec = F.FTLM_C128 if args.precision == "c128" else F.FTLM_C64
     ham = F.Hamiltonian(sysm)

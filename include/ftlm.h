@@ -100,8 +100,9 @@ int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, con
 /* Autotuner: times every admissible H*v configuration for (precision, n_cols) on
  * the caller's device buffers v, w ([dim][n_cols], as ftlm_apply) -- variants
  * 1 = direct gather (columns per lane 1, 2, 4, 8), 2 = windowed LDS passes,
- * 3 = LDS tile (spin 1/2, N >= 11), 4 = L2-window passes (one column), each at
- * 512, 1024, 2048 and 4096 blocks (variant 4: at most 2048) --
+ * 3 = LDS tile (spin 1/2, N >= 11), 4 = L2-window passes (one column), 5 = LDS
+ * tile walked over L2 windows (spin 1/2, N >= 12), each at 512, 1024, 2048 and
+ * 4096 blocks (variants 4, 5: at most 2048) --
  * with HIP events on the stream (blocking), and stores the fastest in the handle
  * for later ftlm_apply / ftlm_run launches of the same shape.  Outputs (may be
  * NULL): the chosen variant, grid size, columns per lane and its mean time. */

@@ -208,7 +208,9 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   uint32_t smask = 0;
   for (int k = 0; k < n; k++)
     if (site_has_singles(hh, k)) smask |= 1u << k;
-  const bool replan = !dh.plan_valid || dh.plan_smask != smask || dh.plan_wb != wb || dh.plan_l2b != l2b;
+  const size_t tbytes = tile_window_bytes_setting();
+  const bool replan = !dh.plan_valid || dh.plan_smask != smask || dh.plan_wb != wb || dh.plan_l2b != l2b ||
+                      dh.plan_tb != tbytes;
   if (replan) {
     int prc = plan_passes_sorted(hh, spi, spj, wb / 16, dh.plan64);
     if (!prc) prc = plan_passes_sorted(hh, spi, spj, wb / 8, dh.plan32);
@@ -217,16 +219,26 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
       return prc;
     }
     const bool half = hh.spin_half && n >= kLowBits;
-    prc = plan_l2_windows(hh, spi, spj, l2b / 16, half, dh.win64);
-    if (!prc) prc = plan_l2_windows(hh, spi, spj, l2b / 8, half, dh.win32);
+    prc = plan_l2_windows(hh, spi, spj, l2b / 16, half ? kLowBits : 0, dh.win64);
+    if (!prc) prc = plan_l2_windows(hh, spi, spj, l2b / 8, half ? kLowBits : 0, dh.win32);
     if (prc) {
       err = "no L2-window plan fits the window size";
       return prc;
+    }
+    dh.tw64 = WinPlan();
+    dh.tw32 = WinPlan();
+    if (hh.spin_half && n > kTileBits) {
+      if (plan_l2_windows(hh, spi, spj, tbytes / 16, kTileBits, dh.tw64) ||
+          plan_l2_windows(hh, spi, spj, tbytes / 8, kTileBits, dh.tw32)) {
+        dh.tw64 = WinPlan();
+        dh.tw32 = WinPlan();
+      }
     }
     dh.plan_valid = true;
     dh.plan_smask = smask;
     dh.plan_wb = wb;
     dh.plan_l2b = l2b;
+    dh.plan_tb = tbytes;
   }
   dh.plan64.window_bytes = wb;
   dh.plan32.window_bytes = wb;
@@ -241,6 +253,8 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   const size_t off_p32 = b.add(dh.plan32.pairs.data(), dh.plan32.pairs.size() * sizeof(int4));
   const size_t off_w64 = b.add(dh.win64.plist.data(), dh.win64.plist.size() * sizeof(int4));
   const size_t off_w32 = b.add(dh.win32.plist.data(), dh.win32.plist.size() * sizeof(int4));
+  const size_t off_t64 = b.add(dh.tw64.plist.data(), dh.tw64.plist.size() * sizeof(int4));
+  const size_t off_t32 = b.add(dh.tw32.plist.data(), dh.tw32.plist.size() * sizeof(int4));
   const size_t bytes = (b.bytes.size() + 255) & ~size_t(255);
   if (dh.block && dh.block_bytes != bytes) {
     (void)hipFree(dh.block);
@@ -265,6 +279,8 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   dh.plan32.d_pairs = reinterpret_cast<const int4 *>(base + off_p32);
   dh.win64.d_plist = reinterpret_cast<const int4 *>(base + off_w64);
   dh.win32.d_plist = reinterpret_cast<const int4 *>(base + off_w32);
+  dh.tw64.d_plist = dh.tw64.plist.empty() ? nullptr : reinterpret_cast<const int4 *>(base + off_t64);
+  dh.tw32.d_plist = dh.tw32.plist.empty() ? nullptr : reinterpret_cast<const int4 *>(base + off_t32);
   HamGeom &g = dh.geom;
   std::memset(&g, 0, sizeof(g));
   g.n = n;

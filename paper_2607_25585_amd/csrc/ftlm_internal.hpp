@@ -160,6 +160,7 @@ struct WinPass {
   // spin-1/2 kernel: row bits 0..7 run over the lanes; emask / omask are the
   // row bits >= 8 that vary inside a window / index the windows
   uint32_t emask, omask;
+  uint32_t xmask;  // tile kernel: outer sites whose partner tile this pass stages
   // general kernel: window sites (ascending) and outer sites with radix and stride
   uint32_t wsize;  // rows per window
   int na, ni;
@@ -181,10 +182,11 @@ struct DevHam {
   DevTables<float> t32;
   PassPlan plan64, plan32;  // windowed-pass plans for complex128 / complex64
   WinPlan win64, win32;     // L2-window plans for complex128 / complex64
+  WinPlan tw64, tw32;       // L2-window plans of the LDS tile kernel (spin 1/2, N >= 12)
   // key of the plans above (recomputed only when it changes)
   bool plan_valid = false;
   uint32_t plan_smask = 0;
-  size_t plan_wb = 0, plan_l2b = 0;
+  size_t plan_wb = 0, plan_l2b = 0, plan_tb = 0;
   void *block = nullptr;  // device allocation holding every table
   size_t block_bytes = 0;
 };
@@ -196,9 +198,12 @@ int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std:
 size_t window_bytes_setting();
 // L2-window plan for windows of at most window_rows rows (spin_half: the
 // kernel's lanes run over row bits 0..7, which every window holds).
+// lane_bits: 0 = general kernel; spin-1/2 kernels: the low row bits that every
+// window holds (8 for the lane kernel, 11 for the LDS tile kernel).
 int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
-                    size_t window_rows, bool spin_half, WinPlan &plan);
+                    size_t window_rows, int lane_bits, WinPlan &plan);
 size_t l2_window_bytes_setting();
+size_t tile_window_bytes_setting();
 void sort_pairs(const HostHam &hh, std::vector<int> &perm, int &n_ll, int &n_lh,
                 int mx_off[kMaxSites + 1]);
 

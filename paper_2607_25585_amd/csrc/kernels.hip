@@ -1168,6 +1168,203 @@ __global__ __launch_bounds__(kBlock) void hv_half_win(HamGeom g, DevTables<R> tb
   if (W.last) hv_finish<1>(P, red);
 }
 
+// Spin-1/2, N >= 12: the LDS tile kernel (2048-row tiles, 8 rows per thread)
+// walked window by window over the tile bits >= 11, terms restricted to the
+// pass: pairs inside the tile (first pass), then for every outer site a of
+// xmask the partner tile (tile with bit a flipped) staged once for the single
+// flip of a and the mixed pairs (i < 11, a), then pairs of two outer sites read
+// straight from global memory (L2-resident: both sites lie in the window).
+template <typename R>
+__global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R> tb, WinPass W,
+                                                         const int4 *__restrict__ plist, HvParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int Q = kRowsPerThread;
+  const int n = g.n, n_in = W.np_ll, e_out = W.np_ll + W.np_lh, np = W.np;
+  Cx<R> *own = reinterpret_cast<Cx<R> *>(smem);   // [2048]
+  Cx<R> *part = own + kTileRows;                  // [2048]
+  Cx<R> *s_pc = part + kTileRows;                 // [n_in][4]
+  Cx<R> *s_fmh = s_pc + 4 * n_in;                 // [n][2][Q]
+  Cx<R> *s_hf = s_fmh + 2 * Q * n;                // [n][2]
+  R *s_hd = reinterpret_cast<R *>(s_hf + 2 * n);  // [n][2]
+  R *s_dmh = s_hd + 2 * n;                        // [Q]
+  R *s_phi = s_dmh + Q;                           // [8][Q]
+  R *s_term = s_phi + 8 * Q;                      // [32][Q]
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.y;
+  const int K = P.K;
+  const int4 *pl = plist + W.p0;
+  for (int i = t; i < 4 * n_in; i += kBlock) s_pc[i] = tb.pc_half[4 * pl[i >> 2].x + (i & 3)];
+  for (int i = t; i < 2 * n; i += kBlock) {
+    s_hf[i] = tb.hflip[i];
+    s_hd[i] = tb.hdiag[(i >> 1) * 16 + (i & 1)];
+  }
+  __syncthreads();
+  R dlow = 0;
+  if (W.diag) {
+    for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((t >> k) & 1)];
+    for (int p = 0; p < g.npair; p++) {
+      const int2 ij = tb.pij[p];
+      if (ij.y >= kLowBits) continue;
+      dlow = fma(tb.pzz[p], (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25), dlow);
+    }
+  }
+  R mlane[kLowBits];
+#pragma unroll
+  for (int i = 0; i < kLowBits; i++) mlane[i] = ((t >> i) & 1) ? R(0.5) : R(-0.5);
+  const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v);
+  const bool zf = W.smask != 0u;
+  double red[3][1] = {{0.0}, {0.0}, {0.0}};
+
+  win_walk(W, [&](uint32_t win, uint32_t item) {
+    const uint32_t base = __builtin_amdgcn_readfirstlane(scatter_bits(item, W.emask) | scatter_bits(win, W.omask));
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; q++) own[q * kBlock + t] = v[(size_t)(base + q * kBlock + t) * K + c0];
+    // per-tile uniform parts: rows of slot q have bits 8..10 = q and bits >= 11 = base
+    if (zf)
+      for (int e = t; e < 2 * Q * n; e += kBlock) {
+        const int k = e / (2 * Q), sel = (e / Q) & 1, q = e % Q;
+        const uint32_t rb = base | ((uint32_t)q << kLowBits);
+        R fr = 0, fi = 0;
+        for (int l = kLowBits; l < n; l++) {
+          if (l == k) continue;
+          const R ml = ((rb >> l) & 1) ? R(0.5) : R(-0.5);
+          const Cx<R> c = tb.cz_half[(k * n + l) * 2 + sel];
+          fr = fma(c.re, ml, fr);
+          fi = fma(c.im, ml, fi);
+        }
+        s_fmh[e] = Cx<R>{fr, fi};
+      }
+    if (W.diag) {
+      if (t < 24 * Q) {
+        const int k = kLowBits + t / Q, q = t % Q;
+        if (k < n) {
+          const uint32_t rb = base | ((uint32_t)q << kLowBits);
+          const R mk = ((rb >> k) & 1) ? R(0.5) : R(-0.5);
+          R acc = s_hd[2 * k + ((rb >> k) & 1)];
+          for (int j = k + 1; j < n; j++) acc = fma(tb.zz[k * n + j] * mk, ((rb >> j) & 1) ? R(0.5) : R(-0.5), acc);
+          s_term[(k - kLowBits) * Q + q] = acc;
+        }
+      } else if (t < 24 * Q + 8 * Q) {
+        const int i = (t - 24 * Q) / Q, q = (t - 24 * Q) % Q;
+        const uint32_t rb = base | ((uint32_t)q << kLowBits);
+        R ph = 0;
+        for (int j = kLowBits; j < n; j++) ph = fma(tb.zz[i * n + j], ((rb >> j) & 1) ? R(0.5) : R(-0.5), ph);
+        s_phi[i * Q + q] = ph;
+      }
+    }
+    __syncthreads();
+    if (W.diag && t < Q) {
+      R d = 0;
+      for (int k = kLowBits; k < n; k++) d += s_term[(k - kLowBits) * Q + t];
+      s_dmh[t] = d;
+    }
+    __syncthreads();
+
+    Cx<R> acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      acc[q] = Cx<R>{0, 0};
+      if (W.diag) {
+        R dg = dlow + s_dmh[q];
+#pragma unroll
+        for (int i = 0; i < kLowBits; i++) dg = fma(mlane[i], s_phi[i * Q + q], dg);
+        const Cx<R> x = own[q * kBlock + t];
+        acc[q] = Cx<R>{dg * x.re, dg * x.im};
+      }
+    }
+    // single flips of tile sites
+#pragma unroll 1
+    for (uint32_t sm = W.smask & ((1u << kTileBits) - 1u); sm; sm &= sm - 1u) {
+      const int k = __builtin_ctz(sm);
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const int r = q * kBlock + t;
+        const int b = (r >> k) & 1;
+        const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + t], a3 = s_fmh[(k * 2 + b) * Q + q];
+        const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
+        const Cx<R> x = own[r ^ (1 << k)];
+        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+      }
+    }
+    // pairs inside the tile
+#pragma unroll 1
+    for (int e = 0; e < n_in; e++) {
+      const int4 ij = pl[e];
+      const int mask = (1 << ij.y) | (1 << ij.z);
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const int r = q * kBlock + t;
+        const int type = (((r >> ij.y) & 1) << 1) | ((r >> ij.z) & 1);
+        const Cx<R> c = s_pc[4 * e + type];
+        const Cx<R> x = own[r ^ mask];
+        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+      }
+    }
+    // outer sites with work in this pass: partner tile staged once
+    int e = n_in;
+#pragma unroll 1
+    for (uint32_t xm = W.xmask; xm; xm &= xm - 1u) {
+      const int a = __builtin_ctz(xm);
+      __syncthreads();
+      const uint32_t pb = base ^ (1u << a);
+#pragma unroll
+      for (int q = 0; q < Q; q++) part[q * kBlock + t] = v[(size_t)(pb + q * kBlock + t) * K + c0];
+      __syncthreads();
+      const int ba = (base >> a) & 1;
+      if ((W.smask >> a) & 1u) {
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          const Cx<R> a1 = s_hf[2 * a + ba], a2 = tb.lowf[(a * 2 + ba) * 256 + t], a3 = s_fmh[(a * 2 + ba) * Q + q];
+          const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
+          const Cx<R> x = part[q * kBlock + t];
+          acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+          acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+        }
+      }
+#pragma unroll 1
+      for (; e < e_out && pl[e].z == a; e++) {
+        const int4 pe = pl[e];
+        const int i = pe.y;
+        const Cx<R> clo = tb.pc_half[4 * pe.x + ba], chi = tb.pc_half[4 * pe.x + 2 + ba];
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          const int r = q * kBlock + t;
+          const Cx<R> c = ((r >> i) & 1) ? chi : clo;
+          const Cx<R> x = part[r ^ (1 << i)];
+          acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+          acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+        }
+      }
+    }
+    // pairs of two outer sites
+#pragma unroll 1
+    for (int e2 = e_out; e2 < np; e2++) {
+      const int4 pe = pl[e2];
+      const int type = (((base >> pe.y) & 1) << 1) | ((base >> pe.z) & 1);
+      const Cx<R> c = tb.pc_half[4 * pe.x + type];
+      const uint32_t pb = base ^ (1u << pe.y) ^ (1u << pe.z);
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const Cx<R> x = v[(size_t)(pb + q * kBlock + t) * K + c0];
+        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      Acc<R, 1> a1;
+      a1.re[0] = acc[q].re;
+      a1.im[0] = acc[q].im;
+      const uint32_t row = base + q * kBlock + t;
+      win_store<R>(W, P, row, c0, a1, v + (size_t)row * K + c0, red);
+    }
+  });
+  if (W.last) hv_finish<1>(P, red);
+}
+
 // General mixed radix: one 256-row slice of a window per item; the window's
 // rows are enumerated with the window sites' digits (lowest site fastest), the
 // outer digits come from the window index.
@@ -1533,6 +1730,36 @@ static int launch_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &p
   return FTLM_OK;
 }
 
+template <typename R>
+static size_t hv_tile_win_smem(const HamGeom &g, const WinPass &W) {
+  return sizeof(Cx<R>) * (2 * (size_t)kTileRows + 4 * (size_t)W.np_ll + 2 * kRowsPerThread * g.n + 2 * g.n) +
+         sizeof(R) * (2 * g.n + kRowsPerThread + 8 * kRowsPerThread + 32 * kRowsPerThread);
+}
+
+template <typename R>
+static int launch_tile_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &plan, const HvParams &P,
+                           int cap, hipStream_t s) {
+  const HamGeom &g = dh.geom;
+  if (!plan.d_plist || plan.passes.empty() || !g.spin_half || g.n <= kTileBits) return FTLM_EINVAL;
+  for (const WinPass &W : plan.passes) {
+    const uint64_t items = (uint64_t)W.nwin * W.nin;
+    uint32_t gx = (uint32_t)(items < (uint64_t)cap ? items : (uint64_t)cap);
+    if (W.nwin >= 8 && gx >= 8) gx &= ~7u;
+    HvParams Pp = P;
+    if (!W.last) Pp.lanczos = 0;
+    const size_t sm = hv_tile_win_smem<R>(g, W);
+    if (sm > 160 * 1024) return FTLM_ERANGE;
+    static size_t granted = 0;
+    if (sm > granted) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_tile_win<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+      granted = sm;
+    }
+    hipLaunchKernelGGL((hv_tile_win<R>), dim3(gx, P.K), dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp);
+  }
+  return FTLM_OK;
+}
+
 int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
   HvLaunch L = Lin;
   if (L.K >= 1 && L.K <= 64 && (L.precision == 0 || L.precision == 1)) {
@@ -1569,6 +1796,13 @@ int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
     P.alpha_out = L.lz->alpha_out;
     P.yre_out = L.lz->yre_out;
     P.yim_out = L.lz->yim_out;
+  }
+  if (L.variant == 5) {
+    const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
+    int rc = (L.precision == FTLM_C64) ? launch_tile_win<float>(dh, dh.t32, dh.tw32, P, cap, s)
+                                       : launch_tile_win<double>(dh, dh.t64, dh.tw64, P, cap, s);
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
   }
   if (L.variant == 4) {
     const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;

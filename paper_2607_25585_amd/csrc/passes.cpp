@@ -272,7 +272,9 @@ int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std:
 constexpr int kRestarts = 64;  // randomised greedy restarts of the L2-window cover
 
 int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
-                    size_t window_rows, bool spin_half, WinPlan &plan) {
+                    size_t window_rows, int lane_bits, WinPlan &plan) {
+  const bool spin_half = lane_bits > 0;
+  const int lb = spin_half ? lane_bits : kLowBits;
   plan = WinPlan();
   plan.window_rows = window_rows;
   const int n = hh.n, np = (int)pi.size();
@@ -288,14 +290,14 @@ int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::ve
     best.pairs.assign(1, all);
   } else if (spin_half) {
     int ebits = 0;
-    while (((uint64_t)1 << (kLowBits + ebits + 1)) <= window_rows) ebits++;
-    if (ebits < 1) return FTLM_ERANGE;
-    if (!greedy_cover(hh, pi, pj, kLowBits, (uint64_t)1 << ebits, ebits, best)) return FTLM_ERANGE;
-    best_c = kLowBits;
+    while (((uint64_t)1 << (lb + ebits + 1)) <= window_rows) ebits++;
+    if (ebits < 1 && n > lb) return FTLM_ERANGE;
+    if (!greedy_cover(hh, pi, pj, lb, (uint64_t)1 << ebits, ebits, best)) return FTLM_ERANGE;
+    best_c = lb;
     std::mt19937 rng(12345u);
     for (int rs = 0; rs < kRestarts; rs++) {
       Cover cv;
-      if (greedy_cover(hh, pi, pj, kLowBits, (uint64_t)1 << ebits, ebits, cv, &rng) &&
+      if (greedy_cover(hh, pi, pj, lb, (uint64_t)1 << ebits, ebits, cv, &rng) &&
           cv.extra.size() < best.extra.size())
         best = cv;
     }
@@ -356,14 +358,22 @@ int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::ve
     W.diag = ps == 0;
     W.p0 = (int)plan.plist.size();
     {
-      // order by the number of sites >= 8 (spin-1/2 kernel: lane / tile classes)
+      // order by the number of sites outside the lane / tile bits (spin-1/2
+      // kernels); pairs with one such site by that site
       std::vector<int> prs = best.pairs[ps];
-      auto cls = [&](int p) { return (pi[p] >= kLowBits) + (pj[p] >= kLowBits); };
-      std::stable_sort(prs.begin(), prs.end(), [&](int a, int b) { return cls(a) < cls(b); });
+      auto cls = [&](int p) { return (pi[p] >= lb) + (pj[p] >= lb); };
+      std::stable_sort(prs.begin(), prs.end(), [&](int a, int b) {
+        if (cls(a) != cls(b)) return cls(a) < cls(b);
+        if (cls(a) == 1) return pj[a] < pj[b];
+        return false;
+      });
       for (int p : prs) {
         plan.plist.push_back(make_int4(p, pi[p], pj[p], 0));
         if (cls(p) == 0) W.np_ll++;
-        else if (cls(p) == 1) W.np_lh++;
+        else if (cls(p) == 1) {
+          W.np_lh++;
+          W.xmask |= 1u << pj[p];
+        }
       }
     }
     W.np = (int)plan.plist.size() - W.p0;
@@ -388,11 +398,12 @@ int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::ve
     W.wsize = (uint32_t)ws;
     W.nwin = (uint32_t)(hh.dim / ws);
     if (spin_half) {
-      for (int k = kLowBits; k < n; k++) {
+      for (int k = lb; k < n; k++) {
         if (inw[k]) W.emask |= 1u << k;
         else W.omask |= 1u << k;
+        if ((W.smask >> k) & 1u) W.xmask |= 1u << k;
       }
-      W.nin = (uint32_t)(ws >> kLowBits);
+      W.nin = (uint32_t)(ws >> lb);
     } else {
       W.nin = (uint32_t)((ws + kBlock - 1) / kBlock);
     }
@@ -400,6 +411,14 @@ int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::ve
   }
   if (plan.plist.empty()) plan.plist.push_back(make_int4(0, 0, 0, 0));
   return FTLM_OK;
+}
+
+size_t tile_window_bytes_setting() {
+  const char *e = std::getenv("FTLM_TILE_WINDOW_KB");
+  long kb = e ? std::atol(e) : 2048;
+  if (kb < 4) kb = 4;
+  if (kb > 65536) kb = 65536;
+  return (size_t)kb * 1024;
 }
 
 size_t l2_window_bytes_setting() {
@@ -497,7 +516,7 @@ extern "C" int ftlm_describe_windows(const ftlm_system *sys, int32_t precision, 
   const size_t wb = window_bytes > 0 ? (size_t)window_bytes : l2_window_bytes_setting();
   WinPlan plan;
   rc = plan_l2_windows(hh, spi, spj, wb / (precision == FTLM_C64 ? 8 : 16),
-                       hh.spin_half && hh.n >= kLowBits, plan);
+                       (hh.spin_half && hh.n >= kLowBits) ? kLowBits : 0, plan);
   if (rc) {
     set_error("no L2-window plan fits the window size");
     return rc;

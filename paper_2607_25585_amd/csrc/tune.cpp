@@ -17,7 +17,7 @@ extern "C" {
 int ftlm_hamiltonian_set_tuning(ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, int32_t variant,
                                 int32_t grid_cap, int32_t kc) {
   if (!h || (precision != FTLM_C128 && precision != FTLM_C64) || n_cols < 1 || n_cols > 64 || variant < 0 ||
-      variant > 4 || grid_cap < 0 || kc < 0) {
+      variant > 5 || grid_cap < 0 || kc < 0) {
     set_error("bad tuning arguments");
     return FTLM_EINVAL;
   }
@@ -48,6 +48,9 @@ int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_
     if (n_cols == 1) cands.push_back({2, cap, 0});
     if (n_cols == 1 && g.spin_half && g.n >= kTileBits) cands.push_back({3, cap, 0});
     if (n_cols == 1 && cap <= 2048) cands.push_back({4, cap, 0});
+    if (n_cols == 1 && cap <= 2048 && g.spin_half && g.n > kTileBits &&
+        !(precision == FTLM_C64 ? h->dev.tw32 : h->dev.tw64).passes.empty())
+      cands.push_back({5, cap, 0});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

@@ -18,6 +18,7 @@ def _force_l2win(monkeypatch):
         pytest.skip("no GPU")
     monkeypatch.setenv("FTLM_HV_VARIANT", "4")
     monkeypatch.setenv("FTLM_L2_WINDOW_KB", "16")
+    monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "128")
 
 
 def F():
@@ -90,5 +91,45 @@ def _sampled(sysm, prec, tol, n_rows=2000):
 def test_l2win_full_size_sampled_rows(wl, monkeypatch):
     monkeypatch.setenv("FTLM_L2_WINDOW_KB", "1024")
     sysm, _ = W.WORKLOADS[wl]()
+    _sampled(sysm, F().FTLM_C128, 1e-12)
+    _sampled(sysm, F().FTLM_C64, 2e-5)
+
+
+@pytest.mark.parametrize("seed,n", [(0, 12), (1, 14), (2, 16), (3, 13)])
+def test_tile_window_hv_matches_oracle(seed, n, monkeypatch):
+    """Variant 5 (LDS tile kernel walked over L2 windows), spin 1/2: tiny windows
+    give many passes (N = 16: ten)."""
+    monkeypatch.setenv("FTLM_HV_VARIANT", "5")
+    rng = np.random.default_rng(2900 + seed)
+    sysm = W.random_small_system(rng, n, max_two_s=1)
+    sysm.two_s[:] = 1
+    print("case tile-window seed", seed, "n", n, flush=True)
+    ham = F().Hamiltonian(sysm)
+    v = rng.standard_normal(ham.dim) + 1j * rng.standard_normal(ham.dim)
+    oh = of.Ham(sysm)
+    assert rel_max(ham.apply(torch.as_tensor(v, device="cuda")).cpu().numpy(), oh.apply(v)) < 1e-12
+    w32 = ham.apply(torch.as_tensor(v, device="cuda", dtype=torch.complex64)).cpu().numpy()
+    assert rel_max(w32, oh.apply(v.astype(np.complex64).astype(np.complex128))) < 2e-5
+
+
+def test_tile_window_run_matches_oracle(monkeypatch):
+    monkeypatch.setenv("FTLM_HV_VARIANT", "5")
+    rng = np.random.default_rng(2950)
+    sysm = W.random_small_system(rng, 15, max_two_s=1)
+    sysm.two_s[:] = 1
+    T = W.t_grid(30)
+    ham = F().Hamiltonian(sysm)
+    got = F().run(ham, 2, 30, T, seed=6, columns=1)
+    ref = of.ftlm(sysm, 2, 30, T, seed=6)[0]
+    for key in ("lnZ", "E", "C", "M"):
+        r = np.asarray(ref[key])
+        err = np.max(np.abs(got[key][0] - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max()))
+        assert err < 1e-8, key
+
+
+def test_tile_window_full_size_sampled_rows(monkeypatch):
+    monkeypatch.setenv("FTLM_HV_VARIANT", "5")
+    monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "2048")
+    sysm, _ = W.cfg2()
     _sampled(sysm, F().FTLM_C128, 1e-12)
     _sampled(sysm, F().FTLM_C64, 2e-5)
