@@ -228,6 +228,77 @@ def surrogate_report(n_train, n_test, train_s):
             "gate_accepts": float(np.mean(spread <= ens.disagreement))}
 
 
+def extras_report():
+    """Throughput of the forms beyond the plain method, each on its own workload:
+    sFTLM with time-reversed pairs on the N=6, s=5/2 ring (both printed fields),
+    the Chebyshev expansion next to FTLM on the same random vectors (s=1 ring),
+    and the powder-averaged FTLM of the Mn9 cube (10 dodecahedron directions)."""
+    import numpy as np
+    import torch
+
+    import ftlm_workloads as W
+    import paper_2607_25585_amd as F
+    out = {}
+    sysm, spec = W.ring6()
+    ham = F.Hamiltonian(sysm)
+    fields = [[0.0, 0.0, 0.1], [0.0, 0.0, 1.0]]
+    F.run_sftlm(ham, 2, 8, spec.T, seed=spec.seed, fields=fields[:1])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = F.run_sftlm(ham, spec.R, spec.n_lanczos, spec.T, seed=spec.seed, fields=fields)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["sftlm_ring6"] = {"curves": 2, "R": spec.R, "N_L": spec.n_lanczos, "dim": ham.dim,
+                          "curves_per_s": round(2 / dt, 4), "s_per_curve": round(dt / 2, 3),
+                          "M_at_T_min": [float(r["M"][f][0]) for f in range(2)]}
+    print("extras: sFTLM done", file=sys.stderr, flush=True)
+    ham.close()
+    sysm, spec = W.cfg1()
+    ham = F.Hamiltonian(sysm)
+    T = spec.T
+    F.run(ham, 2, 8, T, seed=spec.seed)
+    F.run_kpm(ham, 2, 16, T, seed=spec.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lz = F.run(ham, spec.R, spec.n_lanczos, T, seed=spec.seed)
+    torch.cuda.synchronize()
+    t_l = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    kp = F.run_kpm(ham, spec.R, 2000, T, seed=spec.seed, n_bound_steps=60)
+    torch.cuda.synchronize()
+    t_k = time.perf_counter() - t0
+    lz32 = F.run(ham, spec.R, spec.n_lanczos, T, seed=spec.seed, precision=F.FTLM_C64)
+    out["fp32_vs_fp64_cfg1"] = {"R": spec.R, "N_L": spec.n_lanczos,
+                                "lnZ_abs": float(np.max(np.abs(lz32["lnZ"][0] - lz["lnZ"][0]))),
+                                "E_rel": curve_err(lz32["E"][0], lz["E"][0]),
+                                "C_rel": curve_err(lz32["C"][0], lz["C"][0]),
+                                "M_rel": curve_err(lz32["M"][0], lz["M"][0]),
+                                "E0_abs": float(abs(lz32["E_min"][0] - lz["E_min"][0]))}
+    hiT = T >= 1.0
+    out["kpm_cfg1"] = {"R": spec.R, "N_moments": 2000, "lanczos_N_L": spec.n_lanczos,
+                       "kpm_curves_per_s": round(1 / t_k, 3), "lanczos_curves_per_s": round(1 / t_l, 3),
+                       "max_C_rel_diff_T_ge_1K": curve_err(kp["C"][0][hiT], lz["C"][0][hiT]),
+                       "E_lo": float(kp["E_lo"][0]), "E_hi": float(kp["E_hi"][0])}
+    print("extras: KPM done", file=sys.stderr, flush=True)
+    ham.close()
+    sysm, spec = W.mn9()
+    ham = F.Hamiltonian(sysm)
+    F.run(ham, 1, 4, spec.T, seed=spec.seed)
+    torch.cuda.synchronize()
+    R, NL = 4, 100
+    t0 = time.perf_counter()
+    res = F.run(ham, R, NL, spec.T, seed=spec.seed, fields=spec.fields)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    powder = res["M"].mean(axis=0)
+    out["mn9_powder"] = {"dim": ham.dim, "directions": len(spec.fields), "R": R, "N_L": NL,
+                         "curves_per_s": round(len(spec.fields) / dt, 4),
+                         "powder_M_T_over_B_at_T_max": float(powder[-1] * spec.T[-1] / 1.0),
+                         "T_max": float(spec.T[-1]), "B_T": 1.0}
+    print("extras: Mn9 done", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +316,8 @@ def main():
     ap.add_argument("--hv-only", action="store_true",
                     help="time the H*v product alone (GB/s line) instead of whole curves")
     ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--extras", action="store_true",
+                    help="sFTLM (ring6), Chebyshev vs Lanczos (cfg1) and Mn9 powder throughput")
     ap.add_argument("--surrogate", action="store_true",
                     help="surrogate report on the s=3/2 ring data instead of the FTLM curve bench")
     ap.add_argument("--surrogate-train", type=int, default=2000)
@@ -263,6 +336,12 @@ def main():
     import paper_2607_25585_amd as F
 
     torch.cuda.set_device(0)
+    if args.extras:
+        out = {"metric": "curves/s of sFTLM, Chebyshev and powder-averaged FTLM", "n_gpus": 1,
+               "data": "synthetic", "config": {"workload": "ring6 / cfg1 / mn9"}}
+        out.update(extras_report())
+        print(json.dumps(out), flush=True)
+        return
     if args.surrogate:
         out = {"metric": "surrogate curves/s vs FTLM at held-out accuracy", "n_gpus": 1, "data": "synthetic",
                "config": {"workload": "8-spin s=3/2 ring, MLP 7-256-256-256-3 (bf16 weights, fp32 accumulate)"}}

@@ -1174,6 +1174,40 @@ __global__ __launch_bounds__(kBlock) void hv_half_win(HamGeom g, DevTables<R> tb
 // xmask the partner tile (tile with bit a flipped) staged once for the single
 // flip of a and the mixed pairs (i < 11, a), then pairs of two outer sites read
 // straight from global memory (L2-resident: both sites lie in the window).
+// Slot-bit terms of the tile kernels (rows r = q * 256 + t, q = bits 8..10):
+// the flipped slot bit SB is a compile-time constant, so the partner slot and
+// the coefficient choice per q need no instructions.
+template <typename R>
+__device__ __forceinline__ void fma_cx(Cx<R> &a, const Cx<R> &c, const Cx<R> &x) {
+  a.re = fma(c.re, x.re, fma(-c.im, x.im, a.re));
+  a.im = fma(c.re, x.im, fma(c.im, x.re, a.im));
+}
+
+// acc[q] += (bit SB of q ? c1 : c0) * src[(q ^ 2^SB) * 256 + tl]
+template <int SB, typename R>
+__device__ __forceinline__ void slot_flip(Cx<R> (&acc)[kRowsPerThread], const Cx<R> *src, int tl, Cx<R> c0,
+                                          Cx<R> c1) {
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; q++) fma_cx(acc[q], ((q >> SB) & 1) ? c1 : c0, src[(q ^ (1 << SB)) * kBlock + tl]);
+}
+
+// two slot bits A < B: acc[q] += cp[(bit A of q) << 1 | bit B of q] * src[(q ^ 2^A ^ 2^B) * 256 + t]
+template <int A, int B, typename R>
+__device__ __forceinline__ void slot_pair(Cx<R> (&acc)[kRowsPerThread], const Cx<R> *src, int t, const Cx<R> *cp) {
+  const Cx<R> c[4] = {cp[0], cp[1], cp[2], cp[3]};
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; q++)
+    fma_cx(acc[q], c[(((q >> A) & 1) << 1) | ((q >> B) & 1)], src[(q ^ (1 << A) ^ (1 << B)) * kBlock + t]);
+}
+
+template <typename R>
+__device__ __forceinline__ void slot_flip_any(int sb, Cx<R> (&acc)[kRowsPerThread], const Cx<R> *src, int tl,
+                                              Cx<R> c0, Cx<R> c1) {
+  if (sb == 0) slot_flip<0>(acc, src, tl, c0, c1);
+  else if (sb == 1) slot_flip<1>(acc, src, tl, c0, c1);
+  else slot_flip<2>(acc, src, tl, c0, c1);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R> tb, WinPass W,
                                                          const int4 *__restrict__ plist, HvParams P) {
@@ -1218,8 +1252,12 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
   win_walk(W, [&](uint32_t win, uint32_t item) {
     const uint32_t base = __builtin_amdgcn_readfirstlane(scatter_bits(item, W.emask) | scatter_bits(win, W.omask));
     __syncthreads();
+    const size_t tk = (size_t)t * K;  // lane offset; the tile bases below are uniform
+    {
+      const Cx<R> *vb = v + (size_t)base * K + c0;
 #pragma unroll
-    for (int q = 0; q < Q; q++) own[q * kBlock + t] = v[(size_t)(base + q * kBlock + t) * K + c0];
+      for (int q = 0; q < Q; q++) own[q * kBlock + t] = vb[(size_t)q * kBlock * K + tk];
+    }
     // per-tile uniform parts: rows of slot q have bits 8..10 = q and bits >= 11 = base
     if (zf)
       for (int e = t; e < 2 * Q * n; e += kBlock) {
@@ -1277,30 +1315,43 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
 #pragma unroll 1
     for (uint32_t sm = W.smask & ((1u << kTileBits) - 1u); sm; sm &= sm - 1u) {
       const int k = __builtin_ctz(sm);
+      if (k < kLowBits) {  // lane bit: the row bit and the lane part of F do not depend on q
+        const int b = (t >> k) & 1;
+        const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + t];
+        const int tl = t ^ (1 << k);
 #pragma unroll
-      for (int q = 0; q < Q; q++) {
-        const int r = q * kBlock + t;
-        const int b = (r >> k) & 1;
-        const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + t], a3 = s_fmh[(k * 2 + b) * Q + q];
-        const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
-        const Cx<R> x = own[r ^ (1 << k)];
-        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
-        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+        for (int q = 0; q < Q; q++) {
+          const Cx<R> a3 = s_fmh[(k * 2 + b) * Q + q];
+          fma_cx(acc[q], Cx<R>{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im}, own[q * kBlock + tl]);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          const int b = (q >> (k - kLowBits)) & 1;
+          const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + t], a3 = s_fmh[(k * 2 + b) * Q + q];
+          fma_cx(acc[q], Cx<R>{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im},
+                 own[(q ^ (1 << (k - kLowBits))) * kBlock + t]);
+        }
       }
     }
-    // pairs inside the tile
+    // pairs inside the tile (i < j < 11)
 #pragma unroll 1
     for (int e = 0; e < n_in; e++) {
       const int4 ij = pl[e];
-      const int mask = (1 << ij.y) | (1 << ij.z);
+      const int i = ij.y, j = ij.z;
+      if (j < kLowBits) {  // two lane bits: one coefficient per thread, partner lane t ^ mask
+        const Cx<R> c = s_pc[4 * e + ((((t >> i) & 1) << 1) | ((t >> j) & 1))];
+        const int tl = t ^ ((1 << i) | (1 << j));
 #pragma unroll
-      for (int q = 0; q < Q; q++) {
-        const int r = q * kBlock + t;
-        const int type = (((r >> ij.y) & 1) << 1) | ((r >> ij.z) & 1);
-        const Cx<R> c = s_pc[4 * e + type];
-        const Cx<R> x = own[r ^ mask];
-        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
-        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+        for (int q = 0; q < Q; q++) fma_cx(acc[q], c, own[q * kBlock + tl]);
+      } else if (i < kLowBits) {  // lane bit i, slot bit j
+        const int bi = (t >> i) & 1;
+        slot_flip_any(j - kLowBits, acc, own, t ^ (1 << i), s_pc[4 * e + (bi << 1)], s_pc[4 * e + (bi << 1) + 1]);
+      } else {  // two slot bits
+        const Cx<R> *cp = s_pc + 4 * e;
+        if (i == kLowBits && j == kLowBits + 1) slot_pair<0, 1>(acc, own, t, cp);
+        else if (i == kLowBits) slot_pair<0, 2>(acc, own, t, cp);
+        else slot_pair<1, 2>(acc, own, t, cp);
       }
     }
     // outer sites with work in this pass: partner tile staged once
@@ -1309,9 +1360,9 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
     for (uint32_t xm = W.xmask; xm; xm &= xm - 1u) {
       const int a = __builtin_ctz(xm);
       __syncthreads();
-      const uint32_t pb = base ^ (1u << a);
+      const Cx<R> *vb = v + (size_t)(base ^ (1u << a)) * K + c0;
 #pragma unroll
-      for (int q = 0; q < Q; q++) part[q * kBlock + t] = v[(size_t)(pb + q * kBlock + t) * K + c0];
+      for (int q = 0; q < Q; q++) part[q * kBlock + t] = vb[(size_t)q * kBlock * K + tk];
       __syncthreads();
       const int ba = (base >> a) & 1;
       if ((W.smask >> a) & 1u) {
@@ -1329,13 +1380,13 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
         const int4 pe = pl[e];
         const int i = pe.y;
         const Cx<R> clo = tb.pc_half[4 * pe.x + ba], chi = tb.pc_half[4 * pe.x + 2 + ba];
+        if (i < kLowBits) {
+          const Cx<R> c = ((t >> i) & 1) ? chi : clo;
+          const int tl = t ^ (1 << i);
 #pragma unroll
-        for (int q = 0; q < Q; q++) {
-          const int r = q * kBlock + t;
-          const Cx<R> c = ((r >> i) & 1) ? chi : clo;
-          const Cx<R> x = part[r ^ (1 << i)];
-          acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
-          acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+          for (int q = 0; q < Q; q++) fma_cx(acc[q], c, part[q * kBlock + tl]);
+        } else {
+          slot_flip_any(i - kLowBits, acc, part, t, clo, chi);
         }
       }
     }
@@ -1345,13 +1396,9 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
       const int4 pe = pl[e2];
       const int type = (((base >> pe.y) & 1) << 1) | ((base >> pe.z) & 1);
       const Cx<R> c = tb.pc_half[4 * pe.x + type];
-      const uint32_t pb = base ^ (1u << pe.y) ^ (1u << pe.z);
+      const Cx<R> *vb = v + (size_t)(base ^ (1u << pe.y) ^ (1u << pe.z)) * K + c0;
 #pragma unroll
-      for (int q = 0; q < Q; q++) {
-        const Cx<R> x = v[(size_t)(pb + q * kBlock + t) * K + c0];
-        acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
-        acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
-      }
+      for (int q = 0; q < Q; q++) fma_cx(acc[q], c, vb[(size_t)q * kBlock * K + tk]);
     }
 #pragma unroll
     for (int q = 0; q < Q; q++) {
