@@ -1354,15 +1354,40 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
         else slot_pair<1, 2>(acc, own, t, cp);
       }
     }
-    // outer sites with work in this pass: partner tile staged once
+    // outer sites with work in this pass: partner tile staged once; the next
+    // site's tile is loaded into registers while the current one is in use
     int e = n_in;
-#pragma unroll 1
-    for (uint32_t xm = W.xmask; xm; xm &= xm - 1u) {
-      const int a = __builtin_ctz(xm);
-      __syncthreads();
-      const Cx<R> *vb = v + (size_t)(base ^ (1u << a)) * K + c0;
+    uint32_t xm = W.xmask;
+    // (with no next site the own tile is loaded instead, so that the
+    // prefetch registers are always defined)
+    R nre[Q], nim[Q];
+    {
+      const uint32_t nb = xm ? (base ^ (1u << __builtin_ctz(xm))) : base;
+      const Cx<R> *vb = v + (size_t)nb * K + c0;
 #pragma unroll
-      for (int q = 0; q < Q; q++) part[q * kBlock + t] = vb[(size_t)q * kBlock * K + tk];
+      for (int q = 0; q < Q; q++) {
+        const Cx<R> x = vb[(size_t)q * kBlock * K + tk];
+        nre[q] = x.re;
+        nim[q] = x.im;
+      }
+    }
+#pragma unroll 1
+    while (xm) {
+      const int a = __builtin_ctz(xm);
+      xm &= xm - 1u;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < Q; q++) part[q * kBlock + t] = Cx<R>{nre[q], nim[q]};
+      {
+        const uint32_t nb = xm ? (base ^ (1u << __builtin_ctz(xm))) : base;
+        const Cx<R> *vb = v + (size_t)nb * K + c0;
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          const Cx<R> x = vb[(size_t)q * kBlock * K + tk];
+          nre[q] = x.re;
+          nim[q] = x.im;
+        }
+      }
       __syncthreads();
       const int ba = (base >> a) & 1;
       if ((W.smask >> a) & 1u) {
@@ -1370,9 +1395,7 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
         for (int q = 0; q < Q; q++) {
           const Cx<R> a1 = s_hf[2 * a + ba], a2 = tb.lowf[(a * 2 + ba) * 256 + t], a3 = s_fmh[(a * 2 + ba) * Q + q];
           const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
-          const Cx<R> x = part[q * kBlock + t];
-          acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
-          acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+          fma_cx(acc[q], c, part[q * kBlock + t]);
         }
       }
 #pragma unroll 1
