@@ -212,13 +212,21 @@ def surrogate_report(n_train, n_test, train_s):
     torch.cuda.synchronize()
     t_sur = (time.perf_counter() - t0) / reps
 
-    def rel(a, b):
+    def rel(a, b, cols=slice(None)):
+        a, b = a[:, cols], b[:, cols]
         floor = 1e-3 * np.max(np.abs(b), axis=1, keepdims=True)
         return np.max(np.abs(a - b) / np.maximum(np.abs(b), np.maximum(floor, 1e-12)), axis=1)
     eC, eM = rel(pc, cct), np.max(np.abs(pm - mmt), axis=1)
     eZ = np.max(np.abs(plz - lzt), axis=1)
-    q = lambda a: {"median": float(np.median(a)), "p90": float(np.quantile(a, 0.9)), "max": float(np.max(a))}  # noqa: E731
+    hi = T >= 1.0
+    eC1, eM1 = rel(pc, cct, hi), rel(pm, mmt, hi)
+    acc = spread <= ens.disagreement
+    q = lambda a: {"median": float(np.median(a)), "p90": float(np.quantile(a, 0.9)), "max": float(np.max(a))} if len(a) else None  # noqa: E731
+    rms = lambda a, b: float(np.sqrt(np.mean((a - b) ** 2)))  # noqa: E731
     return {"train_sets": n_train, "test_sets": n_test, "T_points": len(T),
+            "rmse_all_T": {"lnZ": rms(plz, lzt), "M_muB": rms(pm, mmt), "C_kB": rms(pc, cct)},
+            "heldout_C_relerr_A12_T_ge_1K": q(eC1), "heldout_M_relerr_A12_T_ge_1K": q(eM1),
+            "gate_accepted_C_relerr_A12_T_ge_1K": q(eC1[acc]),
             "ftlm_fp32_batched_curves_per_s": round(n_train / t_gen, 3),
             "ftlm_fp64_batched_curves_per_s": round(n_test / t_ftlm64, 3),
             "surrogate_curves_per_s": round(n_test / t_sur, 1),
@@ -320,9 +328,9 @@ def main():
                     help="sFTLM (ring6), Chebyshev vs Lanczos (cfg1) and Mn9 powder throughput")
     ap.add_argument("--surrogate", action="store_true",
                     help="surrogate report on the s=3/2 ring data instead of the FTLM curve bench")
-    ap.add_argument("--surrogate-train", type=int, default=2000)
+    ap.add_argument("--surrogate-train", type=int, default=4000)
     ap.add_argument("--surrogate-test", type=int, default=200)
-    ap.add_argument("--surrogate-train-s", type=float, default=60.0)
+    ap.add_argument("--surrogate-train-s", type=float, default=150.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

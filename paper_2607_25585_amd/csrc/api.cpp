@@ -433,7 +433,7 @@ int ftlm_gaussian_vectors(uint64_t seed, uint32_t instance, uint32_t field, uint
   static thread_local int scratch_dev = -1;
   int dev = 0;
   HIP_OK(hipGetDevice(&dev));
-  const size_t need = sizeof(double) * (2048 * 64 + 64) + 256;
+  const size_t need = sizeof(double) * (2048 * 64 + 64) + sizeof(unsigned) * kCounterWords;
   if (!scratch || scratch_dev != dev) {
     HIP_OK(hipMalloc(&scratch, need));
     HIP_OK(hipMemset(scratch, 0, need));

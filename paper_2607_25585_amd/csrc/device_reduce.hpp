@@ -16,15 +16,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sums NV*KC per-lane values over the block (fixed order) and writes them to
-// part[slot*NV*KC ...].  Returns true on the last block of the grid to get
-// there (device-wide counter), which may then read every block's partials and
-// reduce them in slot order; the caller resets the counter.
+// Block-level fixed-order sums of NV*KC per-lane values, stored to
+// part[slot*NV*KC ...] with plain stores.  The grid-level sum runs in a
+// separate finishing kernel launched behind this one on the same stream (the
+// kernel boundary orders the stores): no device-scope fence or atomic per
+// block, which on this GPU cost a write-back of the L2 each and serialise the
+// grid's tail.
 template <int NV, int KC>
-__device__ __forceinline__ bool block_partials(const double (&val)[NV][KC], double *part,
-                                               int slot, unsigned *counter, unsigned total) {
+__device__ __forceinline__ void block_partials_store(const double (&val)[NV][KC], double *part, int slot) {
   __shared__ double red[kBlock / 64][NV * KC];
-  __shared__ bool last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int a = 0; a < NV; a++)
@@ -39,15 +39,6 @@ __device__ __forceinline__ bool block_partials(const double (&val)[NV][KC], doub
     for (int w2 = 0; w2 < kBlock / 64; w2++) s += red[w2][threadIdx.x];
     part[(size_t)slot * NV * KC + threadIdx.x] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == total - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
 }
 
 // Sum of x[bx * stride] over bx < n by the whole block in a fixed order (thread

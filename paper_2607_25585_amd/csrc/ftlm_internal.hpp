@@ -21,6 +21,8 @@ constexpr int kBlock = 256;
 constexpr int kTileBits = 11;                  // spin-1/2 LDS tile: 2048 rows, sites 0..10 vary
 constexpr int kTileRows = 1 << kTileBits;
 constexpr int kRowsPerThread = kTileRows / kBlock;  // 8
+constexpr int kCtrGroups = 64;                 // arrival counters of the grid reductions
+constexpr int kCounterWords = 1 + kCtrGroups;  // words of one reduction counter array
 
 template <typename R>
 struct alignas(2 * sizeof(R)) Cx {

@@ -121,24 +121,33 @@ __device__ __forceinline__ void hv_epilogue(const HvParams &P, uint32_t row, int
 template <int KC>
 __device__ __forceinline__ void hv_finish(const HvParams &P, double (&red)[3][KC]) {
   if (!P.lanczos) return;
-  const unsigned total = gridDim.x * gridDim.y;
-  const int slot = blockIdx.y * gridDim.x + blockIdx.x;
-  if (block_partials<3, KC>(red, P.part, slot, P.counter, total)) {
-    // columns c = cb*KC + q; partial layout [cb][bx][3][KC]
-    const int ncol = gridDim.y * KC;
-    for (int idx = 0; idx < 3 * ncol; idx++) {
-      const int c = idx / 3, a = idx % 3;
-      const int cb = c / KC, q = c % KC;
-      double s = block_sum_strided(P.part + ((size_t)cb * gridDim.x * 3 + a) * KC + q, gridDim.x,
-                                   (size_t)3 * KC);
-      s *= P.scale[c];
-      if (threadIdx.x == 0) {
-        if (a == 0) P.alpha_out[c] = s;
-        else if (a == 1) { if (P.ov1) P.yre_out[c] = s; }
-        else { if (P.ov1) P.yim_out[c] = s; }
-      }
+  block_partials_store<3, KC>(red, P.part, blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// One block: alpha_j and y_j of every column from the H*v kernel's per-block
+// partials (layout [cb][bx][3][KC], gx blocks along x), in block order.
+template <int KC>
+__global__ __launch_bounds__(kBlock) void hv_lanczos_finish(HvParams P, unsigned gx, unsigned gy) {
+  const int ncol = gy * KC;
+  for (int idx = 0; idx < 3 * ncol; idx++) {
+    const int c = idx / 3, a = idx % 3;
+    const int cb = c / KC, q = c % KC;
+    double s = block_sum_strided(P.part + ((size_t)cb * gx * 3 + a) * KC + q, gx, (size_t)3 * KC);
+    s *= P.scale[c];
+    if (threadIdx.x == 0) {
+      if (a == 0) P.alpha_out[c] = s;
+      else if (a == 1) { if (P.ov1) P.yre_out[c] = s; }
+      else { if (P.ov1) P.yim_out[c] = s; }
     }
-    if (threadIdx.x == 0) *P.counter = 0u;
+  }
+}
+
+static void launch_hv_finish(const HvParams &P, unsigned gx, unsigned gy, int kc, hipStream_t s) {
+  switch (kc) {
+    case 8: hipLaunchKernelGGL(hv_lanczos_finish<8>, dim3(1), dim3(kBlock), 0, s, P, gx, gy); break;
+    case 4: hipLaunchKernelGGL(hv_lanczos_finish<4>, dim3(1), dim3(kBlock), 0, s, P, gx, gy); break;
+    case 2: hipLaunchKernelGGL(hv_lanczos_finish<2>, dim3(1), dim3(kBlock), 0, s, P, gx, gy); break;
+    default: hipLaunchKernelGGL(hv_lanczos_finish<1>, dim3(1), dim3(kBlock), 0, s, P, gx, gy); break;
   }
 }
 
@@ -1030,18 +1039,25 @@ __device__ __forceinline__ void win_walk(const WinPass &W, F &&body) {
 }
 
 // Adds the earlier passes' partial sum, then stores the raw partial (not the
-// last pass) or runs the epilogue (last pass).
-template <typename R>
+// last pass) or runs the epilogue (last pass).  KC columns from c0.
+template <typename R, int KC>
 __device__ __forceinline__ void win_store(const WinPass &W, const HvParams &P, uint32_t row, int c0,
-                                          Acc<R, 1> &acc, const Cx<R> *own, double (&red)[3][1]) {
+                                          Acc<R, KC> &acc, const Cx<R> *own, double (&red)[3][KC]) {
   Cx<R> *wp = reinterpret_cast<Cx<R> *>(P.w) + (size_t)row * P.K + c0;
   if (!W.first) {
-    const Cx<R> o = *wp;
-    acc.re[0] += o.re;
-    acc.im[0] += o.im;
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      const Cx<R> o = wp[q];
+      acc.re[q] += o.re;
+      acc.im[q] += o.im;
+    }
   }
-  if (W.last) hv_epilogue<R, 1>(P, row, c0, acc, own, red);
-  else *wp = Cx<R>{acc.re[0], acc.im[0]};
+  if (W.last) {
+    hv_epilogue<R, KC>(P, row, c0, acc, own, red);
+  } else {
+#pragma unroll
+    for (int q = 0; q < KC; q++) wp[q] = Cx<R>{acc.re[q], acc.im[q]};
+  }
 }
 
 // Spin-1/2, N >= 8: one 256-row tile per item (row bits 0..7 over the lanes,
@@ -1163,7 +1179,7 @@ __global__ __launch_bounds__(kBlock) void hv_half_win(HamGeom g, DevTables<R> tb
       const Cx<R> *vp = v + (size_t)(hi ^ ((1u << ij.x) | (1u << ij.y))) * P.K;
       mac(acc, c, vp + tk);
     }
-    win_store<R>(W, P, row, c0, acc, own, red);
+    win_store<R, 1>(W, P, row, c0, acc, own, red);
   });
   if (W.last) hv_finish<1>(P, red);
 }
@@ -1429,7 +1445,7 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
       a1.re[0] = acc[q].re;
       a1.im[0] = acc[q].im;
       const uint32_t row = base + q * kBlock + t;
-      win_store<R>(W, P, row, c0, a1, v + (size_t)row * K + c0, red);
+      win_store<R, 1>(W, P, row, c0, a1, v + (size_t)row * K + c0, red);
     }
   });
   if (W.last) hv_finish<1>(P, red);
@@ -1438,7 +1454,7 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
 // General mixed radix: one 256-row slice of a window per item; the window's
 // rows are enumerated with the window sites' digits (lowest site fastest), the
 // outer digits come from the window index.
-template <typename R>
+template <typename R, int KC>
 __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb, WinPass W,
                                                      const int4 *__restrict__ plist, HvParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1449,7 +1465,7 @@ __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb,
   R *s_gm = s_gp + n * 16;
   R *s_m = s_gm + n * 16;
   const int t = threadIdx.x;
-  const int c0 = blockIdx.y;
+  const int c0 = blockIdx.y * KC;
   for (int i = t; i < n * 64; i += kBlock) s_hoff[i] = tb.hoff[i];
   for (int i = t; i < n * 16; i += kBlock) {
     s_hd[i] = tb.hdiag[i];
@@ -1460,7 +1476,11 @@ __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb,
   __syncthreads();
   const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v) + c0;
   const int4 *pl = plist + W.p0;
-  double red[3][1] = {{0.0}, {0.0}, {0.0}};
+  double red[3][KC];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int q = 0; q < KC; q++) red[a][q] = 0.0;
 
   win_walk(W, [&](uint32_t win, uint32_t item) {
     const uint32_t iw = item * kBlock + (uint32_t)t;
@@ -1490,7 +1510,7 @@ __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb,
     auto digit = [&](int k) -> int {
       return (int)(((k < 16) ? (dlo >> (4 * k)) : (dhi >> (4 * (k - 16)))) & 15u);
     };
-    Acc<R, 1> acc;
+    Acc<R, KC> acc;
     acc_zero(acc);
     const Cx<R> *own = v + (size_t)row * P.K;
     if (W.diag) {
@@ -1558,9 +1578,9 @@ __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb,
         mac(acc, Cx<R>{cq.re * f, cq.im * f}, v + (size_t)partner * P.K);
       }
     }
-    win_store<R>(W, P, row, c0, acc, own, red);
+    win_store<R, KC>(W, P, row, c0, acc, own, red);
   });
-  if (W.last) hv_finish<1>(P, red);
+  if (W.last) hv_finish<KC>(P, red);
 }
 
 static bool tile_ok(const HamGeom &g, int K) { return g.spin_half && g.n >= kTileBits && K == 1; }
@@ -1608,7 +1628,7 @@ static void launch_pass_t(const DevHam &dh, const DevTables<R> &tb, const PassPl
 
 template <typename R>
 static int launch_passes(const DevHam &dh, const DevTables<R> &tb, const PassPlan &plan,
-                         const HvParams &P, int gy, int cap, hipStream_t s) {
+                         const HvParams &P, int gy, int cap, unsigned *last_gx, hipStream_t s) {
   if (!plan.rec_block) return FTLM_EINVAL;
   for (size_t ps = 0; ps < plan.passes.size(); ps++) {
     const PassDesc &D = plan.passes[ps];
@@ -1620,6 +1640,7 @@ static int launch_passes(const DevHam &dh, const DevTables<R> &tb, const PassPla
     if (!D.last) Pp.lanczos = 0;
     if (pass_pow2(D)) launch_pass_t<R, true>(dh, tb, plan, ps, Pp, dim3(gx, gy), sm, s);
     else launch_pass_t<R, false>(dh, tb, plan, ps, Pp, dim3(gx, gy), sm, s);
+    *last_gx = (unsigned)gx;
   }
   return FTLM_OK;
 }
@@ -1778,7 +1799,7 @@ static void launch_hv_r(const DevHam &dh, const DevTables<R> &tb, const HvParams
 
 template <typename R>
 static int launch_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &plan, const HvParams &P,
-                      int cap, hipStream_t s) {
+                      int cap, int kc, unsigned *last_gx, hipStream_t s) {
   const HamGeom &g = dh.geom;
   if (!plan.d_plist || plan.passes.empty()) return FTLM_EINVAL;
   for (const WinPass &W : plan.passes) {
@@ -1794,8 +1815,15 @@ static int launch_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &p
       hipLaunchKernelGGL((hv_half_win<R>), grid, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp);
     } else {
       const size_t sm = sizeof(Cx<R>) * 64 * (size_t)g.n + sizeof(R) * 64 * g.n;
-      hipLaunchKernelGGL((hv_gen_win<R>), grid, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp);
+      const dim3 gk(gx, P.K / kc);
+      switch (kc) {
+        case 8: hipLaunchKernelGGL((hv_gen_win<R, 8>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp); break;
+        case 4: hipLaunchKernelGGL((hv_gen_win<R, 4>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp); break;
+        case 2: hipLaunchKernelGGL((hv_gen_win<R, 2>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp); break;
+        default: hipLaunchKernelGGL((hv_gen_win<R, 1>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp); break;
+      }
     }
+    *last_gx = gx;
   }
   return FTLM_OK;
 }
@@ -1808,7 +1836,7 @@ static size_t hv_tile_win_smem(const HamGeom &g, const WinPass &W) {
 
 template <typename R>
 static int launch_tile_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &plan, const HvParams &P,
-                           int cap, hipStream_t s) {
+                           int cap, unsigned *last_gx, hipStream_t s) {
   const HamGeom &g = dh.geom;
   if (!plan.d_plist || plan.passes.empty() || !g.spin_half || g.n <= kTileBits) return FTLM_EINVAL;
   for (const WinPass &W : plan.passes) {
@@ -1826,6 +1854,7 @@ static int launch_tile_win(const DevHam &dh, const DevTables<R> &tb, const WinPl
       granted = sm;
     }
     hipLaunchKernelGGL((hv_tile_win<R>), dim3(gx, P.K), dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp);
+    *last_gx = gx;
   }
   return FTLM_OK;
 }
@@ -1867,30 +1896,39 @@ int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
     P.yre_out = L.lz->yre_out;
     P.yim_out = L.lz->yim_out;
   }
+  // the grid of the last dispatch and its columns per lane, for the Lanczos
+  // finishing kernel (alpha_j, y_j from the per-block partials)
+  unsigned fin_gx = (unsigned)gx, fin_gy = (unsigned)gy;
+  int fin_kc = kc;
+  int rc = FTLM_OK;
   if (L.variant == 5) {
     const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
-    int rc = (L.precision == FTLM_C64) ? launch_tile_win<float>(dh, dh.t32, dh.tw32, P, cap, s)
-                                       : launch_tile_win<double>(dh, dh.t64, dh.tw64, P, cap, s);
-    if (rc) return rc;
-    return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
-  }
-  if (L.variant == 4) {
+    rc = (L.precision == FTLM_C64) ? launch_tile_win<float>(dh, dh.t32, dh.tw32, P, cap, &fin_gx, s)
+                                   : launch_tile_win<double>(dh, dh.t64, dh.tw64, P, cap, &fin_gx, s);
+    fin_gy = (unsigned)L.K;
+    fin_kc = 1;
+  } else if (L.variant == 4) {
     const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
-    int rc = (L.precision == FTLM_C64) ? launch_win<float>(dh, dh.t32, dh.win32, P, cap, s)
-                                       : launch_win<double>(dh, dh.t64, dh.win64, P, cap, s);
-    if (rc) return rc;
-    return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
-  }
-  if (use_passes(dh.geom, L.K, L.variant)) {
+    // general radix: kc columns per lane (the spin-1/2 window kernel takes one)
+    const int wkc = dh.geom.spin_half ? 1 : kc;
+    rc = (L.precision == FTLM_C64) ? launch_win<float>(dh, dh.t32, dh.win32, P, cap, wkc, &fin_gx, s)
+                                   : launch_win<double>(dh, dh.t64, dh.win64, P, cap, wkc, &fin_gx, s);
+    fin_gy = (unsigned)(L.K / wkc);
+    fin_kc = wkc;
+  } else if (use_passes(dh.geom, L.K, L.variant)) {
     const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
-    int rc = (L.precision == FTLM_C64) ? launch_passes<float>(dh, dh.t32, dh.plan32, P, L.K, cap, s)
-                                       : launch_passes<double>(dh, dh.t64, dh.plan64, P, L.K, cap, s);
-    if (rc) return rc;
-    return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
+    rc = (L.precision == FTLM_C64) ? launch_passes<float>(dh, dh.t32, dh.plan32, P, L.K, cap, &fin_gx, s)
+                                   : launch_passes<double>(dh, dh.t64, dh.plan64, P, L.K, cap, &fin_gx, s);
+    fin_gy = (unsigned)L.K;
+    fin_kc = 1;
+  } else {
+    dim3 grid(gx, gy);
+    if (L.precision == FTLM_C64) launch_hv_r<float>(dh, dh.t32, P, grid, kc, s);
+    else launch_hv_r<double>(dh, dh.t64, P, grid, kc, s);
+    if (use_tile(dh.geom, L.K)) fin_kc = 1;
   }
-  dim3 grid(gx, gy);
-  if (L.precision == FTLM_C64) launch_hv_r<float>(dh, dh.t32, P, grid, kc, s);
-  else launch_hv_r<double>(dh, dh.t64, P, grid, kc, s);
+  if (rc) return rc;
+  if (P.lanczos) launch_hv_finish(P, fin_gx, fin_gy, fin_kc, s);
   return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
 }
 
@@ -1964,15 +2002,17 @@ __global__ __launch_bounds__(kBlock) void start_kernel(StartParams S) {
       red[0][q] += (double)z.re * (double)z.re + (double)z.im * (double)z.im;
     }
   }
-  const unsigned total = gridDim.x * gridDim.y;
-  if (block_partials<1, KC>(red, S.part, blockIdx.y * gridDim.x + blockIdx.x, S.counter, total)) {
-    const int ncol = gridDim.y * KC;
-    for (int c = 0; c < ncol; c++) {
-      const int cb = c / KC, q = c % KC;
-      const double s = block_sum_strided(S.part + (size_t)cb * gridDim.x * KC + q, gridDim.x, KC);
-      if (threadIdx.x == 0) S.sx0[c] = s > 0 ? 1.0 / sqrt(s) : 0.0;
-    }
-    if (threadIdx.x == 0) *S.counter = 0u;
+  block_partials_store<1, KC>(red, S.part, blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// One block: sx0 = 1/|r| of every column from the start kernel's partials.
+template <int KC>
+__global__ __launch_bounds__(kBlock) void start_finish(StartParams S, unsigned gx, unsigned gy) {
+  const int ncol = gy * KC;
+  for (int c = 0; c < ncol; c++) {
+    const int cb = c / KC, q = c % KC;
+    const double s = block_sum_strided(S.part + (size_t)cb * gx * KC + q, gx, KC);
+    if (threadIdx.x == 0) S.sx0[c] = s > 0 ? 1.0 / sqrt(s) : 0.0;
   }
 }
 
@@ -1987,6 +2027,12 @@ static void launch_start_r(const StartParams &S, int grid_cap, hipStream_t s) {
     case 4: hipLaunchKernelGGL((start_kernel<R, 4, COPY>), grid, dim3(kBlock), 0, s, S); break;
     case 2: hipLaunchKernelGGL((start_kernel<R, 2, COPY>), grid, dim3(kBlock), 0, s, S); break;
     default: hipLaunchKernelGGL((start_kernel<R, 1, COPY>), grid, dim3(kBlock), 0, s, S); break;
+  }
+  switch (kc) {
+    case 8: hipLaunchKernelGGL(start_finish<8>, dim3(1), dim3(kBlock), 0, s, S, grid.x, grid.y); break;
+    case 4: hipLaunchKernelGGL(start_finish<4>, dim3(1), dim3(kBlock), 0, s, S, grid.x, grid.y); break;
+    case 2: hipLaunchKernelGGL(start_finish<2>, dim3(1), dim3(kBlock), 0, s, S, grid.x, grid.y); break;
+    default: hipLaunchKernelGGL(start_finish<1>, dim3(1), dim3(kBlock), 0, s, S, grid.x, grid.y); break;
   }
 }
 
@@ -2076,35 +2122,38 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs A) {
       red[0][q] += (double)u.re * (double)u.re + (double)u.im * (double)u.im;
     }
   }
-  const unsigned total = gridDim.x * gridDim.y;
-  if (block_partials<1, KC>(red, A.part, blockIdx.y * gridDim.x + blockIdx.x, A.counter, total)) {
-    const int ncol = gridDim.y * KC;
-    for (int c = 0; c < ncol; c++) {
-      const int cb = c / KC, q = c % KC;
-      const double s = block_sum_strided(A.part + (size_t)cb * gridDim.x * KC + q, gridDim.x, KC);
-      if (threadIdx.x != 0) continue;
-      double b = sqrt(s);
-      const double al = fabs(A.alpha[c]);
-      double sm = A.scale_max[c];
-      if (al > sm) sm = al;
-      if (A.done[c]) {
-        A.beta[c] = 0.0;
+  block_partials_store<1, KC>(red, A.part, blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// One block: beta_j = |u| from the update kernel's per-block partials (layout
+// [cb][bx][KC]), the next scale 1/beta_j and the breakdown test.
+template <int KC>
+__global__ __launch_bounds__(kBlock) void update_finish(UpdateArgs A, unsigned gx, unsigned gy) {
+  const int ncol = gy * KC;
+  for (int c = 0; c < ncol; c++) {
+    const int cb = c / KC, q = c % KC;
+    const double s = block_sum_strided(A.part + (size_t)cb * gx * KC + q, gx, KC);
+    if (threadIdx.x != 0) continue;
+    double b = sqrt(s);
+    const double al = fabs(A.alpha[c]);
+    double sm = A.scale_max[c];
+    if (al > sm) sm = al;
+    if (A.done[c]) {
+      A.beta[c] = 0.0;
+      A.sx_next[c] = 0.0;
+    } else {
+      A.n_used[c] = A.step + 1;
+      const bool breakdown = (A.step + 1 < A.n_lanczos) && !(b > 1e-12 * sm);
+      A.beta[c] = b;
+      if (breakdown) {
+        A.done[c] = 1;
         A.sx_next[c] = 0.0;
       } else {
-        A.n_used[c] = A.step + 1;
-        const bool breakdown = (A.step + 1 < A.n_lanczos) && !(b > 1e-12 * sm);
-        A.beta[c] = b;
-        if (breakdown) {
-          A.done[c] = 1;
-          A.sx_next[c] = 0.0;
-        } else {
-          A.sx_next[c] = b > 0 ? 1.0 / b : 0.0;
-        }
-        if (b > sm) sm = b;
+        A.sx_next[c] = b > 0 ? 1.0 / b : 0.0;
       }
-      A.scale_max[c] = sm;
+      if (b > sm) sm = b;
     }
-    if (threadIdx.x == 0) *A.counter = 0u;
+    A.scale_max[c] = sm;
   }
 }
 
@@ -2131,6 +2180,12 @@ int launch_update(const UpdateArgs &a, hipStream_t s) {
       if (f32) hipLaunchKernelGGL((update_kernel<float, 1>), grid, dim3(kBlock), 0, s, a);
       else hipLaunchKernelGGL((update_kernel<double, 1>), grid, dim3(kBlock), 0, s, a);
       break;
+  }
+  switch (kc) {
+    case 8: hipLaunchKernelGGL(update_finish<8>, dim3(1), dim3(kBlock), 0, s, a, grid.x, grid.y); break;
+    case 4: hipLaunchKernelGGL(update_finish<4>, dim3(1), dim3(kBlock), 0, s, a, grid.x, grid.y); break;
+    case 2: hipLaunchKernelGGL(update_finish<2>, dim3(1), dim3(kBlock), 0, s, a, grid.x, grid.y); break;
+    default: hipLaunchKernelGGL(update_finish<1>, dim3(1), dim3(kBlock), 0, s, a, grid.x, grid.y); break;
   }
   return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
 }

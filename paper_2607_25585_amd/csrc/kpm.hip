@@ -62,12 +62,14 @@ __global__ __launch_bounds__(kBlock) void cheb_kernel(int mode, uint32_t dim, co
     red[0][0] += (double)tv.re * orr + (double)tv.im * oi;
     red[1][0] += (double)o.re * orr + (double)o.im * oi;
   }
-  if (block_partials<2, 1>(red, part, blockIdx.x, counter, gridDim.x)) {
-    for (int k = 0; k < 2; k++) {
-      const double s = block_sum_strided(part + k, gridDim.x, 2);
-      if (threadIdx.x == 0) mom[k] = s;
-    }
-    if (threadIdx.x == 0) *counter = 0u;
+  block_partials_store<2, 1>(red, part, blockIdx.x);
+}
+
+// One block: the two moments from the Chebyshev kernel's per-block partials.
+__global__ __launch_bounds__(kBlock) void cheb_finish(const double *part, unsigned gx, double *mom) {
+  for (int k = 0; k < 2; k++) {
+    const double s = block_sum_strided(part + k, gx, 2);
+    if (threadIdx.x == 0) mom[k] = s;
   }
 }
 
@@ -208,7 +210,7 @@ void make_kplan(const ftlm_hamiltonian *h, const ftlm_run_params *p, int n_momen
   pl.done = c.take(sizeof(int));
   pl.nused = c.take(sizeof(int));
   pl.part = c.take(sd * 2048 * 3);
-  pl.counter = c.take(sizeof(unsigned) * 4);
+  pl.counter = c.take(sizeof(unsigned) * kCounterWords);
   pl.eps = c.take(sd * pl.NB);
   pl.q1 = c.take(sd * pl.NB);
   pl.qy = c.take(sd * pl.NB);
@@ -323,6 +325,7 @@ int ftlm_run_kpm(const ftlm_hamiltonian *hc, const ftlm_run_params *p, int32_t n
                          reinterpret_cast<const Cx<double> *>(y), reinterpret_cast<Cx<double> *>(o),
                          reinterpret_cast<const Cx<double> *>(T0), reinterpret_cast<const Cx<double> *>(OV), ab,
                          part, counter, mom);
+    hipLaunchKernelGGL(cheb_finish, dim3(1), dim3(kBlock), 0, s, part, grid, mom);
     return hipGetLastError() == hipSuccess;
   };
   auto hv = [&](const char *x, char *w) {
@@ -339,7 +342,7 @@ int ftlm_run_kpm(const ftlm_hamiltonian *hc, const ftlm_run_params *p, int32_t n
       if (rc) return fail(rc, std::string("set_field: ") + ftlm_last_error());
     }
     // 1. spectral bounds from N_B Lanczos steps on the first random vector
-    if (launch_zero_state(at3<double>(ws, pl.smax), at3<int>(ws, pl.done), at3<int>(ws, pl.nused), counter, 4, 1, s))
+    if (launch_zero_state(at3<double>(ws, pl.smax), at3<int>(ws, pl.done), at3<int>(ws, pl.nused), counter, kCounterWords, 1, s))
       return fail(FTLM_EHIP, "zero_state launch failed");
     rc = launch_gaussian(p->seed, p->instance, (uint32_t)f, 0, 1, dim, pl.prec, B3[0], part, counter,
                          at3<double>(ws, pl.sx), 0, s);

@@ -83,7 +83,7 @@ void make_plan(const ftlm_hamiltonian *h, const ftlm_run_params *p, RunPlan &pl)
   pl.done = c.take(sizeof(int) * pl.K);
   pl.nused = c.take(sizeof(int) * pl.K);
   pl.part = c.take(sizeof(double) * 2048 * 3 * pl.K);
-  pl.counter = c.take(sizeof(unsigned) * 4);
+  pl.counter = c.take(sizeof(unsigned) * kCounterWords);
   const size_t sR = sizeof(double) * pl.R;
   pl.eps = c.take(sR * pl.NL);
   pl.q1 = c.take(sR * pl.NL);
@@ -242,7 +242,7 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
     for (int c0 = 0; c0 < pl.R; c0 += pl.K) {
       const int K = std::min(pl.K, pl.R - c0);
       if (launch_zero_state(at<double>(ws, pl.smax), at<int>(ws, pl.done), at<int>(ws, pl.nused),
-                            at<unsigned>(ws, pl.counter), 4, K, s))
+                            at<unsigned>(ws, pl.counter), kCounterWords, K, s))
         return fail(FTLM_EHIP, "zero_state launch failed");
       void *x0 = at<char>(ws, pl.buf[0]);
       if (p->r_init) {

@@ -318,7 +318,7 @@ void make_splan(const ftlm_hamiltonian *h, const ftlm_run_params *p, SPlan &pl) 
   pl.done = c.take(sizeof(int));
   pl.nused = c.take(sizeof(int));
   pl.part = c.take(sd * 2048 * 3);
-  pl.counter = c.take(sizeof(unsigned) * 4);
+  pl.counter = c.take(sizeof(unsigned) * kCounterWords);
   pl.gpart = c.take(sizeof(double2) * (size_t)pl.nsplit * pl.NL * pl.NL);
   pl.eps = c.take(sd * (size_t)pl.R * pl.NL);
   pl.Q = c.take(sd * (size_t)pl.R * pl.NL * pl.NL);
@@ -436,7 +436,7 @@ int ftlm_run_sftlm(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *w
     for (int r = 0; r < pl.R; r++) {
       const int pair = r >> 1, rev = r & 1;
       if (launch_zero_state(at2<double>(ws, pl.smax), at2<int>(ws, pl.done), at2<int>(ws, pl.nused),
-                            at2<unsigned>(ws, pl.counter), 4, 1, s))
+                            at2<unsigned>(ws, pl.counter), kCounterWords, 1, s))
         return fail(FTLM_EHIP, "zero_state launch failed");
       // start vector: Gaussian (pair index as the vector index) or its time reverse
       char *dst0 = rev ? V + vbytes : V;

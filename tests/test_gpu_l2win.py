@@ -133,3 +133,25 @@ def test_tile_window_full_size_sampled_rows(monkeypatch):
     sysm, _ = W.cfg2()
     _sampled(sysm, F().FTLM_C128, 1e-12)
     _sampled(sysm, F().FTLM_C64, 2e-5)
+
+
+@pytest.mark.parametrize("K", [2, 4, 8])
+def test_l2win_columns_general_radix(K):
+    """Variant 4 with K interleaved columns (general radix: K/kc column blocks of
+    kc columns per lane), tiny windows, every column against the oracle; and a
+    Lanczos run whose epilogue reduces kc columns per lane."""
+    rng = np.random.default_rng(3100 + K)
+    sysm = W.random_small_system(rng, 6, max_two_s=3)
+    ham = F().Hamiltonian(sysm)
+    v = rng.standard_normal((ham.dim, K)) + 1j * rng.standard_normal((ham.dim, K))
+    oh = of.Ham(sysm)
+    w = ham.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+    for c in range(K):
+        assert rel_max(w[:, c], oh.apply(v[:, c])) < 1e-12, c
+    T = W.t_grid(20)
+    got = F().run(ham, K, 25, T, seed=8, columns=K)
+    ref = of.ftlm(sysm, K, 25, T, seed=8)[0]
+    for key in ("lnZ", "E", "C", "M"):
+        r = np.asarray(ref[key])
+        err = np.max(np.abs(got[key][0] - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max()))
+        assert err < 1e-8, key
