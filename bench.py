@@ -34,8 +34,12 @@ HBM_PEAK_GBPS = 8000.0
 
 
 def _kernel_sha():
-    p = os.path.join(ROOT, "paper_2607_25585_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the sources that define the H*v kernels (kernels, their shared
+    device helpers and internal header)."""
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "device_reduce.hpp", "ftlm_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2607_25585_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _traffic(workload, precision):

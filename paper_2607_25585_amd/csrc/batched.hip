@@ -4,8 +4,8 @@
 // persistent H*v launch over a work queue of (item, row chunk) units for all
 // items of the wave, followed by one persistent update launch; both are
 // replayed from a captured HIP graph.  Reductions are per item and fixed-order:
-// each unit writes its partial sums, and the last unit of an item to finish sums
-// the item's partials in unit order.
+// each unit stores its partial sums, and a finishing launch (one block per
+// item) sums the item's partials in unit order.
 //
 // Vectors of an item are column-interleaved [dim][K], so a gather of one partner
 // row reads K contiguous complex numbers and every coefficient serves K columns.
@@ -18,11 +18,15 @@
 #include <string>
 #include <vector>
 
+#include "device_reduce.hpp"
 #include "ftlm_internal.hpp"
 
 namespace ftlm {
 
-constexpr uint32_t kUnitRows = 16384;  // rows per work unit (64 tiles of 256)
+// Rows per work unit (8 tiles of 256).  Units are laid out item by item and the
+// grid is kept small enough that the units in flight at any time cover about
+// two large items, so the partners an item's gathers touch stay in the caches.
+constexpr uint32_t kUnitRows = 2048;
 
 template <typename R>
 struct BItem {
@@ -48,7 +52,7 @@ struct BStep {
   double *smax;
   int *done, *nused;
   double *part;                        // [n_units][3][K]
-  unsigned *counter;                   // [n_items]
+  uint32_t n_items;                    // items of the wave (blocks of the finishing launch)
   const int *unit_item;                // [n_units]
 };
 
@@ -202,46 +206,6 @@ __device__ __forceinline__ void brow(const BItem<R> &it, bool moment, uint32_t r
   }
 }
 
-__device__ __forceinline__ double bwave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Block-reduces NV*KC values, writes them to part[u], and returns true on the
-// block that completes the last unit of its item (that block then reduces).
-template <int NV, int KC>
-__device__ __forceinline__ bool bunit_partials(const double (&val)[NV][KC], double *part, uint32_t u,
-                                               unsigned *counter, unsigned nunit) {
-  __shared__ double red[kBlock / 64][NV * KC];
-  __shared__ bool last;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int a = 0; a < NV; a++)
-#pragma unroll
-    for (int q = 0; q < KC; q++) {
-      const double s = bwave_sum(val[a][q]);
-      if (lane == 0) red[wv][a * KC + q] = s;
-    }
-  __syncthreads();
-  if (threadIdx.x < NV * KC) {
-    double s = 0;
-    for (int w2 = 0; w2 < kBlock / 64; w2++) s += red[w2][threadIdx.x];
-    part[(size_t)u * NV * KC + threadIdx.x] = s;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == nunit - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  const bool out = last;
-  __syncthreads();
-  return out;
-}
-
 // ------------------------------------------------------------------ kernels
 template <typename R, int KC>
 __global__ __launch_bounds__(kBlock) void bstart_kernel(const BItem<R> *__restrict__ items, BStep S) {
@@ -282,14 +246,8 @@ __global__ __launch_bounds__(kBlock) void bstart_kernel(const BItem<R> *__restri
         red[0][q] += (double)z.re * (double)z.re + (double)z.im * (double)z.im;
       }
     }
-    if (bunit_partials<1, KC>(red, S.part, u, S.counter + ii, it.nunit)) {
-      for (int q = threadIdx.x; q < KC; q += kBlock) {
-        double s = 0;
-        for (uint32_t v2 = 0; v2 < it.nunit; v2++) s += S.part[(size_t)(it.unit0 + v2) * KC + q];
-        S.sx_cur[it.col0 + q] = s > 0 ? 1.0 / sqrt(s) : 0.0;
-      }
-      if (threadIdx.x == 0) S.counter[ii] = 0u;
-    }
+    block_partials_store<1, KC>(red, S.part, u);
+    __syncthreads();  // the block's LDS partials are reused by the next unit
   }
 }
 
@@ -339,18 +297,8 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       }
     }
     if (moment) continue;  // uniform over the launch
-    if (bunit_partials<3, KC>(red, S.part, u, S.counter + ii, it.nunit)) {
-      for (int idx = threadIdx.x; idx < 3 * KC; idx += kBlock) {
-        const int a = idx / KC, q = idx % KC;
-        double s = 0;
-        for (uint32_t v2 = 0; v2 < it.nunit; v2++) s += S.part[((size_t)(it.unit0 + v2) * 3 + a) * KC + q];
-        s *= sx[q];
-        if (a == 0) S.alpha[it.col0 + q] = s;
-        else if (a == 1) S.yre[it.col0 + q] = s;
-        else S.yim[it.col0 + q] = s;
-      }
-      if (threadIdx.x == 0) S.counter[ii] = 0u;
-    }
+    block_partials_store<3, KC>(red, S.part, u);
+    __syncthreads();  // the block's LDS partials are reused by the next unit
   }
 }
 
@@ -379,45 +327,63 @@ __global__ __launch_bounds__(kBlock) void bupdate_kernel(const BItem<R> *__restr
         red[0][q] += (double)uu.re * (double)uu.re + (double)uu.im * (double)uu.im;
       }
     }
-    if (bunit_partials<1, KC>(red, S.part, u, S.counter + ii, it.nunit)) {
-      for (int q = threadIdx.x; q < KC; q += kBlock) {
-        const int c = it.col0 + q;
-        double s = 0;
-        for (uint32_t v2 = 0; v2 < it.nunit; v2++) s += S.part[(size_t)(it.unit0 + v2) * KC + q];
-        const double b = sqrt(s);
-        double sm = S.smax[c];
-        const double al = fabs(S.alpha[c]);
-        if (al > sm) sm = al;
-        if (S.done[c]) {
-          S.beta[c] = 0.0;
+    block_partials_store<1, KC>(red, S.part, u);
+    __syncthreads();  // the block's LDS partials are reused by the next unit
+  }
+}
+
+// One block per item: the item's per-unit partials summed in unit order, then
+// the step's per-column scalars.  kind 0: start-vector norms -> sx; 1: alpha
+// and <O v_1, v_j> (already scaled by sx); 2: beta, breakdown and the next
+// scale.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void bfinish_kernel(const BItem<R> *__restrict__ items, BStep S, int kind) {
+  const BItem<R> &it = items[blockIdx.x];
+  const int K = S.K, j = S.step;
+  const int nv = kind == 1 ? 3 : 1;
+  for (int idx = 0; idx < nv * K; idx++) {  // whole block, fixed order over the item's units
+    const int a = idx / K, q = idx % K, c = it.col0 + q;
+    const double s = block_sum_strided(S.part + ((size_t)it.unit0 * nv + a) * K + q, it.nunit, (size_t)nv * K);
+    if (threadIdx.x != 0) continue;
+    if (kind == 0) {
+      S.sx_cur[c] = s > 0 ? 1.0 / sqrt(s) : 0.0;
+    } else if (kind == 1) {
+      const double v = s * S.sx_cur[c];
+      if (a == 0) S.alpha[c] = v;
+      else if (a == 1) S.yre[c] = v;
+      else S.yim[c] = v;
+    } else {
+      const double b = sqrt(s);
+      double sm = S.smax[c];
+      const double al = fabs(S.alpha[c]);
+      if (al > sm) sm = al;
+      if (S.done[c]) {
+        S.beta[c] = 0.0;
+        S.sx_next[c] = 0.0;
+      } else {
+        S.nused[c] = j + 1;
+        const bool breakdown = (j + 1 < S.n_lanczos) && !(b > 1e-12 * sm);
+        S.beta[c] = b;
+        if (breakdown) {
+          S.done[c] = 1;
           S.sx_next[c] = 0.0;
         } else {
-          S.nused[c] = j + 1;
-          const bool breakdown = (j + 1 < S.n_lanczos) && !(b > 1e-12 * sm);
-          S.beta[c] = b;
-          if (breakdown) {
-            S.done[c] = 1;
-            S.sx_next[c] = 0.0;
-          } else {
-            S.sx_next[c] = b > 0 ? 1.0 / b : 0.0;
-          }
-          if (b > sm) sm = b;
+          S.sx_next[c] = b > 0 ? 1.0 / b : 0.0;
         }
-        S.smax[c] = sm;
+        if (b > sm) sm = b;
       }
-      if (threadIdx.x == 0) S.counter[ii] = 0u;
+      S.smax[c] = sm;
     }
   }
 }
 
-__global__ void bzero_kernel(double *smax, int *done, int *nused, unsigned *counter, int ncol, int nitems) {
+__global__ void bzero_kernel(double *smax, int *done, int *nused, int ncol) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ncol) {
     smax[i] = 0.0;
     done[i] = 0;
     nused[i] = 0;
   }
-  if (i < nitems) counter[i] = 0u;
 }
 
 // ------------------------------------------------------------------ host driver
@@ -573,7 +539,7 @@ void make_plan_b(const ftlm_hamiltonian *const *hs, int n_inst, const ftlm_run_p
   }
 }
 
-// per-wave dynamic part: item array, unit map, scalars, partials, counters, tridiag scratch
+// per-wave dynamic part: item array, unit map, scalars, partials, tridiag scratch
 size_t wave_meta_bytes(size_t n_items, size_t n_units, int K, int NL) {
   const size_t ncol = n_items * (size_t)K;
   Carve c;
@@ -584,7 +550,6 @@ size_t wave_meta_bytes(size_t n_items, size_t n_units, int K, int NL) {
   c.take(sizeof(double) * ncol);                // smax
   c.take(sizeof(int) * ncol * 2);               // done, nused
   c.take(sizeof(double) * n_units * 3 * K);     // partials
-  c.take(sizeof(unsigned) * n_items);           // counters
   c.take(sizeof(double) * 4 * NL * ncol);       // tridiagonal scratch
   return (c.off + 255) & ~size_t(255);
 }
@@ -625,6 +590,8 @@ void launch_b(int kind, dim3 grid, const BItem<R> *items, const BStep &S, hipStr
   if (kind == 0) hipLaunchKernelGGL((bstart_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
   else if (kind == 1) hipLaunchKernelGGL((bhv_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
   else hipLaunchKernelGGL((bupdate_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
+  if (kind != 1 || S.mode == 1)  // O v_1 has no reductions
+    hipLaunchKernelGGL((bfinish_kernel<R>), dim3(S.n_items), dim3(kBlock), 0, s, items, S, kind);
 }
 
 template <typename R>
@@ -786,7 +753,6 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
     const size_t o_done = c.take(sizeof(int) * ncol);
     const size_t o_nused = c.take(sizeof(int) * ncol);
     const size_t o_part = c.take(sizeof(double) * units * 3 * K);
-    const size_t o_cnt = c.take(sizeof(unsigned) * nit);
     const size_t o_tri = c.take(sizeof(double) * 4 * NL * ncol);
     const size_t meta_end = (c.off + 255) & ~size_t(255);
     unsigned char *wbase = base + pl.fixed;
@@ -850,14 +816,16 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       set_error("copy of wave descriptors failed");
       return FTLM_EHIP;
     }
-    const uint32_t gx = (uint32_t)std::min<size_t>(units, 4096);
+    uint32_t gcap = 1024;
+    if (const char *e = std::getenv("FTLM_BATCH_GRID")) gcap = (uint32_t)std::max(64, std::atoi(e));
+    const uint32_t gx = (uint32_t)std::min<size_t>(units, gcap);
     BStep S{};
     S.K = K;
     S.n_lanczos = NL;
     S.n_units = (uint32_t)units;
     S.seed = pp[0].seed;
     S.part = reinterpret_cast<double *>(wbase + o_part);
-    S.counter = reinterpret_cast<unsigned *>(wbase + o_cnt);
+    S.n_items = (uint32_t)nit;
     S.unit_item = reinterpret_cast<const int *>(wbase + o_umap);
     S.smax = reinterpret_cast<double *>(wbase + o_smax);
     S.done = reinterpret_cast<int *>(wbase + o_done);
@@ -868,8 +836,8 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
     double *yim = reinterpret_cast<double *>(wbase + o_yim);
     double *sx = reinterpret_cast<double *>(wbase + o_sx);
     const void *ditems = wbase + o_items;
-    hipLaunchKernelGGL(bzero_kernel, dim3((std::max(ncol, nit) + 255) / 256), dim3(256), 0, s, S.smax, S.done,
-                       S.nused, S.counter, (int)ncol, (int)nit);
+    hipLaunchKernelGGL(bzero_kernel, dim3((ncol + 255) / 256), dim3(256), 0, s, S.smax, S.done, S.nused,
+                       (int)ncol);
     // start vectors (norms -> sx[0]) and O v_1
     BStep S0 = S;
     S0.sx_cur = sx;

@@ -1,7 +1,7 @@
 // Fixed-order device reductions shared by the HIP kernels: wave butterflies,
-// then the block's waves in order, then per-block partials summed in block
-// order by the last block to finish (device-wide counter), so every dot
-// product is bitwise reproducible run to run.
+// then the block's waves in order, then per-block partials stored to memory and
+// summed in block order by a finishing launch, so every dot product is bitwise
+// reproducible run to run.
 #pragma once
 
 #include <hip/hip_runtime.h>
