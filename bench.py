@@ -187,7 +187,12 @@ def surrogate_report(n_train, n_test, train_s):
     ptrain = W.cfg5_params(n_train, seed=5000)
     ptest = W.cfg5_params(n_test, seed=5001)
     t0 = time.perf_counter()
-    lz, mm, cc = S.generate_dataset(ptrain, T, spec.R, spec.n_lanczos, seed=spec.seed, chunk=256)
+    parts = []
+    for a in range(0, n_train, 1024):  # chunk seeds depend only on the row offset
+        parts.append(S.generate_dataset(ptrain[a:a + 1024], T, spec.R, spec.n_lanczos, seed=spec.seed + a,
+                                        chunk=256))
+        print("surrogate: %d training curves" % min(n_train, a + 1024), file=sys.stderr, flush=True)
+    lz, mm, cc = (np.concatenate([p[i] for p in parts]) for i in range(3))
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     print("surrogate: %d training curves in %.1f s" % (n_train, t_gen), file=sys.stderr, flush=True)
@@ -204,6 +209,7 @@ def surrogate_report(n_train, n_test, train_s):
         m = S.MLP(seed=seed)
         losses.append(S.train(m, x, y, epochs=400, batch=4096, lr=2e-3, seed=seed, time_budget_s=train_s)[-1])
         models.append(m)
+        print("surrogate: member %d trained" % seed, file=sys.stderr, flush=True)
     t_train = time.perf_counter() - t0
     print("surrogate: trained in %.1f s" % t_train, file=sys.stderr, flush=True)
     ens = S.Surrogate(models, disagreement=0.05)

@@ -101,8 +101,9 @@ int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, con
  * the caller's device buffers v, w ([dim][n_cols], as ftlm_apply) -- variants
  * 1 = direct gather (columns per lane 1, 2, 4, 8), 2 = windowed LDS passes,
  * 3 = LDS tile (spin 1/2, N >= 11), 4 = L2-window passes (one column), 5 = LDS
- * tile walked over L2 windows (spin 1/2, N >= 12), each at 512, 1024, 2048 and
- * 4096 blocks (variants 4, 5: at most 2048) --
+ * tile walked over L2 windows (spin 1/2, N >= 12; 256 or 512 threads per tile,
+ * given in the columns-per-lane field as 1 or 2 row groups), each at 512, 1024,
+ * 2048 and 4096 blocks (variants 4, 5: at most 2048) --
  * with HIP events on the stream (blocking), and stores the fastest in the handle
  * for later ftlm_apply / ftlm_run launches of the same shape.  Outputs (may be
  * NULL): the chosen variant, grid size, columns per lane and its mean time. */

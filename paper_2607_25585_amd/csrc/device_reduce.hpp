@@ -16,15 +16,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-level fixed-order sums of NV*KC per-lane values, stored to
+// Block-level (NT threads) fixed-order sums of NV*KC per-lane values, stored to
 // part[slot*NV*KC ...] with plain stores.  The grid-level sum runs in a
 // separate finishing kernel launched behind this one on the same stream (the
 // kernel boundary orders the stores): no device-scope fence or atomic per
 // block, which on this GPU cost a write-back of the L2 each and serialise the
 // grid's tail.
-template <int NV, int KC>
+template <int NV, int KC, int NT = kBlock>
 __device__ __forceinline__ void block_partials_store(const double (&val)[NV][KC], double *part, int slot) {
-  __shared__ double red[kBlock / 64][NV * KC];
+  __shared__ double red[NT / 64][NV * KC];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int a = 0; a < NV; a++)
@@ -36,7 +36,7 @@ __device__ __forceinline__ void block_partials_store(const double (&val)[NV][KC]
   __syncthreads();
   if (threadIdx.x < NV * KC) {
     double s = 0;
-    for (int w2 = 0; w2 < kBlock / 64; w2++) s += red[w2][threadIdx.x];
+    for (int w2 = 0; w2 < NT / 64; w2++) s += red[w2][threadIdx.x];
     part[(size_t)slot * NV * KC + threadIdx.x] = s;
   }
 }

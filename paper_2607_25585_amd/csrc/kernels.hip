@@ -118,10 +118,10 @@ __device__ __forceinline__ void hv_epilogue(const HvParams &P, uint32_t row, int
   }
 }
 
-template <int KC>
+template <int KC, int NT = kBlock>
 __device__ __forceinline__ void hv_finish(const HvParams &P, double (&red)[3][KC]) {
   if (!P.lanczos) return;
-  block_partials_store<3, KC>(red, P.part, blockIdx.y * gridDim.x + blockIdx.x);
+  block_partials_store<3, KC, NT>(red, P.part, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // One block: alpha_j and y_j of every column from the H*v kernel's per-block
@@ -1184,133 +1184,187 @@ __global__ __launch_bounds__(kBlock) void hv_half_win(HamGeom g, DevTables<R> tb
   if (W.last) hv_finish<1>(P, red);
 }
 
-// Spin-1/2, N >= 12: the LDS tile kernel (2048-row tiles, 8 rows per thread)
-// walked window by window over the tile bits >= 11, terms restricted to the
-// pass: pairs inside the tile (first pass), then for every outer site a of
-// xmask the partner tile (tile with bit a flipped) staged once for the single
-// flip of a and the mixed pairs (i < 11, a), then pairs of two outer sites read
-// straight from global memory (L2-resident: both sites lie in the window).
-// Slot-bit terms of the tile kernels (rows r = q * 256 + t, q = bits 8..10):
-// the flipped slot bit SB is a compile-time constant, so the partner slot and
-// the coefficient choice per q need no instructions.
+// Spin-1/2, N >= 12: the LDS tile kernel (2048-row tiles) walked window by
+// window over the tile bits >= 11, terms restricted to the pass: pairs inside
+// the tile (first pass), then for every outer site a of xmask the partner tile
+// (tile with bit a flipped) staged once for the single flip of a and the mixed
+// pairs (i < 11, a), then pairs of two outer sites read straight from global
+// memory (L2-resident: both sites lie in the window).
+//
+// Thread layout: a block of 256 G threads holds one tile; thread t = 256 g + l
+// owns the Q = 8 / G rows q 256 + tq, tq = g Q 256 + l: lane part l (row bits
+// 0..7) and slots s = g Q + q (row bits 8..10; g gives the high slot bits).  The
+// tile's LDS bounds the blocks per CU, so G > 1 puts more waves on the same LDS.
+// g is uniform over a wave.  In the slot-bit terms the flipped slot bit SB is a
+// compile-time constant: a flip of a q bit moves to another of the thread's
+// rows, a flip of a g bit to the same row of another group.
 template <typename R>
 __device__ __forceinline__ void fma_cx(Cx<R> &a, const Cx<R> &c, const Cx<R> &x) {
   a.re = fma(c.re, x.re, fma(-c.im, x.im, a.re));
   a.im = fma(c.re, x.im, fma(c.im, x.re, a.im));
 }
 
-// acc[q] += (bit SB of q ? c1 : c0) * src[(q ^ 2^SB) * 256 + tl]
-template <int SB, typename R>
-__device__ __forceinline__ void slot_flip(Cx<R> (&acc)[kRowsPerThread], const Cx<R> *src, int tl, Cx<R> c0,
-                                          Cx<R> c1) {
+// For slot bit SB and Q rows per thread: the flip of the row index q, the flip
+// of the thread offset tq, and the bit's value for row q of group gg.
+template <int SB, int Q>
+__device__ __forceinline__ constexpr int slot_qflip() { return (1 << SB) < Q ? (1 << SB) : 0; }
+template <int SB, int Q>
+__device__ __forceinline__ constexpr int slot_tflip() { return (1 << SB) < Q ? 0 : ((1 << SB) / Q) * Q * kBlock; }
+template <int SB, int Q>
+__device__ __forceinline__ int slot_bit(int q, int gg) {
+  if constexpr ((1 << SB) < Q) return (q >> SB) & 1;
+  else return (gg >> (SB - (Q == 8 ? 3 : Q == 4 ? 2 : Q == 2 ? 1 : 0))) & 1;
+}
+
+// acc[q] += (bit SB of slot ? c1 : c0) * src[row q of offset tq with slot bit SB flipped]
+template <int SB, int G, typename R>
+__device__ __forceinline__ void slot_flip(Cx<R> (&acc)[kRowsPerThread / G], const Cx<R> *src, int gg, int tq,
+                                          Cx<R> c0, Cx<R> c1) {
+  constexpr int Q = kRowsPerThread / G;
+  const int tp = tq ^ slot_tflip<SB, Q>();
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; q++) fma_cx(acc[q], ((q >> SB) & 1) ? c1 : c0, src[(q ^ (1 << SB)) * kBlock + tl]);
+  for (int q = 0; q < Q; q++)
+    fma_cx(acc[q], slot_bit<SB, Q>(q, gg) ? c1 : c0, src[(q ^ slot_qflip<SB, Q>()) * kBlock + tp]);
 }
 
-// two slot bits A < B: acc[q] += cp[(bit A of q) << 1 | bit B of q] * src[(q ^ 2^A ^ 2^B) * 256 + t]
-template <int A, int B, typename R>
-__device__ __forceinline__ void slot_pair(Cx<R> (&acc)[kRowsPerThread], const Cx<R> *src, int t, const Cx<R> *cp) {
-  const Cx<R> c[4] = {cp[0], cp[1], cp[2], cp[3]};
+// two slot bits A < B: acc[q] += cp[(bit A) << 1 | bit B] * src[row with both flipped]
+template <int A, int B, int G, typename R>
+__device__ __forceinline__ void slot_pair(Cx<R> (&acc)[kRowsPerThread / G], const Cx<R> *src, int gg, int tq,
+                                          const Cx<R> *cp) {
+  constexpr int Q = kRowsPerThread / G;
+  const Cx<R> c00 = cp[0], c01 = cp[1], c10 = cp[2], c11 = cp[3];
+  const int tp = tq ^ slot_tflip<A, Q>() ^ slot_tflip<B, Q>();
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; q++)
-    fma_cx(acc[q], c[(((q >> A) & 1) << 1) | ((q >> B) & 1)], src[(q ^ (1 << A) ^ (1 << B)) * kBlock + t]);
+  for (int q = 0; q < Q; q++) {
+    const int ba = slot_bit<A, Q>(q, gg), bb = slot_bit<B, Q>(q, gg);  // selects, no indexed array
+    fma_cx(acc[q], ba ? (bb ? c11 : c10) : (bb ? c01 : c00),
+           src[(q ^ slot_qflip<A, Q>() ^ slot_qflip<B, Q>()) * kBlock + tp]);
+  }
 }
 
-template <typename R>
-__device__ __forceinline__ void slot_flip_any(int sb, Cx<R> (&acc)[kRowsPerThread], const Cx<R> *src, int tl,
-                                              Cx<R> c0, Cx<R> c1) {
-  if (sb == 0) slot_flip<0>(acc, src, tl, c0, c1);
-  else if (sb == 1) slot_flip<1>(acc, src, tl, c0, c1);
-  else slot_flip<2>(acc, src, tl, c0, c1);
+template <int G, typename R>
+__device__ __forceinline__ void slot_flip_any(int sb, Cx<R> (&acc)[kRowsPerThread / G], const Cx<R> *src, int gg,
+                                              int tq, Cx<R> c0, Cx<R> c1) {
+  if (sb == 0) slot_flip<0, G>(acc, src, gg, tq, c0, c1);
+  else if (sb == 1) slot_flip<1, G>(acc, src, gg, tq, c0, c1);
+  else slot_flip<2, G>(acc, src, gg, tq, c0, c1);
 }
 
-template <typename R>
-__global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R> tb, WinPass W,
-                                                         const int4 *__restrict__ plist, HvParams P) {
+// NB pairs of two outer sites: every partner tile row is loaded before the
+// first FMA, so NB Q loads per lane are in flight at once.  The FMAs run in
+// pair order, as a one-at-a-time loop would.
+template <int NB, int G, typename R>
+__device__ __forceinline__ void outer_pairs(Cx<R> (&acc)[kRowsPerThread / G], const int4 *__restrict__ pe,
+                                            uint32_t base, const Cx<R> *__restrict__ pc, const Cx<R> *v,
+                                            size_t K, size_t tk) {
+  constexpr int Q = kRowsPerThread / G;
+  Cx<R> x[NB][Q];
+  Cx<R> c[NB];
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int4 e = pe[b];
+    c[b] = pc[4 * e.x + ((((base >> e.y) & 1) << 1) | ((base >> e.z) & 1))];
+    const Cx<R> *vb = v + (size_t)(base ^ (1u << e.y) ^ (1u << e.z)) * K;
+#pragma unroll
+    for (int q = 0; q < Q; q++) x[b][q] = vb[(size_t)q * kBlock * K + tk];
+  }
+#pragma unroll
+  for (int b = 0; b < NB; b++)
+#pragma unroll
+    for (int q = 0; q < Q; q++) fma_cx(acc[q], c[b], x[b][q]);
+}
+
+template <typename R, int G>
+__global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevTables<R> tb, WinPass W,
+                                                             const int4 *__restrict__ plist, HvParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int Q = kRowsPerThread;
+  constexpr int NT = kBlock * G;           // threads per block
+  constexpr int S = kRowsPerThread;        // slots per tile (row bits 8..10)
+  constexpr int Q = S / G;                 // rows per thread
+  constexpr int NB = 2;                    // outer pairs per batch
   const int n = g.n, n_in = W.np_ll, e_out = W.np_ll + W.np_lh, np = W.np;
   Cx<R> *own = reinterpret_cast<Cx<R> *>(smem);   // [2048]
   Cx<R> *part = own + kTileRows;                  // [2048]
   Cx<R> *s_pc = part + kTileRows;                 // [n_in][4]
-  Cx<R> *s_fmh = s_pc + 4 * n_in;                 // [n][2][Q]
-  Cx<R> *s_hf = s_fmh + 2 * Q * n;                // [n][2]
+  Cx<R> *s_fmh = s_pc + 4 * n_in;                 // [n][2][S]
+  Cx<R> *s_hf = s_fmh + 2 * S * n;                // [n][2]
   R *s_hd = reinterpret_cast<R *>(s_hf + 2 * n);  // [n][2]
-  R *s_dmh = s_hd + 2 * n;                        // [Q]
-  R *s_phi = s_dmh + Q;                           // [8][Q]
-  R *s_term = s_phi + 8 * Q;                      // [32][Q]
+  R *s_dmh = s_hd + 2 * n;                        // [S]
+  R *s_phi = s_dmh + S;                           // [8][S]
+  R *s_term = s_phi + 8 * S;                      // [32][S]
   const int t = threadIdx.x;
+  const int l = t & (kBlock - 1);
+  const int gg = G == 1 ? 0 : __builtin_amdgcn_readfirstlane(t >> 8);
+  const int tq = gg * Q * kBlock + l;  // the thread's row offset in the tile for q = 0
   const int c0 = blockIdx.y;
   const int K = P.K;
   const int4 *pl = plist + W.p0;
-  for (int i = t; i < 4 * n_in; i += kBlock) s_pc[i] = tb.pc_half[4 * pl[i >> 2].x + (i & 3)];
-  for (int i = t; i < 2 * n; i += kBlock) {
+  for (int i = t; i < 4 * n_in; i += NT) s_pc[i] = tb.pc_half[4 * pl[i >> 2].x + (i & 3)];
+  for (int i = t; i < 2 * n; i += NT) {
     s_hf[i] = tb.hflip[i];
     s_hd[i] = tb.hdiag[(i >> 1) * 16 + (i & 1)];
   }
   __syncthreads();
   R dlow = 0;
   if (W.diag) {
-    for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((t >> k) & 1)];
+    for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((l >> k) & 1)];
     for (int p = 0; p < g.npair; p++) {
       const int2 ij = tb.pij[p];
       if (ij.y >= kLowBits) continue;
-      dlow = fma(tb.pzz[p], (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25), dlow);
+      dlow = fma(tb.pzz[p], (((l >> ij.x) ^ (l >> ij.y)) & 1) ? R(-0.25) : R(0.25), dlow);
     }
   }
-  R mlane[kLowBits];
-#pragma unroll
-  for (int i = 0; i < kLowBits; i++) mlane[i] = ((t >> i) & 1) ? R(0.5) : R(-0.5);
   const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v);
   const bool zf = W.smask != 0u;
   double red[3][1] = {{0.0}, {0.0}, {0.0}};
+  const size_t tk = (size_t)tq * K;  // thread offset; the tile bases below are uniform
+  constexpr size_t QS = (size_t)kBlock;  // row step between a thread's rows
 
   win_walk(W, [&](uint32_t win, uint32_t item) {
     const uint32_t base = __builtin_amdgcn_readfirstlane(scatter_bits(item, W.emask) | scatter_bits(win, W.omask));
     __syncthreads();
-    const size_t tk = (size_t)t * K;  // lane offset; the tile bases below are uniform
     {
       const Cx<R> *vb = v + (size_t)base * K + c0;
 #pragma unroll
-      for (int q = 0; q < Q; q++) own[q * kBlock + t] = vb[(size_t)q * kBlock * K + tk];
+      for (int q = 0; q < Q; q++) own[q * kBlock + tq] = vb[q * QS * K + tk];
     }
-    // per-tile uniform parts: rows of slot q have bits 8..10 = q and bits >= 11 = base
+    // per-tile uniform parts: rows of slot s have bits 8..10 = s and bits >= 11 = base
     if (zf)
-      for (int e = t; e < 2 * Q * n; e += kBlock) {
-        const int k = e / (2 * Q), sel = (e / Q) & 1, q = e % Q;
-        const uint32_t rb = base | ((uint32_t)q << kLowBits);
+      for (int e = t; e < 2 * S * n; e += NT) {
+        const int k = e / (2 * S), sel = (e / S) & 1, sl = e % S;
+        const uint32_t rb = base | ((uint32_t)sl << kLowBits);
         R fr = 0, fi = 0;
-        for (int l = kLowBits; l < n; l++) {
-          if (l == k) continue;
-          const R ml = ((rb >> l) & 1) ? R(0.5) : R(-0.5);
-          const Cx<R> c = tb.cz_half[(k * n + l) * 2 + sel];
-          fr = fma(c.re, ml, fr);
-          fi = fma(c.im, ml, fi);
+        for (int j = kLowBits; j < n; j++) {
+          if (j == k) continue;
+          const R mj = ((rb >> j) & 1) ? R(0.5) : R(-0.5);
+          const Cx<R> c = tb.cz_half[(k * n + j) * 2 + sel];
+          fr = fma(c.re, mj, fr);
+          fi = fma(c.im, mj, fi);
         }
         s_fmh[e] = Cx<R>{fr, fi};
       }
     if (W.diag) {
-      if (t < 24 * Q) {
-        const int k = kLowBits + t / Q, q = t % Q;
+      if (t < 24 * S) {
+        const int k = kLowBits + t / S, sl = t % S;
         if (k < n) {
-          const uint32_t rb = base | ((uint32_t)q << kLowBits);
+          const uint32_t rb = base | ((uint32_t)sl << kLowBits);
           const R mk = ((rb >> k) & 1) ? R(0.5) : R(-0.5);
           R acc = s_hd[2 * k + ((rb >> k) & 1)];
           for (int j = k + 1; j < n; j++) acc = fma(tb.zz[k * n + j] * mk, ((rb >> j) & 1) ? R(0.5) : R(-0.5), acc);
-          s_term[(k - kLowBits) * Q + q] = acc;
+          s_term[(k - kLowBits) * S + sl] = acc;
         }
-      } else if (t < 24 * Q + 8 * Q) {
-        const int i = (t - 24 * Q) / Q, q = (t - 24 * Q) % Q;
-        const uint32_t rb = base | ((uint32_t)q << kLowBits);
+      } else if (t < 24 * S + 8 * S) {
+        const int i = (t - 24 * S) / S, sl = (t - 24 * S) % S;
+        const uint32_t rb = base | ((uint32_t)sl << kLowBits);
         R ph = 0;
         for (int j = kLowBits; j < n; j++) ph = fma(tb.zz[i * n + j], ((rb >> j) & 1) ? R(0.5) : R(-0.5), ph);
-        s_phi[i * Q + q] = ph;
+        s_phi[i * S + sl] = ph;
       }
     }
     __syncthreads();
-    if (W.diag && t < Q) {
+    if (W.diag && t < S) {
       R d = 0;
-      for (int k = kLowBits; k < n; k++) d += s_term[(k - kLowBits) * Q + t];
+      for (int k = kLowBits; k < n; k++) d += s_term[(k - kLowBits) * S + t];
       s_dmh[t] = d;
     }
     __syncthreads();
@@ -1320,10 +1374,11 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
     for (int q = 0; q < Q; q++) {
       acc[q] = Cx<R>{0, 0};
       if (W.diag) {
-        R dg = dlow + s_dmh[q];
+        const int sl = gg * Q + q;
+        R dg = dlow + s_dmh[sl];
 #pragma unroll
-        for (int i = 0; i < kLowBits; i++) dg = fma(mlane[i], s_phi[i * Q + q], dg);
-        const Cx<R> x = own[q * kBlock + t];
+        for (int i = 0; i < kLowBits; i++) dg = fma(((l >> i) & 1) ? R(0.5) : R(-0.5), s_phi[i * S + sl], dg);
+        const Cx<R> x = own[q * kBlock + tq];
         acc[q] = Cx<R>{dg * x.re, dg * x.im};
       }
     }
@@ -1332,21 +1387,22 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
     for (uint32_t sm = W.smask & ((1u << kTileBits) - 1u); sm; sm &= sm - 1u) {
       const int k = __builtin_ctz(sm);
       if (k < kLowBits) {  // lane bit: the row bit and the lane part of F do not depend on q
-        const int b = (t >> k) & 1;
-        const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + t];
-        const int tl = t ^ (1 << k);
+        const int b = (l >> k) & 1;
+        const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + l];
+        const int tf = tq ^ (1 << k);
 #pragma unroll
         for (int q = 0; q < Q; q++) {
-          const Cx<R> a3 = s_fmh[(k * 2 + b) * Q + q];
-          fma_cx(acc[q], Cx<R>{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im}, own[q * kBlock + tl]);
+          const Cx<R> a3 = s_fmh[(k * 2 + b) * S + gg * Q + q];
+          fma_cx(acc[q], Cx<R>{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im}, own[q * kBlock + tf]);
         }
       } else {
 #pragma unroll
         for (int q = 0; q < Q; q++) {
-          const int b = (q >> (k - kLowBits)) & 1;
-          const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + t], a3 = s_fmh[(k * 2 + b) * Q + q];
+          const int sl = gg * Q + q;
+          const int b = (sl >> (k - kLowBits)) & 1;
+          const Cx<R> a1 = s_hf[2 * k + b], a2 = tb.lowf[(k * 2 + b) * 256 + l], a3 = s_fmh[(k * 2 + b) * S + sl];
           fma_cx(acc[q], Cx<R>{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im},
-                 own[(q ^ (1 << (k - kLowBits))) * kBlock + t]);
+                 own[(sl ^ (1 << (k - kLowBits))) * kBlock + l]);
         }
       }
     }
@@ -1355,34 +1411,35 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
     for (int e = 0; e < n_in; e++) {
       const int4 ij = pl[e];
       const int i = ij.y, j = ij.z;
-      if (j < kLowBits) {  // two lane bits: one coefficient per thread, partner lane t ^ mask
-        const Cx<R> c = s_pc[4 * e + ((((t >> i) & 1) << 1) | ((t >> j) & 1))];
-        const int tl = t ^ ((1 << i) | (1 << j));
+      if (j < kLowBits) {  // two lane bits: one coefficient per thread, partner t ^ mask
+        const Cx<R> c = s_pc[4 * e + ((((l >> i) & 1) << 1) | ((l >> j) & 1))];
+        const int tf = tq ^ ((1 << i) | (1 << j));
 #pragma unroll
-        for (int q = 0; q < Q; q++) fma_cx(acc[q], c, own[q * kBlock + tl]);
+        for (int q = 0; q < Q; q++) fma_cx(acc[q], c, own[q * kBlock + tf]);
       } else if (i < kLowBits) {  // lane bit i, slot bit j
-        const int bi = (t >> i) & 1;
-        slot_flip_any(j - kLowBits, acc, own, t ^ (1 << i), s_pc[4 * e + (bi << 1)], s_pc[4 * e + (bi << 1) + 1]);
+        const int bi = (l >> i) & 1;
+        slot_flip_any<G>(j - kLowBits, acc, own, gg, tq ^ (1 << i), s_pc[4 * e + (bi << 1)],
+                         s_pc[4 * e + (bi << 1) + 1]);
       } else {  // two slot bits
         const Cx<R> *cp = s_pc + 4 * e;
-        if (i == kLowBits && j == kLowBits + 1) slot_pair<0, 1>(acc, own, t, cp);
-        else if (i == kLowBits) slot_pair<0, 2>(acc, own, t, cp);
-        else slot_pair<1, 2>(acc, own, t, cp);
+        if (i == kLowBits && j == kLowBits + 1) slot_pair<0, 1, G>(acc, own, gg, tq, cp);
+        else if (i == kLowBits) slot_pair<0, 2, G>(acc, own, gg, tq, cp);
+        else slot_pair<1, 2, G>(acc, own, gg, tq, cp);
       }
     }
     // outer sites with work in this pass: partner tile staged once; the next
     // site's tile is loaded into registers while the current one is in use
     int e = n_in;
     uint32_t xm = W.xmask;
-    // (with no next site the own tile is loaded instead, so that the
-    // prefetch registers are always defined)
+    // (with no next site the own tile is loaded instead, so that the prefetch
+    // registers are always defined)
     R nre[Q], nim[Q];
     {
       const uint32_t nb = xm ? (base ^ (1u << __builtin_ctz(xm))) : base;
       const Cx<R> *vb = v + (size_t)nb * K + c0;
 #pragma unroll
       for (int q = 0; q < Q; q++) {
-        const Cx<R> x = vb[(size_t)q * kBlock * K + tk];
+        const Cx<R> x = vb[q * QS * K + tk];
         nre[q] = x.re;
         nim[q] = x.im;
       }
@@ -1393,13 +1450,13 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
       xm &= xm - 1u;
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < Q; q++) part[q * kBlock + t] = Cx<R>{nre[q], nim[q]};
+      for (int q = 0; q < Q; q++) part[q * kBlock + tq] = Cx<R>{nre[q], nim[q]};
       {
         const uint32_t nb = xm ? (base ^ (1u << __builtin_ctz(xm))) : base;
         const Cx<R> *vb = v + (size_t)nb * K + c0;
 #pragma unroll
         for (int q = 0; q < Q; q++) {
-          const Cx<R> x = vb[(size_t)q * kBlock * K + tk];
+          const Cx<R> x = vb[q * QS * K + tk];
           nre[q] = x.re;
           nim[q] = x.im;
         }
@@ -1407,11 +1464,11 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
       __syncthreads();
       const int ba = (base >> a) & 1;
       if ((W.smask >> a) & 1u) {
+        const Cx<R> a1 = s_hf[2 * a + ba], a2 = tb.lowf[(a * 2 + ba) * 256 + l];
 #pragma unroll
         for (int q = 0; q < Q; q++) {
-          const Cx<R> a1 = s_hf[2 * a + ba], a2 = tb.lowf[(a * 2 + ba) * 256 + t], a3 = s_fmh[(a * 2 + ba) * Q + q];
-          const Cx<R> c{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im};
-          fma_cx(acc[q], c, part[q * kBlock + t]);
+          const Cx<R> a3 = s_fmh[(a * 2 + ba) * S + gg * Q + q];
+          fma_cx(acc[q], Cx<R>{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im}, part[q * kBlock + tq]);
         }
       }
 #pragma unroll 1
@@ -1420,35 +1477,40 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile_win(HamGeom g, DevTables<R>
         const int i = pe.y;
         const Cx<R> clo = tb.pc_half[4 * pe.x + ba], chi = tb.pc_half[4 * pe.x + 2 + ba];
         if (i < kLowBits) {
-          const Cx<R> c = ((t >> i) & 1) ? chi : clo;
-          const int tl = t ^ (1 << i);
+          const Cx<R> c = ((l >> i) & 1) ? chi : clo;
+          const int tf = tq ^ (1 << i);
 #pragma unroll
-          for (int q = 0; q < Q; q++) fma_cx(acc[q], c, part[q * kBlock + tl]);
+          for (int q = 0; q < Q; q++) fma_cx(acc[q], c, part[q * kBlock + tf]);
         } else {
-          slot_flip_any(i - kLowBits, acc, part, t, clo, chi);
+          slot_flip_any<G>(i - kLowBits, acc, part, gg, tq, clo, chi);
         }
       }
     }
-    // pairs of two outer sites
-#pragma unroll 1
-    for (int e2 = e_out; e2 < np; e2++) {
-      const int4 pe = pl[e2];
-      const int type = (((base >> pe.y) & 1) << 1) | ((base >> pe.z) & 1);
-      const Cx<R> c = tb.pc_half[4 * pe.x + type];
-      const Cx<R> *vb = v + (size_t)(base ^ (1u << pe.y) ^ (1u << pe.z)) * K + c0;
+    // the earlier passes' partial sums of these rows, loaded now so that they
+    // arrive during the outer pairs
+    Cx<R> wprev[Q];
+    Cx<R> *wt = reinterpret_cast<Cx<R> *>(P.w) + (size_t)base * K + c0;
 #pragma unroll
-      for (int q = 0; q < Q; q++) fma_cx(acc[q], c, vb[(size_t)q * kBlock * K + tk]);
+    for (int q = 0; q < Q; q++) wprev[q] = W.first ? Cx<R>{0, 0} : wt[q * QS * K + tk];
+    // pairs of two outer sites, NB at a time
+    {
+      const Cx<R> *vc = v + c0;
+      int e2 = e_out;
+#pragma unroll 1
+      for (; e2 + NB <= np; e2 += NB) outer_pairs<NB, G>(acc, pl + e2, base, tb.pc_half, vc, (size_t)K, tk);
+      if (e2 < np) outer_pairs<1, G>(acc, pl + e2, base, tb.pc_half, vc, (size_t)K, tk);
     }
 #pragma unroll
     for (int q = 0; q < Q; q++) {
       Acc<R, 1> a1;
-      a1.re[0] = acc[q].re;
-      a1.im[0] = acc[q].im;
-      const uint32_t row = base + q * kBlock + t;
-      win_store<R, 1>(W, P, row, c0, a1, v + (size_t)row * K + c0, red);
+      a1.re[0] = acc[q].re + wprev[q].re;
+      a1.im[0] = acc[q].im + wprev[q].im;
+      const uint32_t row = base + q * kBlock + tq;
+      if (W.last) hv_epilogue<R, 1>(P, row, c0, a1, own + q * kBlock + tq, red);
+      else wt[q * QS * K + tk] = Cx<R>{a1.re[0], a1.im[0]};
     }
   });
-  if (W.last) hv_finish<1>(P, red);
+  if (W.last) hv_finish<1, NT>(P, red);
 }
 
 // General mixed radix: one 256-row slice of a window per item; the window's
@@ -1834,11 +1896,34 @@ static size_t hv_tile_win_smem(const HamGeom &g, const WinPass &W) {
          sizeof(R) * (2 * g.n + kRowsPerThread + 8 * kRowsPerThread + 32 * kRowsPerThread);
 }
 
+// Threads per tile-window block: 256 G (G groups of rows on one LDS tile).
+// want = 1 or 2 (the tuned choice), else FTLM_TILE_GROUPS, else 2 for complex128
+// (the tile's LDS allows two blocks per CU: eight more waves) and 1 for
+// complex64 (four 256-thread blocks already fit).
+static int tile_win_groups(int want, bool f32) {
+  if (want == 1 || want == 2) return want;
+  if (const char *e = std::getenv("FTLM_TILE_GROUPS")) return std::atoi(e) == 1 ? 1 : 2;
+  return f32 ? 1 : 2;
+}
+
+template <typename R, int G>
+static void launch_tile_win_g(dim3 grid, size_t sm, hipStream_t s, const HamGeom &g, const DevTables<R> &tb,
+                              const WinPass &W, const int4 *plist, const HvParams &P) {
+  static size_t granted = 0;  // per instantiation
+  if (sm > granted) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_tile_win<R, G>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    granted = sm;
+  }
+  hipLaunchKernelGGL((hv_tile_win<R, G>), grid, dim3(kBlock * G), sm, s, g, tb, W, plist, P);
+}
+
 template <typename R>
 static int launch_tile_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &plan, const HvParams &P,
-                           int cap, unsigned *last_gx, hipStream_t s) {
+                           int cap, int groups, unsigned *last_gx, hipStream_t s) {
   const HamGeom &g = dh.geom;
   if (!plan.d_plist || plan.passes.empty() || !g.spin_half || g.n <= kTileBits) return FTLM_EINVAL;
+  const int G = tile_win_groups(groups, sizeof(R) == 4);
   for (const WinPass &W : plan.passes) {
     const uint64_t items = (uint64_t)W.nwin * W.nin;
     uint32_t gx = (uint32_t)(items < (uint64_t)cap ? items : (uint64_t)cap);
@@ -1847,13 +1932,9 @@ static int launch_tile_win(const DevHam &dh, const DevTables<R> &tb, const WinPl
     if (!W.last) Pp.lanczos = 0;
     const size_t sm = hv_tile_win_smem<R>(g, W);
     if (sm > 160 * 1024) return FTLM_ERANGE;
-    static size_t granted = 0;
-    if (sm > granted) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_tile_win<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-      granted = sm;
-    }
-    hipLaunchKernelGGL((hv_tile_win<R>), dim3(gx, P.K), dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp);
+    const dim3 grid(gx, P.K);
+    if (G == 2) launch_tile_win_g<R, 2>(grid, sm, s, g, tb, W, plan.d_plist, Pp);
+    else launch_tile_win_g<R, 1>(grid, sm, s, g, tb, W, plan.d_plist, Pp);
     *last_gx = gx;
   }
   return FTLM_OK;
@@ -1903,8 +1984,9 @@ int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
   int rc = FTLM_OK;
   if (L.variant == 5) {
     const int cap = L.grid_cap > 0 ? std::min(L.grid_cap, 2048) : 2048;
-    rc = (L.precision == FTLM_C64) ? launch_tile_win<float>(dh, dh.t32, dh.tw32, P, cap, &fin_gx, s)
-                                   : launch_tile_win<double>(dh, dh.t64, dh.tw64, P, cap, &fin_gx, s);
+    // (the columns-per-lane field carries the row groups per tile)
+    rc = (L.precision == FTLM_C64) ? launch_tile_win<float>(dh, dh.t32, dh.tw32, P, cap, L.kc, &fin_gx, s)
+                                   : launch_tile_win<double>(dh, dh.t64, dh.tw64, P, cap, L.kc, &fin_gx, s);
     fin_gy = (unsigned)L.K;
     fin_kc = 1;
   } else if (L.variant == 4) {

@@ -50,7 +50,7 @@ int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_
     if (n_cols == 1 && cap <= 2048) cands.push_back({4, cap, 0});
     if (n_cols == 1 && cap <= 2048 && g.spin_half && g.n > kTileBits &&
         !(precision == FTLM_C64 ? h->dev.tw32 : h->dev.tw64).passes.empty())
-      cands.push_back({5, cap, 0});
+      for (int groups : {1, 2}) cands.push_back({5, cap, groups});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

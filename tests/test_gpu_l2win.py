@@ -95,11 +95,13 @@ def test_l2win_full_size_sampled_rows(wl, monkeypatch):
     _sampled(sysm, F().FTLM_C64, 2e-5)
 
 
+@pytest.mark.parametrize("groups", [1, 2])
 @pytest.mark.parametrize("seed,n", [(0, 12), (1, 14), (2, 16), (3, 13)])
-def test_tile_window_hv_matches_oracle(seed, n, monkeypatch):
-    """Variant 5 (LDS tile kernel walked over L2 windows), spin 1/2: tiny windows
-    give many passes (N = 16: ten)."""
+def test_tile_window_hv_matches_oracle(seed, n, groups, monkeypatch):
+    """Variant 5 (LDS tile kernel walked over L2 windows), spin 1/2, with one and
+    two row groups per tile: tiny windows give many passes (N = 16: ten)."""
     monkeypatch.setenv("FTLM_HV_VARIANT", "5")
+    monkeypatch.setenv("FTLM_TILE_GROUPS", str(groups))
     rng = np.random.default_rng(2900 + seed)
     sysm = W.random_small_system(rng, n, max_two_s=1)
     sysm.two_s[:] = 1
@@ -112,8 +114,10 @@ def test_tile_window_hv_matches_oracle(seed, n, monkeypatch):
     assert rel_max(w32, oh.apply(v.astype(np.complex64).astype(np.complex128))) < 2e-5
 
 
-def test_tile_window_run_matches_oracle(monkeypatch):
+@pytest.mark.parametrize("groups", [1, 2])
+def test_tile_window_run_matches_oracle(groups, monkeypatch):
     monkeypatch.setenv("FTLM_HV_VARIANT", "5")
+    monkeypatch.setenv("FTLM_TILE_GROUPS", str(groups))
     rng = np.random.default_rng(2950)
     sysm = W.random_small_system(rng, 15, max_two_s=1)
     sysm.two_s[:] = 1
@@ -127,8 +131,10 @@ def test_tile_window_run_matches_oracle(monkeypatch):
         assert err < 1e-8, key
 
 
-def test_tile_window_full_size_sampled_rows(monkeypatch):
+@pytest.mark.parametrize("groups", [1, 2])
+def test_tile_window_full_size_sampled_rows(groups, monkeypatch):
     monkeypatch.setenv("FTLM_HV_VARIANT", "5")
+    monkeypatch.setenv("FTLM_TILE_GROUPS", str(groups))
     monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "2048")
     sysm, _ = W.cfg2()
     _sampled(sysm, F().FTLM_C128, 1e-12)
