@@ -1274,9 +1274,14 @@ __device__ __forceinline__ void outer_pairs(Cx<R> (&acc)[kRowsPerThread / G], co
     for (int q = 0; q < Q; q++) fma_cx(acc[q], c[b], x[b][q]);
 }
 
+// plist and pch (the spin-1/2 pair coefficients, tb.pc_half) are read at
+// wave-uniform addresses; as __restrict__ kernel arguments they are known not
+// to be written by the kernel's stores, so these reads go through the scalar
+// data cache instead of becoming vector loads with a full wait in every trip.
 template <typename R, int G>
 __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevTables<R> tb, WinPass W,
-                                                             const int4 *__restrict__ plist, HvParams P) {
+                                                             const int4 *__restrict__ plist,
+                                                             const Cx<R> *__restrict__ pch, HvParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NT = kBlock * G;           // threads per block
   constexpr int S = kRowsPerThread;        // slots per tile (row bits 8..10)
@@ -1299,7 +1304,7 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
   const int c0 = blockIdx.y;
   const int K = P.K;
   const int4 *pl = plist + W.p0;
-  for (int i = t; i < 4 * n_in; i += NT) s_pc[i] = tb.pc_half[4 * pl[i >> 2].x + (i & 3)];
+  for (int i = t; i < 4 * n_in; i += NT) s_pc[i] = pch[4 * pl[i >> 2].x + (i & 3)];
   for (int i = t; i < 2 * n; i += NT) {
     s_hf[i] = tb.hflip[i];
     s_hd[i] = tb.hdiag[(i >> 1) * 16 + (i & 1)];
@@ -1472,10 +1477,12 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
         }
       }
 #pragma unroll 1
-      for (; e < e_out && pl[e].z == a; e++) {
+      for (; e < e_out; e++) {
+        e = __builtin_amdgcn_readfirstlane(e);
         const int4 pe = pl[e];
+        if (pe.z != a) break;
         const int i = pe.y;
-        const Cx<R> clo = tb.pc_half[4 * pe.x + ba], chi = tb.pc_half[4 * pe.x + 2 + ba];
+        const Cx<R> clo = pch[4 * pe.x + ba], chi = pch[4 * pe.x + 2 + ba];
         if (i < kLowBits) {
           const Cx<R> c = ((l >> i) & 1) ? chi : clo;
           const int tf = tq ^ (1 << i);
@@ -1497,8 +1504,8 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
       const Cx<R> *vc = v + c0;
       int e2 = e_out;
 #pragma unroll 1
-      for (; e2 + NB <= np; e2 += NB) outer_pairs<NB, G>(acc, pl + e2, base, tb.pc_half, vc, (size_t)K, tk);
-      if (e2 < np) outer_pairs<1, G>(acc, pl + e2, base, tb.pc_half, vc, (size_t)K, tk);
+      for (; e2 + NB <= np; e2 += NB) outer_pairs<NB, G>(acc, pl + e2, base, pch, vc, (size_t)K, tk);
+      if (e2 < np) outer_pairs<1, G>(acc, pl + e2, base, pch, vc, (size_t)K, tk);
     }
 #pragma unroll
     for (int q = 0; q < Q; q++) {
@@ -1915,7 +1922,7 @@ static void launch_tile_win_g(dim3 grid, size_t sm, hipStream_t s, const HamGeom
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     granted = sm;
   }
-  hipLaunchKernelGGL((hv_tile_win<R, G>), grid, dim3(kBlock * G), sm, s, g, tb, W, plist, P);
+  hipLaunchKernelGGL((hv_tile_win<R, G>), grid, dim3(kBlock * G), sm, s, g, tb, W, plist, tb.pc_half, P);
 }
 
 template <typename R>
