@@ -53,6 +53,7 @@ struct BStep {
   int *done, *nused;
   double *part;                        // [n_units][3][K]
   uint32_t n_items;                    // items of the wave (blocks of the finishing launch)
+  uint32_t lds;                        // dynamic LDS of the H*v launch (largest item's tables)
   const int *unit_item;                // [n_units]
 };
 
@@ -73,11 +74,94 @@ __device__ __forceinline__ void bmac(BAcc<R, KC> &a, R cr, R ci, const Cx<R> *__
   }
 }
 
-// One row of H v (or O v) for KC columns.  ops selects the operator's tables.
+// LDS bytes of one item's staged tables (see stage_tables).
+__host__ __device__ inline size_t staged_bytes(int n, int npair, bool half, size_t rs) {
+  const size_t cs = 2 * rs;
+  auto a16 = [](size_t b) { return (b + 15) & ~size_t(15); };
+  size_t b = a16((size_t)n * 16 * rs) + 2 * a16((size_t)n * n * cs) + a16((size_t)npair * 8) +
+             a16((size_t)npair * rs) + a16((size_t)npair * 4 * cs);
+  if (half) b += a16((size_t)n * 2 * cs);
+  else b += 3 * a16((size_t)n * 16 * rs) + a16((size_t)n * 64 * cs);
+  return b;
+}
+
+// LDS layout of one item's staged tables (operator H, or O for the moment
+// product): the tables brow reads, at offsets that depend only on the item's
+// sizes.  Recomputed from the LDS base wherever it is used, so that the
+// compiler sees LDS pointers (not generic ones) in brow.
+template <typename R>
+__device__ __forceinline__ DevTables<R> table_layout(const BItem<R> &it, bool moment, unsigned char *lds) {
+  const int n = it.n, np = moment ? 0 : it.npair;
+  const size_t rs = sizeof(R), cs = sizeof(Cx<R>);
+  auto a16 = [](size_t b) { return (b + 15) & ~size_t(15); };
+  DevTables<R> d{};
+  size_t off = 0;
+  d.hdiag = reinterpret_cast<const R *>(lds + off);
+  off += a16((size_t)n * 16 * rs);
+  d.czp = reinterpret_cast<const Cx<R> *>(lds + off);
+  off += a16((size_t)n * n * cs);
+  d.czm = reinterpret_cast<const Cx<R> *>(lds + off);
+  off += a16((size_t)n * n * cs);
+  d.pij = reinterpret_cast<const int2 *>(lds + off);
+  off += a16((size_t)np * 8);
+  d.pzz = reinterpret_cast<const R *>(lds + off);
+  off += a16((size_t)np * rs);
+  if (it.half) {
+    d.pc_half = reinterpret_cast<const Cx<R> *>(lds + off);
+    off += a16((size_t)np * 4 * cs);
+    d.hflip = reinterpret_cast<const Cx<R> *>(lds + off);
+  } else {
+    d.pc = reinterpret_cast<const Cx<R> *>(lds + off);
+    off += a16((size_t)np * 4 * cs);
+    d.mval = reinterpret_cast<const R *>(lds + off);
+    off += a16((size_t)n * 16 * rs);
+    d.gp = reinterpret_cast<const R *>(lds + off);
+    off += a16((size_t)n * 16 * rs);
+    d.gm = reinterpret_cast<const R *>(lds + off);
+    off += a16((size_t)n * 16 * rs);
+    d.hoff = reinterpret_cast<const Cx<R> *>(lds + off);
+  }
+  return d;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_copy(const T *dst, const T *src, size_t cnt) {
+  T *d = const_cast<T *>(dst);
+  if (src)
+    for (size_t i = threadIdx.x; i < cnt; i += kBlock) d[i] = src[i];
+}
+
+// Copies the tables brow reads for item it into LDS (layout table_layout).
+// brow walks the pairs and sites at wave-uniform indices; read from global
+// memory those reads are vector loads that each wait out their latency, read
+// from LDS they are broadcasts.  The caller synchronises before and after.
+template <typename R>
+__device__ void stage_tables(const BItem<R> &it, bool moment, unsigned char *lds) {
+  const DevTables<R> &src = moment ? it.tbo : it.tb;
+  const DevTables<R> d = table_layout(it, moment, lds);
+  const int n = it.n, np = moment ? 0 : it.npair;
+  const bool hz = !moment && it.has_z;
+  stage_copy(d.hdiag, src.hdiag, (size_t)n * 16);
+  stage_copy(d.czp, hz ? src.czp : nullptr, (size_t)n * n);
+  stage_copy(d.czm, hz ? src.czm : nullptr, (size_t)n * n);
+  stage_copy(d.pij, src.pij, (size_t)np);
+  stage_copy(d.pzz, src.pzz, (size_t)np);
+  if (it.half) {
+    stage_copy(d.pc_half, src.pc_half, (size_t)np * 4);
+    stage_copy(d.hflip, src.hflip, (size_t)n * 2);
+  } else {
+    stage_copy(d.pc, src.pc, (size_t)np * 4);
+    stage_copy(d.mval, src.mval, (size_t)n * 16);
+    stage_copy(d.gp, src.gp, (size_t)n * 16);
+    stage_copy(d.gm, src.gm, (size_t)n * 16);
+    stage_copy(d.hoff, src.hoff, (size_t)n * 64);
+  }
+}
+
+// One row of H v (or O v) for KC columns; tb holds the operator's tables.
 template <typename R, int KC>
-__device__ __forceinline__ void brow(const BItem<R> &it, bool moment, uint32_t row,
+__device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb, bool moment, uint32_t row,
                                      const Cx<R> *__restrict__ v, BAcc<R, KC> &acc) {
-  const DevTables<R> &tb = moment ? it.tbo : it.tb;
   const int n = it.n;
   const int npair = moment ? 0 : it.npair;
   const bool has_z = !moment && it.has_z;
@@ -253,10 +337,19 @@ __global__ __launch_bounds__(kBlock) void bstart_kernel(const BItem<R> *__restri
 
 template <typename R, int KC>
 __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict__ items, BStep S) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const int j = S.step;
+  int staged = -1;  // item whose tables are in LDS (a block's units are mostly of one item)
   for (uint32_t u = blockIdx.x; u < S.n_units; u += gridDim.x) {
     const int ii = S.unit_item[u];
     const BItem<R> &it = items[ii];
+    if (ii != staged) {
+      __syncthreads();
+      stage_tables(it, S.mode == 0, smem);
+      __syncthreads();
+      staged = ii;
+    }
+    const DevTables<R> lt = table_layout(it, S.mode == 0, smem);
     const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
     const bool moment = S.mode == 0;
     const Cx<R> *v = moment ? it.x[0] : it.x[j % 3];
@@ -275,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       for (int q = 0; q < KC; q++) red[a][q] = 0.0;
     for (uint32_t row = r0 + threadIdx.x; row < r1; row += kBlock) {
       BAcc<R, KC> acc;
-      brow<R, KC>(it, moment, row, v, acc);
+      brow<R, KC>(it, lt, moment, row, v, acc);
       const size_t o = (size_t)row * KC;
 #pragma unroll
       for (int q = 0; q < KC; q++) {
@@ -588,7 +681,15 @@ void pack_site(const HostHam &hh, unsigned char *dst, int maxn, DevTables<R> &tb
 template <typename R, int KC>
 void launch_b(int kind, dim3 grid, const BItem<R> *items, const BStep &S, hipStream_t s) {
   if (kind == 0) hipLaunchKernelGGL((bstart_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
-  else if (kind == 1) hipLaunchKernelGGL((bhv_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
+  else if (kind == 1) {
+    static uint32_t granted = 64 * 1024;
+    if (S.lds > granted) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bhv_kernel<R, KC>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)S.lds);
+      granted = S.lds;
+    }
+    hipLaunchKernelGGL((bhv_kernel<R, KC>), grid, dim3(kBlock), S.lds, s, items, S);
+  }
   else hipLaunchKernelGGL((bupdate_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
   if (kind != 1 || S.mode == 1)  // O v_1 has no reductions
     hipLaunchKernelGGL((bfinish_kernel<R>), dim3(S.n_items), dim3(kBlock), 0, s, items, S, kind);
@@ -826,6 +927,18 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
     S.seed = pp[0].seed;
     S.part = reinterpret_cast<double *>(wbase + o_part);
     S.n_items = (uint32_t)nit;
+    {
+      size_t lds = 16;
+      for (size_t i = 0; i < nit; i++) {
+        const HostHam &hh = hs[pl.curves[items[next + i].curve].inst]->host;
+        lds = std::max(lds, staged_bytes(hh.n, hh.npair, hh.spin_half, pl.es / 2));
+      }
+      if (lds > 160 * 1024) {
+        set_error("batched item tables exceed the LDS");
+        return FTLM_ERANGE;
+      }
+      S.lds = (uint32_t)lds;
+    }
     S.unit_item = reinterpret_cast<const int *>(wbase + o_umap);
     S.smax = reinterpret_cast<double *>(wbase + o_smax);
     S.done = reinterpret_cast<int *>(wbase + o_done);

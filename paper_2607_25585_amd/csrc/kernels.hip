@@ -62,6 +62,20 @@ __device__ __forceinline__ void mac_real(Acc<R, KC> &a, R c, const Cx<R> *__rest
   }
 }
 
+// Table pointers passed separately as __restrict__ kernel arguments (reads at
+// wave-uniform addresses then use the scalar data cache).
+template <typename R>
+struct UniformTabs {
+  const Cx<R> *pc, *czp, *czm;
+  const int2 *pij;
+  const R *pzz;
+};
+
+template <typename R>
+static inline UniformTabs<R> uniform_tabs(const DevTables<R> &tb, bool half) {
+  return UniformTabs<R>{half ? tb.pc_half : tb.pc, tb.czp, tb.czm, tb.pij, tb.pzz};
+}
+
 // ------------------------------------------------------------------ H*v
 struct HvParams {
   int K;             // row stride in columns
@@ -154,7 +168,8 @@ static void launch_hv_finish(const HvParams &P, unsigned gx, unsigned gy, int kc
 // Spin-1/2 systems with N >= 8: tile = 256 rows whose low 8 bits run over the
 // lanes; bits >= 8 (the tile index) are uniform over the block.
 template <typename R, int KC>
-__global__ __launch_bounds__(kBlock) void hv_half(HamGeom g, DevTables<R> tb, HvParams P) {
+__global__ __launch_bounds__(kBlock) void hv_half(HamGeom g, DevTables<R> tb, const int2 *__restrict__ pij,
+                                                  const R *__restrict__ pzz, HvParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = g.n, np = g.npair;
   Cx<R> *s_pc = reinterpret_cast<Cx<R> *>(smem);   // [np][4]
@@ -175,10 +190,10 @@ __global__ __launch_bounds__(kBlock) void hv_half(HamGeom g, DevTables<R> tb, Hv
   R dlow = 0;
   for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((t >> k) & 1)];
   for (int p = 0; p < np; p++) {
-    const int2 ij = tb.pij[p];
+    const int2 ij = pij[p];
     if (ij.y >= kLowBits) continue;
     const R mm = (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25);
-    dlow = fma(tb.pzz[p], mm, dlow);
+    dlow = fma(pzz[p], mm, dlow);
   }
   const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v) + c0;
   double red[3][KC];
@@ -234,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void hv_half(HamGeom g, DevTables<R> tb, Hv
     }
     // pair flips: exactly one of the four ladder pairs connects each row
     for (int p = 0; p < np; p++) {
-      const int2 ij = tb.pij[p];
+      const int2 ij = pij[p];
       const int type = (((row >> ij.x) & 1) << 1) | ((row >> ij.y) & 1);
       const Cx<R> c = s_pc[4 * p + type];
       mac(acc, c, v + (size_t)(row ^ ((1u << ij.x) | (1u << ij.y))) * P.K);
@@ -251,7 +266,9 @@ __global__ __launch_bounds__(kBlock) void hv_half(HamGeom g, DevTables<R> tb, Hv
 // and serves the single flip of a and all mixed pairs (i < 11, a).  Pairs of two
 // outer sites read the partner tile straight from global memory (one use each).
 template <typename R>
-__global__ __launch_bounds__(kBlock, 2) void hv_tile(HamGeom g, DevTables<R> tb, HvParams P) {
+__global__ __launch_bounds__(kBlock, 2) void hv_tile(HamGeom g, DevTables<R> tb, const int2 *__restrict__ pij,
+                                                     const Cx<R> *__restrict__ pch, const R *__restrict__ pzz,
+                                                     HvParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int Q = kRowsPerThread;
   const int n = g.n, np = g.npair, n_in = g.n_ll, n_out0 = g.n_ll + g.n_lh;
@@ -267,7 +284,7 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile(HamGeom g, DevTables<R> tb,
   const int t = threadIdx.x;
   const int c0 = blockIdx.y;
   const int K = P.K;
-  for (int i = t; i < 4 * n_in; i += kBlock) s_pc[i] = tb.pc_half[i];
+  for (int i = t; i < 4 * n_in; i += kBlock) s_pc[i] = pch[i];
   for (int i = t; i < 2 * n; i += kBlock) {
     s_hf[i] = tb.hflip[i];
     s_hd[i] = tb.hdiag[(i >> 1) * 16 + (i & 1)];
@@ -276,9 +293,9 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile(HamGeom g, DevTables<R> tb,
   R dlow = 0;
   for (int k = 0; k < kLowBits; k++) dlow += s_hd[2 * k + ((t >> k) & 1)];
   for (int p = 0; p < n_in; p++) {
-    const int2 ij = tb.pij[p];
+    const int2 ij = pij[p];
     if (ij.y >= kLowBits) continue;
-    dlow = fma(tb.pzz[p], (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25), dlow);
+    dlow = fma(pzz[p], (((t >> ij.x) ^ (t >> ij.y)) & 1) ? R(-0.25) : R(0.25), dlow);
   }
   R mlane[kLowBits];
 #pragma unroll
@@ -357,7 +374,7 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile(HamGeom g, DevTables<R> tb,
     // pairs inside the tile
 #pragma unroll 1
     for (int p = 0; p < n_in; p++) {
-      const int2 ij = tb.pij[p];
+      const int2 ij = pij[p];
       const int mask = (1 << ij.x) | (1 << ij.y);
 #pragma unroll
       for (int q = 0; q < Q; q++) {
@@ -392,8 +409,8 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile(HamGeom g, DevTables<R> tb,
       const int p1 = g.mx_off[a + 1];
 #pragma unroll 1
       for (int p = g.mx_off[a]; p < p1; p++) {
-        const int i = tb.pij[p].x;
-        const Cx<R> clo = tb.pc_half[4 * p + ba], chi = tb.pc_half[4 * p + 2 + ba];
+        const int i = pij[p].x;
+        const Cx<R> clo = pch[4 * p + ba], chi = pch[4 * p + 2 + ba];
 #pragma unroll
         for (int q = 0; q < Q; q++) {
           const int r = q * kBlock + t;
@@ -407,9 +424,9 @@ __global__ __launch_bounds__(kBlock, 2) void hv_tile(HamGeom g, DevTables<R> tb,
     // pairs of two outer sites: partner tile read once from global memory
 #pragma unroll 1
     for (int p = n_out0; p < np; p++) {
-      const int2 ij = tb.pij[p];
+      const int2 ij = pij[p];
       const int type = (((base >> ij.x) & 1) << 1) | ((base >> ij.y) & 1);
-      const Cx<R> c = tb.pc_half[4 * p + type];
+      const Cx<R> c = pch[4 * p + type];
       const uint32_t pb = base ^ (1u << ij.x) ^ (1u << ij.y);
 #pragma unroll
       for (int q = 0; q < Q; q++) {
@@ -636,7 +653,9 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
                                                   const int4 *__restrict__ pp,
                                                   const R *__restrict__ rec,
                                                   const uint32_t *__restrict__ bases,
-                                                  const unsigned char *__restrict__ lane, HvParams P) {
+                                                  const unsigned char *__restrict__ lane,
+                                                  const Cx<R> *__restrict__ czp, const Cx<R> *__restrict__ czm,
+                                                  const R *__restrict__ zz, HvParams P) {
   using L = PassRec<R, POW2, RPT>;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t ws = D.wsize;
@@ -692,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
       }
     }
     dig[q] = packed;
-    gof[q] = off;
+    gof[q] = r < ws ? off : 0u;  // rows past the window read the window's first row (unused)
   }
   auto digit = [&](int q, int a) -> uint32_t {
     return POW2 ? ((dig[q] >> a) & 1u) : ((dig[q] >> (4 * a)) & 15u);
@@ -719,10 +738,18 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
   for (uint32_t wid = blockIdx.x; wid < D.nwin; wid += gridDim.x) {
     const uint32_t base = bases[wid];
     __syncthreads();
+    // eight rows' loads in flight before the first LDS store (a load and store
+    // per row under the row's bound check would wait out each load in turn)
 #pragma unroll
-    for (int q = 0; q < RPT; q++) {
-      const uint32_t r = (uint32_t)(t + kBlock * q);
-      if (r < ws) win[r] = v[(size_t)(base + gof[q]) * K + c0];
+    for (int h = 0; h < RPT; h += 8) {
+      Cx<R> tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) tmp[u] = v[(size_t)(base + gof[h + u]) * K + c0];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const uint32_t r = (uint32_t)(t + kBlock * (h + u));
+        if (r < ws) win[r] = tmp[u];
+      }
     }
     for (int i = t; i < L::kLen; i += kBlock) s_rec[i] = rec[(size_t)wid * L::kLen + i];
     __syncthreads();
@@ -746,7 +773,7 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
             const uint32_t da = digit(q, a);
             dg += s_hd[a * 16 + da];
             R zs = s_rec[L::kPhi + a];
-            for (int a2 = a + 1; a2 < na; a2++) zs = fma(tb.zz[D.act[a] * n + D.act[a2]], s_m[a2 * 16 + digit(q, a2)], zs);
+            for (int a2 = a + 1; a2 < na; a2++) zs = fma(zz[D.act[a] * n + D.act[a2]], s_m[a2 * 16 + digit(q, a2)], zs);
             dg = fma(s_m[a * 16 + da], zs, dg);
           }
         }
@@ -787,7 +814,7 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
             for (int a2 = 0; a2 < na; a2++) {
               if (a2 == a) continue;
               const R m2 = s_m[a2 * 16 + digit(q, a2)];
-              const Cx<R> cm = tb.czm[k * n + D.act[a2]], cp = tb.czp[k * n + D.act[a2]];
+              const Cx<R> cm = czm[k * n + D.act[a2]], cp = czp[k * n + D.act[a2]];
               fmr = fma(cm.re, m2, fmr);
               fmi = fma(cm.im, m2, fmi);
               fpr = fma(cp.re, m2, fpr);
@@ -862,25 +889,49 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
         }
       }
     }
+    // four rows at a time: every load of the group (earlier passes' partial
+    // sums; on the last pass of a Lanczos step the previous vector and O v_1)
+    // is issued before the group's first store
+    const Cx<R> *xpv = P.xprev ? reinterpret_cast<const Cx<R> *>(P.xprev) : nullptr;
+    const Cx<R> *o1v = P.ov1 ? reinterpret_cast<const Cx<R> *>(P.ov1) : nullptr;
+    const bool lz = D.last && P.lanczos;
+    const double sx = lz ? P.scale[c0] : 0.0;
+    const double bp = (lz && xpv) ? P.beta_prev[c0] * P.sx_prev[c0] : 0.0;
+    const R sc = (D.last && !P.lanczos && P.scale) ? (R)P.scale[c0] : R(1);
 #pragma unroll
-    for (int q = 0; q < RPT; q++) {
-      const uint32_t r = (uint32_t)(t + kBlock * q);
-      if (r >= ws) continue;
-      const uint32_t gi = base + gof[q];
-      Cx<R> *wp = wout + (size_t)gi * K + c0;
-      Cx<R> a = acc[q];
-      if (!D.first) {
-        const Cx<R> o = *wp;
-        a.re += o.re;
-        a.im += o.im;
+    for (int h = 0; h < RPT; h += 4) {
+      Cx<R> wo[4], xo[4], ov[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const size_t gi = (size_t)(base + gof[h + u]) * K + c0;
+        wo[u] = D.first ? Cx<R>{0, 0} : wout[gi];
+        xo[u] = (lz && xpv) ? xpv[gi] : Cx<R>{0, 0};
+        ov[u] = (lz && o1v) ? o1v[gi] : Cx<R>{0, 0};
       }
-      if (!D.last) {
-        *wp = a;
-      } else {
-        Acc<R, 1> a1;
-        a1.re[0] = a.re;
-        a1.im[0] = a.im;
-        hv_epilogue<R, 1>(P, gi, c0, a1, &win[r], red);
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int q = h + u;
+        const uint32_t r = (uint32_t)(t + kBlock * q);
+        if (r >= ws) continue;
+        Cx<R> *wp = wout + (size_t)(base + gof[q]) * K + c0;
+        const R are = acc[q].re + wo[u].re, aim = acc[q].im + wo[u].im;
+        if (!D.last) {
+          *wp = Cx<R>{are, aim};
+        } else if (!P.lanczos) {
+          *wp = Cx<R>{are * sc, aim * sc};
+        } else {
+          // the Lanczos epilogue of hv_epilogue with its loads hoisted
+          const double wr = (double)are * sx - bp * (double)xo[u].re;
+          const double wi = (double)aim * sx - bp * (double)xo[u].im;
+          const Cx<R> out{(R)wr, (R)wi};
+          *wp = out;
+          const Cx<R> x = win[r];
+          red[0][0] += (double)x.re * (double)out.re + (double)x.im * (double)out.im;
+          if (o1v) {
+            red[1][0] += (double)ov[u].re * (double)x.re + (double)ov[u].im * (double)x.im;
+            red[2][0] += (double)ov[u].re * (double)x.im - (double)ov[u].im * (double)x.re;
+          }
+        }
       }
     }
   }
@@ -889,7 +940,10 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
 
 // General mixed-radix systems (any 2 s_i <= 15, N <= 32).
 template <typename R, int KC>
-__global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, HvParams P) {
+__global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, const Cx<R> *__restrict__ pcg,
+                                                 const Cx<R> *__restrict__ czp, const Cx<R> *__restrict__ czm,
+                                                 const int2 *__restrict__ pij, const R *__restrict__ pzz,
+                                                 HvParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = g.n;
   Cx<R> *s_hoff = reinterpret_cast<Cx<R> *>(smem);  // [n][4][16]
@@ -936,8 +990,8 @@ __global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, HvP
     R diag = 0;
     for (int k = 0; k < n; k++) diag += s_hd[k * 16 + digit(k)];
     for (int p = 0; p < g.npair; p++) {
-      const int2 ij = tb.pij[p];
-      diag = fma(tb.pzz[p], s_m[ij.x * 16 + digit(ij.x)] * s_m[ij.y * 16 + digit(ij.y)], diag);
+      const int2 ij = pij[p];
+      diag = fma(pzz[p], s_m[ij.x * 16 + digit(ij.x)] * s_m[ij.y * 16 + digit(ij.y)], diag);
     }
     Acc<R, KC> acc;
     acc_zero(acc);
@@ -951,7 +1005,7 @@ __global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, HvP
         for (int l = 0; l < n; l++) {
           if (l == k) continue;
           const R ml = s_m[l * 16 + digit(l)];
-          const Cx<R> cp = tb.czp[k * n + l], cm = tb.czm[k * n + l];
+          const Cx<R> cp = czp[k * n + l], cm = czm[k * n + l];
           fpr = fma(cp.re, ml, fpr);
           fpi = fma(cp.im, ml, fpi);
           fmr = fma(cm.re, ml, fmr);
@@ -978,13 +1032,13 @@ __global__ __launch_bounds__(kBlock) void hv_gen(HamGeom g, DevTables<R> tb, HvP
       }
     }
     for (int p = 0; p < g.npair; p++) {
-      const int2 ij = tb.pij[p];
+      const int2 ij = pij[p];
       const int di = digit(ij.x), dj = digit(ij.y);
       const int ri = g.radix[ij.x], rj = g.radix[ij.y];
       const uint32_t si = g.stride[ij.x], sj = g.stride[ij.y];
       const R gpi = s_gp[ij.x * 16 + di], gmi = s_gm[ij.x * 16 + di];
       const R gpj = s_gp[ij.y * 16 + dj], gmj = s_gm[ij.y * 16 + dj];
-      const Cx<R> *pc = tb.pc + 4 * p;
+      const Cx<R> *pc = pcg + 4 * p;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         const Cx<R> cq = pc[q];
@@ -1523,9 +1577,17 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
 // General mixed radix: one 256-row slice of a window per item; the window's
 // rows are enumerated with the window sites' digits (lowest site fastest), the
 // outer digits come from the window index.
+// The tables read at wave-uniform addresses in loops (pair coefficients, the
+// z-field coupling tables, the diagonal pair list) come in as __restrict__
+// kernel arguments as well: the kernel's stores cannot alias them, so those
+// reads go through the scalar data cache instead of vector loads with a full
+// wait each.
 template <typename R, int KC>
 __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb, WinPass W,
-                                                     const int4 *__restrict__ plist, HvParams P) {
+                                                     const int4 *__restrict__ plist,
+                                                     const Cx<R> *__restrict__ pcg, const Cx<R> *__restrict__ czp,
+                                                     const Cx<R> *__restrict__ czm, const int2 *__restrict__ pij,
+                                                     const R *__restrict__ pzz, HvParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = g.n;
   Cx<R> *s_hoff = reinterpret_cast<Cx<R> *>(smem);  // [n][4][16]
@@ -1586,8 +1648,8 @@ __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb,
       R diag = 0;
       for (int k = 0; k < n; k++) diag += s_hd[k * 16 + digit(k)];
       for (int p = 0; p < g.npair; p++) {
-        const int2 ij = tb.pij[p];
-        diag = fma(tb.pzz[p], s_m[ij.x * 16 + digit(ij.x)] * s_m[ij.y * 16 + digit(ij.y)], diag);
+        const int2 ij = pij[p];
+        diag = fma(pzz[p], s_m[ij.x * 16 + digit(ij.x)] * s_m[ij.y * 16 + digit(ij.y)], diag);
       }
       mac_real(acc, diag, own);
     }
@@ -1600,7 +1662,7 @@ __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb,
         for (int l = 0; l < n; l++) {
           if (l == k) continue;
           const R ml = s_m[l * 16 + digit(l)];
-          const Cx<R> cp = tb.czp[k * n + l], cm = tb.czm[k * n + l];
+          const Cx<R> cp = czp[k * n + l], cm = czm[k * n + l];
           fpr = fma(cp.re, ml, fpr);
           fpi = fma(cp.im, ml, fpi);
           fmr = fma(cm.re, ml, fmr);
@@ -1633,7 +1695,7 @@ __global__ __launch_bounds__(kBlock) void hv_gen_win(HamGeom g, DevTables<R> tb,
       const uint32_t si = g.stride[pi_], sj = g.stride[pj_];
       const R gpi = s_gp[pi_ * 16 + di], gmi = s_gm[pi_ * 16 + di];
       const R gpj = s_gp[pj_ * 16 + dj], gmj = s_gm[pj_ * 16 + dj];
-      const Cx<R> *pc = tb.pc + 4 * pe.x;
+      const Cx<R> *pc = pcg + 4 * pe.x;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         const Cx<R> cq = pc[q];
@@ -1692,7 +1754,8 @@ static void launch_pass_t(const DevHam &dh, const DevTables<R> &tb, const PassPl
   const unsigned char *blk = reinterpret_cast<const unsigned char *>(plan.rec_block);
   hipLaunchKernelGGL((hv_pass<R, POW2, RPT>), grid, dim3(kBlock), sm, s, dh.geom, tb, plan.passes[ps],
                      plan.d_pairs, reinterpret_cast<const R *>(blk + plan.rec_off[ps]),
-                     reinterpret_cast<const uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps], P);
+                     reinterpret_cast<const uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps],
+                     tb.czp, tb.czm, tb.zz, P);
 }
 
 template <typename R>
@@ -1838,10 +1901,11 @@ static void launch_hv_t(const DevHam &dh, const DevTables<R> &tb, const HvParams
                         hipStream_t s) {
   const HamGeom &g = dh.geom;
   const size_t sm = hv_smem<R>(g);
+  const UniformTabs<R> U = uniform_tabs(tb, false);
   if (g.spin_half && g.n >= kLowBits)
-    hipLaunchKernelGGL((hv_half<R, KC>), grid, dim3(kBlock), sm, s, g, tb, P);
+    hipLaunchKernelGGL((hv_half<R, KC>), grid, dim3(kBlock), sm, s, g, tb, U.pij, U.pzz, P);
   else
-    hipLaunchKernelGGL((hv_gen<R, KC>), grid, dim3(kBlock), sm, s, g, tb, P);
+    hipLaunchKernelGGL((hv_gen<R, KC>), grid, dim3(kBlock), sm, s, g, tb, U.pc, U.czp, U.czm, U.pij, U.pzz, P);
 }
 
 template <typename R>
@@ -1855,7 +1919,7 @@ static void launch_hv_r(const DevHam &dh, const DevTables<R> &tb, const HvParams
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
       granted = sm;
     }
-    hipLaunchKernelGGL((hv_tile<R>), grid, dim3(kBlock), sm, s, dh.geom, tb, P);
+    hipLaunchKernelGGL((hv_tile<R>), grid, dim3(kBlock), sm, s, dh.geom, tb, tb.pij, tb.pc_half, tb.pzz, P);
     return;
   }
   switch (kc) {
@@ -1885,11 +1949,12 @@ static int launch_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &p
     } else {
       const size_t sm = sizeof(Cx<R>) * 64 * (size_t)g.n + sizeof(R) * 64 * g.n;
       const dim3 gk(gx, P.K / kc);
+      const UniformTabs<R> U = uniform_tabs(tb, false);
       switch (kc) {
-        case 8: hipLaunchKernelGGL((hv_gen_win<R, 8>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp); break;
-        case 4: hipLaunchKernelGGL((hv_gen_win<R, 4>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp); break;
-        case 2: hipLaunchKernelGGL((hv_gen_win<R, 2>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp); break;
-        default: hipLaunchKernelGGL((hv_gen_win<R, 1>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, Pp); break;
+        case 8: hipLaunchKernelGGL((hv_gen_win<R, 8>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, U.pc, U.czp, U.czm, U.pij, U.pzz, Pp); break;
+        case 4: hipLaunchKernelGGL((hv_gen_win<R, 4>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, U.pc, U.czp, U.czm, U.pij, U.pzz, Pp); break;
+        case 2: hipLaunchKernelGGL((hv_gen_win<R, 2>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, U.pc, U.czp, U.czm, U.pij, U.pzz, Pp); break;
+        default: hipLaunchKernelGGL((hv_gen_win<R, 1>), gk, dim3(kBlock), sm, s, g, tb, W, plan.d_plist, U.pc, U.czp, U.czm, U.pij, U.pzz, Pp); break;
       }
     }
     *last_gx = gx;
