@@ -208,9 +208,10 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   uint32_t smask = 0;
   for (int k = 0; k < n; k++)
     if (site_has_singles(hh, k)) smask |= 1u << k;
-  const size_t tbytes = tile_window_bytes_setting();
+  const size_t tbytes = tile_window_bytes_setting((uint64_t)hh.dim * 16);
+  const size_t tbytes32 = tile_window_bytes_setting((uint64_t)hh.dim * 8);
   const bool replan = !dh.plan_valid || dh.plan_smask != smask || dh.plan_wb != wb || dh.plan_l2b != l2b ||
-                      dh.plan_tb != tbytes;
+                      dh.plan_tb != tbytes || dh.plan_tb32 != tbytes32;
   if (replan) {
     int prc = plan_passes_sorted(hh, spi, spj, wb / 16, dh.plan64);
     if (!prc) prc = plan_passes_sorted(hh, spi, spj, wb / 8, dh.plan32);
@@ -229,7 +230,7 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
     dh.tw32 = WinPlan();
     if (hh.spin_half && n > kTileBits) {
       if (plan_l2_windows(hh, spi, spj, tbytes / 16, kTileBits, dh.tw64) ||
-          plan_l2_windows(hh, spi, spj, tbytes / 8, kTileBits, dh.tw32)) {
+          plan_l2_windows(hh, spi, spj, tbytes32 / 8, kTileBits, dh.tw32)) {
         dh.tw64 = WinPlan();
         dh.tw32 = WinPlan();
       }
@@ -239,6 +240,7 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
     dh.plan_wb = wb;
     dh.plan_l2b = l2b;
     dh.plan_tb = tbytes;
+    dh.plan_tb32 = tbytes32;
   }
   dh.plan64.window_bytes = wb;
   dh.plan32.window_bytes = wb;

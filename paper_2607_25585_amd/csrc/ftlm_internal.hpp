@@ -188,7 +188,7 @@ struct DevHam {
   // key of the plans above (recomputed only when it changes)
   bool plan_valid = false;
   uint32_t plan_smask = 0;
-  size_t plan_wb = 0, plan_l2b = 0, plan_tb = 0;
+  size_t plan_wb = 0, plan_l2b = 0, plan_tb = 0, plan_tb32 = 0;
   void *block = nullptr;  // device allocation holding every table
   size_t block_bytes = 0;
 };
@@ -205,7 +205,7 @@ size_t window_bytes_setting();
 int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
                     size_t window_rows, int lane_bits, WinPlan &plan);
 size_t l2_window_bytes_setting();
-size_t tile_window_bytes_setting();
+size_t tile_window_bytes_setting(uint64_t vec_bytes);  // window of the tile kernel for a vector of vec_bytes
 void sort_pairs(const HostHam &hh, std::vector<int> &perm, int &n_ll, int &n_lh,
                 int mx_off[kMaxSites + 1]);
 

@@ -1465,12 +1465,31 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
         }
       }
     }
-    // pairs inside the tile (i < j < 11)
+    // pairs inside the tile (i < j < 11); two consecutive pairs of two lane
+    // bits go together, so that the second pair's LDS reads are in flight
+    // during the first pair's FMAs (the accumulation order is unchanged)
 #pragma unroll 1
     for (int e = 0; e < n_in; e++) {
       const int4 ij = pl[e];
       const int i = ij.y, j = ij.z;
-      if (j < kLowBits) {  // two lane bits: one coefficient per thread, partner t ^ mask
+      if (j < kLowBits && e + 1 < n_in && pl[e + 1].z < kLowBits) {
+        const int4 ij2 = pl[e + 1];
+        const Cx<R> c = s_pc[4 * e + ((((l >> i) & 1) << 1) | ((l >> j) & 1))];
+        const Cx<R> c2 = s_pc[4 * (e + 1) + ((((l >> ij2.y) & 1) << 1) | ((l >> ij2.z) & 1))];
+        const int tf = tq ^ ((1 << i) | (1 << j)), tf2 = tq ^ ((1 << ij2.y) | (1 << ij2.z));
+        Cx<R> x[Q], x2[Q];
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          x[q] = own[q * kBlock + tf];
+          x2[q] = own[q * kBlock + tf2];
+        }
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          fma_cx(acc[q], c, x[q]);
+          fma_cx(acc[q], c2, x2[q]);
+        }
+        e++;
+      } else if (j < kLowBits) {  // two lane bits: one coefficient per thread, partner t ^ mask
         const Cx<R> c = s_pc[4 * e + ((((l >> i) & 1) << 1) | ((l >> j) & 1))];
         const int tf = tq ^ ((1 << i) | (1 << j));
 #pragma unroll
@@ -1537,6 +1556,28 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
         if (pe.z != a) break;
         const int i = pe.y;
         const Cx<R> clo = pch[4 * pe.x + ba], chi = pch[4 * pe.x + 2 + ba];
+        if (i < kLowBits && e + 1 < e_out) {
+          // two lane-bit mixed pairs of site a together when the next one is one
+          const int4 pe2 = pl[e + 1];
+          if (pe2.z == a && pe2.y < kLowBits) {
+            const Cx<R> clo2 = pch[4 * pe2.x + ba], chi2 = pch[4 * pe2.x + 2 + ba];
+            const Cx<R> c = ((l >> i) & 1) ? chi : clo, c2 = ((l >> pe2.y) & 1) ? chi2 : clo2;
+            const int tf = tq ^ (1 << i), tf2 = tq ^ (1 << pe2.y);
+            Cx<R> x[Q], x2[Q];
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+              x[q] = part[q * kBlock + tf];
+              x2[q] = part[q * kBlock + tf2];
+            }
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+              fma_cx(acc[q], c, x[q]);
+              fma_cx(acc[q], c2, x2[q]);
+            }
+            e++;
+            continue;
+          }
+        }
         if (i < kLowBits) {
           const Cx<R> c = ((l >> i) & 1) ? chi : clo;
           const int tf = tq ^ (1 << i);

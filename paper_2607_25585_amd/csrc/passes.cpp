@@ -413,9 +413,12 @@ int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::ve
   return FTLM_OK;
 }
 
-size_t tile_window_bytes_setting() {
+size_t tile_window_bytes_setting(uint64_t vec_bytes) {
   const char *e = std::getenv("FTLM_TILE_WINDOW_KB");
-  long kb = e ? std::atol(e) : 2048;
+  // default: 2 MB windows (two in flight per XCD fill its 4 MB L2); a vector of
+  // at most 160 MB stays in the 256 MB last-level cache, where one window over
+  // everything (a single pass) is faster
+  long kb = e ? std::atol(e) : (vec_bytes <= (160ull << 20) ? 65536 : 2048);
   if (kb < 4) kb = 4;
   if (kb > 65536) kb = 65536;
   return (size_t)kb * 1024;
