@@ -369,7 +369,9 @@ def main():
     sysm, spec = W.WORKLOADS[args.workload]()
     prec = F.FTLM_C128 if args.precision == "c128" else F.FTLM_C64
     ham = F.Hamiltonian(sysm)
-    K = args.columns if args.columns > 0 else (1 if ham.dim >= (1 << 20) else min(spec.R, 16))
+    # the library's default column count (ftlm_run_params.columns = 0)
+    K = args.columns if args.columns > 0 else (
+        1 if ham.dim >= (1 << 20) else min(spec.R, 4) if ham.dim >= (1 << 17) else min(spec.R, 16))
     ws = None
 
     def step(time_hv=False):

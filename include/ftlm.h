@@ -138,7 +138,8 @@ typedef struct {
   int32_t n_fields;
   int32_t precision;    /* ftlm_precision */
   int32_t columns;      /* K: random vectors iterated together, 1..64; 0 = automatic
-                           (1 for dim >= 2^20, else min(R, 16)) */
+                           (1 for dim >= 2^20, min(R, 4) for dim >= 2^17,
+                           else min(R, 16)) */
   const void *r_init;   /* optional device complex128 start vectors (not
                            normalised) replacing the generator, element (f, nu, r)
                            at offset (f*dim + nu)*R + r; NULL */
@@ -207,8 +208,10 @@ int ftlm_run_kpm(const ftlm_hamiltonian *h, const ftlm_run_params *p, int32_t n_
  * directions run together; every Lanczos step is one persistent launch over a
  * work queue of (curve, row tile) units for all curves of a wave, replayed as a
  * HIP graph.  per_inst[k] describes instance k (R, N_L, n_T, precision and
- * columns must agree across instances; columns = R).  out[k] receives instance
- * k's results.  Blocks on the stream before returning. */
+ * columns must agree across instances).  columns = random vectors per work item,
+ * one of 16, 8, 4, 2, 1 dividing R; 0 = automatic (4 when the largest instance
+ * has >= 2^17 rows, else the largest dividing R).  out[k] receives instance k's
+ * results.  Blocks on the stream before returning. */
 int ftlm_run_batched_workspace_size(const ftlm_hamiltonian *const *hs, int32_t n_inst,
                                     const ftlm_run_params *per_inst, size_t *bytes);
 int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst,

@@ -491,13 +491,20 @@ struct Carve {
   }
 };
 
-int pick_batch_k(int R, int requested) {
+// Columns per item: the requested count if it is one of 16, 8, 4, 2, 1 and
+// divides R; automatic: 4 once the largest instance has 2^17 rows or more (the
+// gathers of 16 interleaved columns then miss the caches), else the widest of
+// 16, 8, 4, 2, 1 dividing R.
+int pick_batch_k(int R, int requested, uint64_t max_dim) {
   const int opts[5] = {16, 8, 4, 2, 1};
   if (requested > 0) {
     for (int o : opts)
       if (o == requested && R % o == 0) return o;
     return -1;
   }
+  if (max_dim >= (1ull << 17))
+    for (int o : {4, 2, 1})
+      if (R % o == 0) return o;
   for (int o : opts)
     if (R % o == 0) return o;
   return 1;
@@ -574,7 +581,7 @@ int validate_batched(const ftlm_hamiltonian *const *hs, int n_inst, const ftlm_r
         return FTLM_EINVAL;
       }
   }
-  if (pick_batch_k(pp[0].R, pp[0].columns) < 0) {
+  if (pick_batch_k(pp[0].R, pp[0].columns, 0) < 0) {
     err = "columns must be one of 1, 2, 4, 8, 16 and divide R";
     return FTLM_EINVAL;
   }
@@ -582,7 +589,9 @@ int validate_batched(const ftlm_hamiltonian *const *hs, int n_inst, const ftlm_r
 }
 
 void make_plan_b(const ftlm_hamiltonian *const *hs, int n_inst, const ftlm_run_params *pp, PlanB &pl) {
-  pl.K = pick_batch_k(pp[0].R, pp[0].columns);
+  uint64_t max_dim = 0;
+  for (int k = 0; k < n_inst; k++) max_dim = std::max<uint64_t>(max_dim, hs[k]->host.dim);
+  pl.K = pick_batch_k(pp[0].R, pp[0].columns, max_dim);
   pl.R = pp[0].R;
   pl.NL = pp[0].n_lanczos;
   pl.nT = pp[0].n_T;
