@@ -34,6 +34,9 @@ struct RunPlan {
   uint64_t dim = 0;
   size_t buf[3], ov1, alpha, beta, yre, yim, sx, smax, done, nused, part, counter;
   size_t eps, q1, qy, nused_all, tri, T, dims, lnZ, E, C, M, emin;
+  // two staging slots of a wave's (alpha, beta, y_re, n_used) for the
+  // eigenpairs, which run on a second stream while the next wave iterates
+  size_t st_ab[2], st_nu[2], st_tri[2];
   size_t total = 0;
 };
 
@@ -92,6 +95,11 @@ void make_plan(const ftlm_hamiltonian *h, const ftlm_run_params *p, RunPlan &pl)
   pl.qy = c.take(sR * pl.NL);
   pl.nused_all = c.take(sizeof(int) * pl.R * pl.nF);
   pl.tri = c.take(sizeof(double) * 4 * pl.NL * pl.K);
+  for (int k = 0; k < 2; k++) {
+    pl.st_ab[k] = c.take(sK * pl.NL * 3);
+    pl.st_nu[k] = c.take(sizeof(int) * pl.K);
+    pl.st_tri[k] = c.take(sizeof(double) * 4 * pl.NL * pl.K);
+  }
   pl.T = c.take(sizeof(double) * pl.nT);
   pl.dims = c.take(sizeof(double));
   const size_t res = sizeof(double) * pl.nT * pl.nF;
@@ -219,9 +227,21 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
   hipGraph_t graph = nullptr;
   hipStream_t cap = nullptr;
   int exec_K = 0;
+  // eigenpairs of a finished wave run on s2 (default priority) while the next
+  // wave iterates on s; ev[0..1]: slot's inputs staged, ev[2..3]: slot's
+  // eigenpairs done, ev[4]: join before the Boltzmann sums
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   auto cleanup = [&]() {
     for (auto &x : events) if (x) (void)hipEventDestroy(x);
     events.clear();
+    if (s2) (void)hipStreamSynchronize(s2);
+    for (auto &x : ev) {
+      if (x) (void)hipEventDestroy(x);
+      x = nullptr;
+    }
+    if (s2) (void)hipStreamDestroy(s2);
+    s2 = nullptr;
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
@@ -236,6 +256,10 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
     return code;
   };
   std::vector<double> host_ab;
+  if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) return fail(FTLM_EHIP, "stream create failed");
+  for (auto &x : ev)
+    if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) return fail(FTLM_EHIP, "event create failed");
+  int wave = 0;
   for (int f = 0; f < pl.nF; f++) {
     if (p->fields) {
       rc = ftlm_hamiltonian_set_field(h, p->fields + 3 * f);
@@ -293,11 +317,27 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
         }
       }
       (void)exec_K;
-      rc = launch_tridiag(K, pl.NL, at<int>(ws, pl.nused), 1, pl.K, at<double>(ws, pl.alpha),
-                          at<double>(ws, pl.beta), at<double>(ws, pl.yre), at<double>(ws, pl.eps),
-                          at<double>(ws, pl.q1), at<double>(ws, pl.qy), pl.R, c0,
-                          at<double>(ws, pl.tri), s);
-      if (rc) return fail(rc, "tridiagonal launch failed");
+      {
+        // stage (alpha, beta, y_re, n_used) in this wave's slot once the slot's
+        // previous eigenpairs are done, then solve them on s2
+        const int slot = wave & 1;
+        const size_t ab = sizeof(double) * pl.K * pl.NL;
+        double *st = at<double>(ws, pl.st_ab[slot]);
+        int *snu = at<int>(ws, pl.st_nu[slot]);
+        if ((wave >= 2 && hipStreamWaitEvent(s, ev[2 + slot], 0) != hipSuccess) ||
+            hipMemcpyAsync(st, at<double>(ws, pl.alpha), ab, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(st + (size_t)pl.K * pl.NL, at<double>(ws, pl.beta), ab, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(st + 2 * (size_t)pl.K * pl.NL, at<double>(ws, pl.yre), ab, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(snu, at<int>(ws, pl.nused), sizeof(int) * K, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipEventRecord(ev[slot], s) != hipSuccess || hipStreamWaitEvent(s2, ev[slot], 0) != hipSuccess)
+          return fail(FTLM_EHIP, "staging of the tridiagonals failed");
+        rc = launch_tridiag(K, pl.NL, snu, 1, pl.K, st, st + (size_t)pl.K * pl.NL, st + 2 * (size_t)pl.K * pl.NL,
+                            at<double>(ws, pl.eps), at<double>(ws, pl.q1), at<double>(ws, pl.qy), pl.R, c0,
+                            at<double>(ws, pl.st_tri[slot]), s2);
+        if (rc) return fail(rc, "tridiagonal launch failed");
+        if (hipEventRecord(ev[2 + slot], s2) != hipSuccess) return fail(FTLM_EHIP, "event record failed");
+        wave++;
+      }
       if (hipMemcpyAsync(at<int>(ws, pl.nused_all) + (size_t)f * pl.R + c0, at<int>(ws, pl.nused),
                          sizeof(int) * K, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(FTLM_EHIP, "copy of n_used failed");
@@ -318,6 +358,8 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
       }
     }
     const size_t ro = (size_t)f * pl.nT;
+    if (hipEventRecord(ev[4], s2) != hipSuccess || hipStreamWaitEvent(s, ev[4], 0) != hipSuccess)
+      return fail(FTLM_EHIP, "join of the eigenpair stream failed");
     rc = launch_boltzmann(1, pl.R, pl.NL, at<int>(ws, pl.nused_all) + (size_t)f * pl.R,
                           at<double>(ws, pl.eps), at<double>(ws, pl.q1), at<double>(ws, pl.qy),
                           at<double>(ws, pl.dims), at<double>(ws, pl.T), pl.nT,
