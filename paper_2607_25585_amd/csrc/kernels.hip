@@ -1766,14 +1766,22 @@ static bool use_passes(const HamGeom &g, int K, int variant) {
   return K == 1 && g.dim >= (1u << 20) && !tile_ok(g, K);
 }
 
+// Rows per thread of a pass: 16 (4096-row windows), or 32 for complex64 windows
+// above 4096 rows (a 64 KB LDS window holds 8192 of them).  Windows of general
+// radix are usually smaller (5^5 = 3125 rows): with 16 rows per thread most
+// lanes stay busy.
 template <typename R>
-static constexpr int pass_rpt() { return sizeof(R) == 8 ? 16 : 32; }
+static int pass_rpt(const PassDesc &D) {
+  return (sizeof(R) == 4 && D.wsize > 16u * kBlock) ? 32 : 16;
+}
 
 static bool pass_pow2(const PassDesc &D) { return D.pow2 && D.na >= kLowBits && D.na - kLowBits <= 5; }
 
 template <typename R>
 static size_t pass_rec_len(const PassDesc &D) {
-  return pass_pow2(D) ? PassRec<R, true, pass_rpt<R>()>::kLen : PassRec<R, false, pass_rpt<R>()>::kLen;
+  const bool p2 = pass_pow2(D);
+  if (pass_rpt<R>(D) == 32) return p2 ? PassRec<R, true, 32>::kLen : PassRec<R, false, 32>::kLen;
+  return p2 ? PassRec<R, true, 16>::kLen : PassRec<R, false, 16>::kLen;
 }
 
 template <typename R>
@@ -1782,10 +1790,9 @@ static size_t pass_smem(const PassDesc &D) {
          sizeof(R) * (pass_rec_len<R>(D) + 64 * (size_t)D.na) + sizeof(int4) * (size_t)D.npp;
 }
 
-template <typename R, bool POW2>
+template <typename R, bool POW2, int RPT>
 static void launch_pass_t(const DevHam &dh, const DevTables<R> &tb, const PassPlan &plan, size_t ps,
                           const HvParams &P, dim3 grid, size_t sm, hipStream_t s) {
-  constexpr int RPT = pass_rpt<R>();
   static size_t granted = 0;
   if (sm > granted) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_pass<R, POW2, RPT>),
@@ -1805,34 +1812,46 @@ static int launch_passes(const DevHam &dh, const DevTables<R> &tb, const PassPla
   if (!plan.rec_block) return FTLM_EINVAL;
   for (size_t ps = 0; ps < plan.passes.size(); ps++) {
     const PassDesc &D = plan.passes[ps];
-    if (D.wsize > (uint32_t)(kBlock * pass_rpt<R>()) || D.nsing > kMaxPassSingles) return FTLM_ERANGE;
+    const int rpt = pass_rpt<R>(D);
+    if (D.wsize > (uint32_t)(kBlock * rpt) || D.nsing > kMaxPassSingles) return FTLM_ERANGE;
     const size_t sm = pass_smem<R>(D);
     if (sm > 160 * 1024) return FTLM_ERANGE;
     const int gx = (int)(D.nwin < (uint32_t)cap ? D.nwin : (uint32_t)cap);
     HvParams Pp = P;
     if (!D.last) Pp.lanczos = 0;
-    if (pass_pow2(D)) launch_pass_t<R, true>(dh, tb, plan, ps, Pp, dim3(gx, gy), sm, s);
-    else launch_pass_t<R, false>(dh, tb, plan, ps, Pp, dim3(gx, gy), sm, s);
+    const dim3 grid(gx, gy);
+    if (rpt == 32) {
+      if (pass_pow2(D)) launch_pass_t<R, true, 32>(dh, tb, plan, ps, Pp, grid, sm, s);
+      else launch_pass_t<R, false, 32>(dh, tb, plan, ps, Pp, grid, sm, s);
+    } else {
+      if (pass_pow2(D)) launch_pass_t<R, true, 16>(dh, tb, plan, ps, Pp, grid, sm, s);
+      else launch_pass_t<R, false, 16>(dh, tb, plan, ps, Pp, grid, sm, s);
+    }
     *last_gx = (unsigned)gx;
   }
   return FTLM_OK;
 }
 
+template <typename R, int RPT>
+static void launch_records(const DevHam &dh, const DevTables<R> &tb, const PassPlan &plan, size_t ps) {
+  unsigned char *blk = reinterpret_cast<unsigned char *>(plan.rec_block);
+  const PassDesc &D = plan.passes[ps];
+  const uint32_t gx = D.nwin < 65536u ? D.nwin : 65536u;
+  if (pass_pow2(D))
+    hipLaunchKernelGGL((pass_record_kernel<R, true, RPT>), dim3(gx), dim3(kBlock), 0, 0, dh.geom, tb, D,
+                       reinterpret_cast<R *>(blk + plan.rec_off[ps]),
+                       reinterpret_cast<uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps]);
+  else
+    hipLaunchKernelGGL((pass_record_kernel<R, false, RPT>), dim3(gx), dim3(kBlock), 0, 0, dh.geom, tb, D,
+                       reinterpret_cast<R *>(blk + plan.rec_off[ps]),
+                       reinterpret_cast<uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps]);
+}
+
 template <typename R>
 static int build_records_t(DevHam &dh, const DevTables<R> &tb, PassPlan &plan) {
-  constexpr int RPT = pass_rpt<R>();
-  unsigned char *blk = reinterpret_cast<unsigned char *>(plan.rec_block);
   for (size_t ps = 0; ps < plan.passes.size(); ps++) {
-    const PassDesc &D = plan.passes[ps];
-    const uint32_t gx = D.nwin < 65536u ? D.nwin : 65536u;
-    if (pass_pow2(D))
-      hipLaunchKernelGGL((pass_record_kernel<R, true, RPT>), dim3(gx), dim3(kBlock), 0, 0, dh.geom, tb, D,
-                         reinterpret_cast<R *>(blk + plan.rec_off[ps]),
-                         reinterpret_cast<uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps]);
-    else
-      hipLaunchKernelGGL((pass_record_kernel<R, false, RPT>), dim3(gx), dim3(kBlock), 0, 0, dh.geom, tb, D,
-                         reinterpret_cast<R *>(blk + plan.rec_off[ps]),
-                         reinterpret_cast<uint32_t *>(blk + plan.base_off[ps]), blk + plan.lane_off[ps]);
+    if (pass_rpt<R>(plan.passes[ps]) == 32) launch_records<R, 32>(dh, tb, plan, ps);
+    else launch_records<R, 16>(dh, tb, plan, ps);
     if (hipGetLastError() != hipSuccess) return FTLM_EHIP;
   }
   return FTLM_OK;

@@ -121,6 +121,8 @@ bool greedy_cover(const HostHam &hh, const std::vector<int> &pi, const std::vect
 
 }  // namespace
 
+constexpr int kPassRestarts = 256;  // randomised greedy restarts of the LDS-window cover
+
 int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
                        size_t window_rows, PassPlan &plan) {
   plan.passes.clear();
@@ -148,6 +150,17 @@ int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std:
       if (chunk > window_rows) break;
       Cover cv;
       if (!greedy_cover(hh, pi, pj, c, window_rows / chunk, max_active - c, cv)) continue;
+      // randomised restarts (fixed seed: the plan is reproducible); every pass
+      // saved is one read of v and one read and write of w
+      {
+        std::mt19937 rng(1234567u + (unsigned)c);
+        for (int r = 0; r < kPassRestarts && cv.extra.size() > 1; r++) {
+          Cover alt;
+          if (greedy_cover(hh, pi, pj, c, window_rows / chunk, max_active - c, alt, &rng) &&
+              alt.extra.size() < cv.extra.size())
+            cv = alt;
+        }
+      }
       // place sites with single flips that no pass holds yet
       for (int k = c; k < n; k++) {
         if (!need_single[k]) continue;

@@ -96,3 +96,29 @@ def test_batched_matches_plain_run():
         pl = F().run(h, 4, 35, T, seed=9, fields=fields[k], instance=k)
         for key in ("lnZ", "E", "C", "M"):
             assert np.max(np.abs(bat[k][key] - pl[key])) <= 1e-9 * np.max(np.abs(pl[key])) + 1e-12, (k, key)
+
+
+def test_batched_large_instances_default_columns():
+    """Instances of 2^18 rows (many 2048-row work units per item, so blocks walk
+    several units of one item with its tables staged once) next to a small
+    one, with the automatic column count (four per item here): FP64 batched
+    against the plain GPU run (itself tied to the oracle), FP32 batched within
+    the FP32 budget."""
+    rng = np.random.default_rng(4242)
+    systems = []
+    for n in (18, 18, 10):
+        s = W.random_small_system(rng, n, max_two_s=1)
+        s.two_s[:] = 1
+        systems.append(s)
+    fields = [W.unit_vectors(rng, 1) * 0.9 for _ in systems]
+    T = W.t_grid(20)
+    hams = [F().Hamiltonian(s) for s in systems]
+    print("case batched large instances dims", [h.dim for h in hams], flush=True)
+    b64 = F().run_batched(hams, 4, 25, T, fields, seed=5, precision=0)
+    b32 = F().run_batched(hams, 4, 25, T, fields, seed=5, precision=1)
+    for k, h in enumerate(hams):
+        pl = F().run(h, 4, 25, T, seed=5, fields=fields[k], instance=k)
+        for key in ("lnZ", "E", "C", "M"):
+            assert np.max(np.abs(b64[k][key] - pl[key])) <= 1e-9 * np.max(np.abs(pl[key])) + 1e-12, (k, key)
+        assert curve_err(b32[k]["C"][0], pl["C"][0]) < 1e-3, k
+        assert curve_err(b32[k]["M"][0], pl["M"][0]) < 1e-3, k
