@@ -8,7 +8,7 @@ Adam run in the library's HIP kernels (ftlm_mlp_forward / _backward,
 ftlm_adam_step); PyTorch only owns device memory and streams.  Training data
 are FTLM curves from the batched GPU path.  A gate (parameter domain and the
 disagreement of an ensemble of two networks) decides when to fall back to full
-FTLM, which also judges the surrogate's error.
+FTLM, which also measures the surrogate's error.
 
 Encodings (readings, not from the paper):
   inputs  -- J/3, d/5, 2 tilt/(pi/2) - 1, |B|/3.5 - 1, 2 theta/pi - 1,
