@@ -1021,20 +1021,20 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       set_error("batched Lanczos launch failed");
       return FTLM_EHIP;
     }
-    // Krylov eigenpairs of every column of the wave, written at the columns'
-    // global positions (curve * R + group * K + c)
-    for (size_t i = 0; i < nit; i++) {
-      const Item &itm = items[next + i];
-      const int gcol = (int)(itm.curve * R + itm.group * K);
-      rc = launch_tridiag(K, NL, S.nused + i * K, 1, (int)ncol, alpha + i * K, beta + i * K, yre + i * K,
+    // Krylov eigenpairs of every column of the wave in one launch: items are in
+    // (curve, group) order, so item j's columns sit at global positions
+    // curve * R + group * K + c = j * K + c and the wave's columns are contiguous
+    {
+      const int gcol = (int)(next * K);
+      rc = launch_tridiag((int)ncol, NL, S.nused, 1, (int)ncol, alpha, beta, yre,
                           reinterpret_cast<double *>(base + pl.eps), reinterpret_cast<double *>(base + pl.q1),
                           reinterpret_cast<double *>(base + pl.qy), (int)(ncurve * R), gcol,
-                          reinterpret_cast<double *>(wbase + o_tri) + (size_t)i * 4 * NL * K, s);
+                          reinterpret_cast<double *>(wbase + o_tri), s);
       if (rc) {
         set_error("tridiagonal launch failed");
         return rc;
       }
-      if (hipMemcpyAsync(reinterpret_cast<int *>(base + pl.nused_all) + gcol, S.nused + i * K, sizeof(int) * K,
+      if (hipMemcpyAsync(reinterpret_cast<int *>(base + pl.nused_all) + gcol, S.nused, sizeof(int) * ncol,
                          hipMemcpyDeviceToDevice, s) != hipSuccess) {
         set_error("copy of n_used failed");
         return FTLM_EHIP;
