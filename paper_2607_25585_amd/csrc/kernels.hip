@@ -94,7 +94,27 @@ struct HvParams {
   double *alpha_out, *yre_out, *yim_out;
 };
 
-template <typename R, int KC>
+// Streaming (non-temporal) loads and stores for vectors touched once per pass
+// (partial sums of w, the Lanczos epilogue's operands): keeping them out of L2
+// leaves it to the window's v tiles that the outer pairs gather.
+template <typename R>
+using V2 = R __attribute__((ext_vector_type(2)));
+
+template <typename R>
+__device__ __forceinline__ Cx<R> ld_stream(const Cx<R> *p) {
+  const V2<R> v = __builtin_nontemporal_load(reinterpret_cast<const V2<R> *>(p));
+  return Cx<R>{v.x, v.y};
+}
+
+template <typename R>
+__device__ __forceinline__ void st_stream(Cx<R> *p, const Cx<R> &x) {
+  V2<R> v;
+  v.x = x.re;
+  v.y = x.im;
+  __builtin_nontemporal_store(v, reinterpret_cast<V2<R> *>(p));
+}
+
+template <typename R, int KC, bool STREAM = false>
 __device__ __forceinline__ void hv_epilogue(const HvParams &P, uint32_t row, int c0,
                                             const Acc<R, KC> &acc, const Cx<R> *own,
                                             double (&red)[3][KC]) {
@@ -115,17 +135,18 @@ __device__ __forceinline__ void hv_epilogue(const HvParams &P, uint32_t row, int
     double wr = (double)acc.re[q] * sx, wi = (double)acc.im[q] * sx;
     if (xp) {
       const double bp = P.beta_prev[c0 + q] * P.sx_prev[c0 + q];
-      Cx<R> a = xp[q];
+      Cx<R> a = STREAM ? ld_stream(xp + q) : xp[q];
       wr -= bp * (double)a.re;
       wi -= bp * (double)a.im;
     }
     Cx<R> out{(R)wr, (R)wi};
-    w[q] = out;
+    if (STREAM) st_stream(w + q, out);
+    else w[q] = out;
     Cx<R> xo = own[q];
     // alpha partial uses the stored (rounded) w so that the update sees the same numbers
     red[0][q] += (double)xo.re * (double)out.re + (double)xo.im * (double)out.im;
     if (o1) {
-      Cx<R> ov = o1[q];
+      Cx<R> ov = STREAM ? ld_stream(o1 + q) : o1[q];
       red[1][q] += (double)ov.re * (double)xo.re + (double)ov.im * (double)xo.im;
       red[2][q] += (double)ov.re * (double)xo.im - (double)ov.im * (double)xo.re;
     }
@@ -1593,7 +1614,7 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
     Cx<R> wprev[Q];
     Cx<R> *wt = reinterpret_cast<Cx<R> *>(P.w) + (size_t)base * K + c0;
 #pragma unroll
-    for (int q = 0; q < Q; q++) wprev[q] = W.first ? Cx<R>{0, 0} : wt[q * QS * K + tk];
+    for (int q = 0; q < Q; q++) wprev[q] = W.first ? Cx<R>{0, 0} : ld_stream(wt + q * QS * K + tk);
     // pairs of two outer sites, NB at a time
     {
       const Cx<R> *vc = v + c0;
@@ -1608,8 +1629,8 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
       a1.re[0] = acc[q].re + wprev[q].re;
       a1.im[0] = acc[q].im + wprev[q].im;
       const uint32_t row = base + q * kBlock + tq;
-      if (W.last) hv_epilogue<R, 1>(P, row, c0, a1, own + q * kBlock + tq, red);
-      else wt[q * QS * K + tk] = Cx<R>{a1.re[0], a1.im[0]};
+      if (W.last) hv_epilogue<R, 1, true>(P, row, c0, a1, own + q * kBlock + tq, red);
+      else st_stream(wt + q * QS * K + tk, Cx<R>{a1.re[0], a1.im[0]});
     }
   });
   if (W.last) hv_finish<1, NT>(P, red);
