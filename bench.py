@@ -201,13 +201,21 @@ def surrogate_report(n_train, n_test, train_s):
                                        precision=0)
     torch.cuda.synchronize()
     t_ftlm64 = time.perf_counter() - t0
+    print("surrogate: %d held-out FP64 curves in %.1f s" % (n_test, t_ftlm64), file=sys.stderr, flush=True)
     x = S.encode_inputs(ptrain, T)
     y = S.encode_targets(lz, mm, cc, T)
     models, losses = [], []
     t0 = time.perf_counter()
     for seed in (0, 1):
         m = S.MLP(seed=seed)
-        losses.append(S.train(m, x, y, epochs=400, batch=4096, lr=2e-3, seed=seed, time_budget_s=train_s)[-1])
+        last = [time.perf_counter()]
+
+        def progress(ep, loss, last=last, seed=seed):
+            if time.perf_counter() - last[0] > 20.0:
+                print("surrogate: member %d epoch %d loss %.3g" % (seed, ep, loss), file=sys.stderr, flush=True)
+                last[0] = time.perf_counter()
+        losses.append(S.train(m, x, y, epochs=400, batch=4096, lr=2e-3, seed=seed, time_budget_s=train_s,
+                              progress=progress)[-1])
         models.append(m)
         print("surrogate: member %d trained" % seed, file=sys.stderr, flush=True)
     t_train = time.perf_counter() - t0
@@ -338,9 +346,9 @@ def main():
                     help="sFTLM (ring6), Chebyshev vs Lanczos (cfg1) and Mn9 powder throughput")
     ap.add_argument("--surrogate", action="store_true",
                     help="surrogate report on the s=3/2 ring data instead of the FTLM curve bench")
-    ap.add_argument("--surrogate-train", type=int, default=4000)
-    ap.add_argument("--surrogate-test", type=int, default=200)
-    ap.add_argument("--surrogate-train-s", type=float, default=150.0)
+    ap.add_argument("--surrogate-train", type=int, default=20000)
+    ap.add_argument("--surrogate-test", type=int, default=1000)
+    ap.add_argument("--surrogate-train-s", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "

@@ -6,6 +6,7 @@
 // L = 1/(3B) sum (y - t)^2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -44,6 +45,7 @@ __device__ __forceinline__ float dsilu(float z) {
 //   3: backward:        g = C * silu'(zin[m][n]) -> zf (fp32) and ob (bf16)
 struct GemmArgs {
   int M, N, K;
+  int ksplit;  // mode 2: K split over blockIdx.z, partial products at zf + z*M*N (0 or 1: none)
   const uint16_t *A;
   long sam, sak;
   const uint16_t *B;
@@ -60,25 +62,30 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   __shared__ uint16_t Bs[16][64 + 4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  // K range of this block (all of K unless split)
+  const int ks = g.ksplit > 1 ? g.ksplit : 1;
+  const int kchunk = ((g.K + ks - 1) / ks + 15) & ~15;
+  const int kb = (int)blockIdx.z * kchunk, ke = min(g.K, kb + kchunk);
+  float *zf = g.zf + (ks > 1 ? (long)blockIdx.z * g.M * g.N : 0L);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
     for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       const int idx = t + 256 * e;  // 0..1023
       {
         const int r = idx >> 4, c = idx & 15;
         const int m = m0 + r, k = k0 + c;
-        As[r][c] = (m < g.M && k < g.K) ? g.A[(long)m * g.sam + (long)k * g.sak] : (uint16_t)0;
+        As[r][c] = (m < g.M && k < ke) ? g.A[(long)m * g.sam + (long)k * g.sak] : (uint16_t)0;
       }
       {
         const int r = idx >> 6, c = idx & 63;
         const int k = k0 + r, n = n0 + c;
-        Bs[r][c] = (k < g.K && n < g.N) ? g.B[(long)k * g.sbk + (long)n * g.sbn] : (uint16_t)0;
+        Bs[r][c] = (k < ke && n < g.N) ? g.B[(long)k * g.sbk + (long)n * g.sbn] : (uint16_t)0;
       }
     }
     __syncthreads();
@@ -117,7 +124,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
         } else if (g.mode == 1) {
           g.zf[o] = c + g.bias[n];
         } else if (g.mode == 2) {
-          g.zf[o] = c;
+          zf[o] = c;
         } else {
           c *= dsilu(g.zin[o]);
           g.zf[o] = c;
@@ -126,9 +133,40 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
       }
 }
 
+// out[i] = sum_z part[z][i] in split order
+__global__ void splitk_sum_kernel(const float *part, int splits, long n, float *out) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < splits; z++) s += part[(long)z * n + i];
+    out[i] = s;
+  }
+}
+
 void gemm(const GemmArgs &a, hipStream_t s) {
-  dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
+  dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, a.ksplit > 1 ? a.ksplit : 1);
   hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, a);
+}
+
+// Plain GEMM (mode 2) with a long K and few output tiles (the weight gradients:
+// K = batch): K is split over up to kMaxSplit blocks per tile, the partial
+// products go to scratch and are summed in split order.
+constexpr int kMaxSplit = 16;
+void gemm_splitk(GemmArgs a, float *scratch, hipStream_t s) {
+  const int tiles = ((a.N + 63) / 64) * ((a.M + 63) / 64);
+  int splits = std::min(kMaxSplit, std::max(1, (a.K + 255) / 256));
+  if (tiles >= 256) splits = 1;
+  if (splits <= 1) {
+    a.ksplit = 1;
+    gemm(a, s);
+    return;
+  }
+  float *out = a.zf;
+  a.ksplit = splits;
+  a.zf = scratch;
+  gemm(a, s);
+  const long n = (long)a.M * a.N;
+  hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)std::min<long>((n + 255) / 256, 1024)), dim3(256), 0, s,
+                     scratch, splits, n, out);
 }
 
 __global__ void to_bf16_kernel(const float *x, uint16_t *y, long n) {
@@ -159,13 +197,24 @@ __global__ void loss_kernel(const float *y, const float *tg, int n, float *dyf, 
   if (threadIdx.x == 0 && loss) *loss = red[0] / (float)n;
 }
 
-// db[n] = sum_b g[b][n]
-__global__ void colsum_kernel(const float *g, int rows, int cols, float *db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= cols) return;
+// db[n] = sum_b g[b][n].  A block of 256 threads takes 16 columns: thread t sums
+// rows t/16, t/16 + 16, ... of column t % 16 (16 lanes read 64 contiguous bytes),
+// then the 16 row phases are added in order -- a fixed summation order, and
+// rows/16 independent loads per thread instead of one serial chain over rows.
+__global__ __launch_bounds__(256) void colsum_kernel(const float *g, int rows, int cols, float *db) {
+  __shared__ float part[16][16];
+  const int c = threadIdx.x & 15, ph = threadIdx.x >> 4;
+  const int n = blockIdx.x * 16 + c;
   float s = 0.f;
-  for (int b = 0; b < rows; b++) s += g[(long)b * cols + n];
-  db[n] = s;
+  if (n < cols)
+    for (int b = ph; b < rows; b += 16) s += g[(long)b * cols + n];
+  part[ph][c] = s;
+  __syncthreads();
+  if (threadIdx.x < 16 && n < cols) {
+    float t = 0.f;
+    for (int q = 0; q < 16; q++) t += part[q][c];
+    db[n] = t;
+  }
 }
 
 __global__ void adam_kernel(long n, float *p, const float *g, float *m, float *v, uint16_t *pb,
@@ -191,6 +240,7 @@ struct MlpWs {
   uint16_t *gb[2];       // [B][256] gradient (bf16), ping-pong
   float *dyf;            // [B][3]
   uint16_t *dyb;         // [B][3]
+  float *splitk;         // [kMaxSplit][256][256] partial weight gradients
   size_t bytes;
 };
 
@@ -210,6 +260,7 @@ MlpWs layout(int B, void *base) {
   for (int k = 0; k < 2; k++) w.gb[k] = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * B * kHid));
   w.dyf = reinterpret_cast<float *>(take(sizeof(float) * B * kOut));
   w.dyb = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * B * kOut));
+  w.splitk = reinterpret_cast<float *>(take(sizeof(float) * kMaxSplit * kHid * kHid));
   w.bytes = (off + 255) & ~size_t(255);
   return w;
 }
@@ -317,8 +368,8 @@ int ftlm_mlp_backward(const ftlm_mlp_weights *w, int32_t B, const float *t, floa
     gw.sbn = 1;
     gw.mode = 2;
     gw.zf = dW[k];
-    gemm(gw, s);
-    hipLaunchKernelGGL(colsum_kernel, dim3((kFanOut[k] + 255) / 256), dim3(256), 0, s, gin_f, B, kFanOut[k],
+    gemm_splitk(gw, L.splitk, s);
+    hipLaunchKernelGGL(colsum_kernel, dim3((kFanOut[k] + 15) / 16), dim3(256), 0, s, gin_f, B, kFanOut[k],
                        db[k]);
     if (k == 0) break;
     // g_{k-1} = (g W_k^T) * silu'(z_{k-1})

@@ -208,8 +208,12 @@ def generate_dataset(params: np.ndarray, T: np.ndarray, R: int = 20, n_lanczos: 
 
 
 def train(model: MLP, x: np.ndarray, y: np.ndarray, epochs: int = 20, batch: int = 4096,
-          lr: float = 2e-3, seed: int = 0, time_budget_s: Optional[float] = None):
-    """Adam on mean squared error; cosine learning-rate decay.  Returns losses."""
+          lr: float = 2e-3, seed: int = 0, time_budget_s: Optional[float] = None, progress=None):
+    """Adam on mean squared error; cosine learning-rate decay.  Returns losses.
+
+    With a time budget, the epoch count is cut after the first epoch to what
+    fits in the budget, so that the cosine decay still reaches its end.
+    progress(epoch, loss), if given, is called after every epoch."""
     torch = _torch()
     X = torch.as_tensor(np.asarray(x, np.float32), device="cuda")
     Y = torch.as_tensor(np.asarray(y, np.float32), device="cuda")
@@ -227,8 +231,17 @@ def train(model: MLP, x: np.ndarray, y: np.ndarray, epochs: int = 20, batch: int
             ep_loss = ep_loss + model.train_step(X[idx], Y[idx], cur_lr)[0]
             it += 1
         losses.append(float(ep_loss) / steps_per_epoch)
-        if time_budget_s is not None and time.time() - t0 > time_budget_s:
+        if progress is not None:
+            progress(ep, losses[-1])
+        if time_budget_s is not None and ep == 0:
+            fit = max(1, int(time_budget_s / max(time.time() - t0, 1e-6)))
+            if fit < epochs:  # the cosine decay now ends with the last epoch that fits
+                epochs = fit
+                total = epochs * steps_per_epoch
+        if ep + 1 >= epochs:
             break
+        if time_budget_s is not None and time.time() - t0 > 1.5 * time_budget_s:
+            break  # the first epoch underestimated the rest
     return losses
 
 
