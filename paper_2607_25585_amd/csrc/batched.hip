@@ -27,6 +27,7 @@ namespace ftlm {
 // grid is kept small enough that the units in flight at any time cover about
 // two large items, so the partners an item's gathers touch stay in the caches.
 constexpr uint32_t kUnitRows = 2048;
+constexpr int kUnitBits = 11;  // log2(kUnitRows): a unit's rows share their bits >= 11
 
 template <typename R>
 struct BItem {
@@ -80,7 +81,7 @@ __host__ __device__ inline size_t staged_bytes(int n, int npair, bool half, size
   auto a16 = [](size_t b) { return (b + 15) & ~size_t(15); };
   size_t b = a16((size_t)n * 16 * rs) + 2 * a16((size_t)n * n * cs) + a16((size_t)npair * 8) +
              a16((size_t)npair * rs) + a16((size_t)npair * 4 * cs);
-  if (half) b += a16((size_t)n * 2 * cs);
+  if (half) b += a16((size_t)n * 2 * cs) + a16((size_t)n * 2 * cs);  // hflip, unit z-field
   else b += 3 * a16((size_t)n * 16 * rs) + a16((size_t)n * 64 * cs);
   return b;
 }
@@ -110,6 +111,10 @@ __device__ __forceinline__ DevTables<R> table_layout(const BItem<R> &it, bool mo
     d.pc_half = reinterpret_cast<const Cx<R> *>(lds + off);
     off += a16((size_t)np * 4 * cs);
     d.hflip = reinterpret_cast<const Cx<R> *>(lds + off);
+    off += a16((size_t)n * 2 * cs);
+    // z-field of the sites >= 11 for the current 2048-row unit, [k][b] (filled
+    // per unit by bhv_kernel: those row bits are the unit's)
+    d.cz_half = reinterpret_cast<const Cx<R> *>(lds + off);
   } else {
     d.pc = reinterpret_cast<const Cx<R> *>(lds + off);
     off += a16((size_t)np * 4 * cs);
@@ -185,9 +190,10 @@ __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb,
     for (int k = 0; k < n; k++) {
       const int b = (row >> k) & 1;
       Cx<R> c = tb.hflip[2 * k + b];
-      if (has_z) {
+      if (has_z) {  // sites < 11 per row, sites >= 11 from the unit's table
         R f0r = 0, f0i = 0, f1r = 0, f1i = 0;
-        for (int l = 0; l < n; l++) {
+        const int lmax = n < kUnitBits ? n : kUnitBits;
+        for (int l = 0; l < lmax; l++) {
           if (l == k) continue;
           const R ml = ((row >> l) & 1) ? R(0.5) : R(-0.5);
           const Cx<R> cm = tb.czm[k * n + l], cp = tb.czp[k * n + l];
@@ -196,8 +202,9 @@ __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb,
           f1r = fma(cp.re, ml, f1r);
           f1i = fma(cp.im, ml, f1i);
         }
-        c.re += b ? f1r : f0r;
-        c.im += b ? f1i : f0i;
+        const Cx<R> fh = tb.cz_half[2 * k + b];
+        c.re += (b ? f1r : f0r) + fh.re;
+        c.im += (b ? f1i : f0i) + fh.im;
       }
       bmac<R, KC>(acc, c.re, c.im, v + (size_t)(row ^ (1u << k)) * KC);
     }
@@ -351,6 +358,23 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
     }
     const DevTables<R> lt = table_layout(it, S.mode == 0, smem);
     const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
+    if (it.half && it.has_z && S.mode != 0) {
+      // z-field of the sites >= 11 for this unit: F_k^b = sum_{l >= 11, l != k} C^b_kl m_l(r0)
+      const int n = it.n;
+      if ((int)threadIdx.x < 2 * n) {
+        const int k = threadIdx.x >> 1, b = threadIdx.x & 1;
+        R fr = 0, fi = 0;
+        for (int l = kUnitBits; l < n; l++) {
+          if (l == k) continue;
+          const R ml = ((r0 >> l) & 1) ? R(0.5) : R(-0.5);
+          const Cx<R> c = b ? lt.czp[k * n + l] : lt.czm[k * n + l];
+          fr = fma(c.re, ml, fr);
+          fi = fma(c.im, ml, fi);
+        }
+        const_cast<Cx<R> *>(lt.cz_half)[threadIdx.x] = Cx<R>{fr, fi};
+      }
+      __syncthreads();
+    }
     const bool moment = S.mode == 0;
     const Cx<R> *v = moment ? it.x[0] : it.x[j % 3];
     Cx<R> *w = moment ? it.ov1 : it.x[(j + 1) % 3];
