@@ -28,6 +28,9 @@ namespace ftlm {
 // two large items, so the partners an item's gathers touch stay in the caches.
 constexpr uint32_t kUnitRows = 2048;
 constexpr int kUnitBits = 11;  // log2(kUnitRows): a unit's rows share their bits >= 11
+// the z-field tables split a spin-1/2 row into bits 0..7 (two nibbles), 8..10
+// (the unit table's index) and >= 11 (the unit's)
+static_assert(kUnitRows == (1u << kUnitBits) && kUnitBits == 11, "z-field table split assumes 2048-row units");
 
 template <typename R>
 struct BItem {
@@ -81,7 +84,8 @@ __host__ __device__ inline size_t staged_bytes(int n, int npair, bool half, size
   auto a16 = [](size_t b) { return (b + 15) & ~size_t(15); };
   size_t b = a16((size_t)n * 16 * rs) + 2 * a16((size_t)n * n * cs) + a16((size_t)npair * 8) +
              a16((size_t)npair * rs) + a16((size_t)npair * 4 * cs);
-  if (half) b += a16((size_t)n * 2 * cs) + a16((size_t)n * 2 * cs);  // hflip, unit z-field
+  // hflip; lane-bit z-field tables [2 nibbles][k][b][16]; unit table [k][b][8]
+  if (half) b += a16((size_t)n * 2 * cs) + a16((size_t)2 * n * 2 * 16 * cs) + a16((size_t)n * 2 * 8 * cs);
   else b += 3 * a16((size_t)n * 16 * rs) + a16((size_t)n * 64 * cs);
   return b;
 }
@@ -112,9 +116,13 @@ __device__ __forceinline__ DevTables<R> table_layout(const BItem<R> &it, bool mo
     off += a16((size_t)np * 4 * cs);
     d.hflip = reinterpret_cast<const Cx<R> *>(lds + off);
     off += a16((size_t)n * 2 * cs);
-    // z-field of the sites >= 11 for the current 2048-row unit, [k][b] (filled
-    // per unit by bhv_kernel: those row bits are the unit's)
+    // z-field F_k^b(row) = sum_{l != k} C^b_kl m_l(row) split by row bits:
+    // cz_half [nibble j < 2][k][b][v]: the sites 4j..4j+3 (lane bits) for
+    // nibble value v (staged per item); lowf [k][b][i]: the sites >= 8 for row
+    // bits 8..10 = i and the current unit's bits >= 11 (filled per unit)
     d.cz_half = reinterpret_cast<const Cx<R> *>(lds + off);
+    off += a16((size_t)2 * n * 2 * 16 * cs);
+    d.lowf = reinterpret_cast<const Cx<R> *>(lds + off);
   } else {
     d.pc = reinterpret_cast<const Cx<R> *>(lds + off);
     off += a16((size_t)np * 4 * cs);
@@ -154,6 +162,21 @@ __device__ void stage_tables(const BItem<R> &it, bool moment, unsigned char *lds
   if (it.half) {
     stage_copy(d.pc_half, src.pc_half, (size_t)np * 4);
     stage_copy(d.hflip, src.hflip, (size_t)n * 2);
+    if (hz) {
+      Cx<R> *T = const_cast<Cx<R> *>(d.cz_half);
+      for (int e = threadIdx.x; e < 2 * n * 32; e += kBlock) {
+        const int v = e & 15, b = (e >> 4) & 1, k = (e >> 5) % n, j = (e >> 5) / n;
+        R fr = 0, fi = 0;
+        for (int l = 4 * j; l < 4 * j + 4 && l < n; l++) {
+          if (l == k) continue;
+          const R ml = ((v >> (l - 4 * j)) & 1) ? R(0.5) : R(-0.5);
+          const Cx<R> c = b ? src.czp[k * n + l] : src.czm[k * n + l];
+          fr = fma(c.re, ml, fr);
+          fi = fma(c.im, ml, fi);
+        }
+        T[e] = Cx<R>{fr, fi};
+      }
+    }
   } else {
     stage_copy(d.pc, src.pc, (size_t)np * 4);
     stage_copy(d.mval, src.mval, (size_t)n * 16);
@@ -190,21 +213,12 @@ __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb,
     for (int k = 0; k < n; k++) {
       const int b = (row >> k) & 1;
       Cx<R> c = tb.hflip[2 * k + b];
-      if (has_z) {  // sites < 11 per row, sites >= 11 from the unit's table
-        R f0r = 0, f0i = 0, f1r = 0, f1i = 0;
-        const int lmax = n < kUnitBits ? n : kUnitBits;
-        for (int l = 0; l < lmax; l++) {
-          if (l == k) continue;
-          const R ml = ((row >> l) & 1) ? R(0.5) : R(-0.5);
-          const Cx<R> cm = tb.czm[k * n + l], cp = tb.czp[k * n + l];
-          f0r = fma(cm.re, ml, f0r);
-          f0i = fma(cm.im, ml, f0i);
-          f1r = fma(cp.re, ml, f1r);
-          f1i = fma(cp.im, ml, f1i);
-        }
-        const Cx<R> fh = tb.cz_half[2 * k + b];
-        c.re += (b ? f1r : f0r) + fh.re;
-        c.im += (b ? f1i : f0i) + fh.im;
+      if (has_z) {  // three table reads: row bits 0..3, 4..7, and 8.. (unit table)
+        const Cx<R> f0 = tb.cz_half[((size_t)k * 2 + b) * 16 + (row & 15u)];
+        const Cx<R> f1 = tb.cz_half[((size_t)(n + k) * 2 + b) * 16 + ((row >> 4) & 15u)];
+        const Cx<R> f2 = tb.lowf[((size_t)k * 2 + b) * 8 + ((row >> 8) & 7u)];
+        c.re += f0.re + f1.re + f2.re;
+        c.im += f0.im + f1.im + f2.im;
       }
       bmac<R, KC>(acc, c.re, c.im, v + (size_t)(row ^ (1u << k)) * KC);
     }
@@ -359,19 +373,21 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
     const DevTables<R> lt = table_layout(it, S.mode == 0, smem);
     const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
     if (it.half && it.has_z && S.mode != 0) {
-      // z-field of the sites >= 11 for this unit: F_k^b = sum_{l >= 11, l != k} C^b_kl m_l(r0)
+      // z-field of the sites >= 8 for the unit's rows with bits 8..10 = i:
+      // F_k^b(i) = sum_{l >= 8, l != k} C^b_kl m_l
       const int n = it.n;
-      if ((int)threadIdx.x < 2 * n) {
-        const int k = threadIdx.x >> 1, b = threadIdx.x & 1;
+      for (int e = threadIdx.x; e < n * 16; e += kBlock) {
+        const int i = e & 7, b = (e >> 3) & 1, k = e >> 4;
+        const uint32_t rb = r0 | ((uint32_t)i << 8);
         R fr = 0, fi = 0;
-        for (int l = kUnitBits; l < n; l++) {
+        for (int l = 8; l < n; l++) {
           if (l == k) continue;
-          const R ml = ((r0 >> l) & 1) ? R(0.5) : R(-0.5);
+          const R ml = ((rb >> l) & 1) ? R(0.5) : R(-0.5);
           const Cx<R> c = b ? lt.czp[k * n + l] : lt.czm[k * n + l];
           fr = fma(c.re, ml, fr);
           fi = fma(c.im, ml, fi);
         }
-        const_cast<Cx<R> *>(lt.cz_half)[threadIdx.x] = Cx<R>{fr, fi};
+        const_cast<Cx<R> *>(lt.lowf)[e] = Cx<R>{fr, fi};
       }
       __syncthreads();
     }
