@@ -124,6 +124,8 @@ struct PassDesc {
   int irad[kMaxSites];
   uint32_t ist[kMaxSites];
   int sing[kMaxSites];      // active positions whose single flips this pass applies
+  int ctab;                 // general radix: entries of the pass's pair-coefficient table
+                            // (sum over its pairs of 4 radix_i radix_j)
 };
 
 struct PassPlan {

@@ -690,6 +690,10 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
   R *s_gm = s_gp + 16 * na;                            // [na][16]
   R *s_m = s_gm + 16 * na;                             // [na][16]
   int4 *s_pi = reinterpret_cast<int4 *>(s_m + 16 * na);  // [npp]
+  // general radix: pair coefficients with the ladder factors and the validity
+  // folded in, per pair [d_i][d_j][type] (0 where a digit leaves its range)
+  int *s_toff = reinterpret_cast<int *>(s_pi + npp);     // [npp + 1]
+  Cx<R> *s_ct = reinterpret_cast<Cx<R> *>(smem + ((reinterpret_cast<unsigned char *>(s_toff + npp + 1) - smem + 15) & ~(size_t)15));
   const int t = threadIdx.x;
   const int K = P.K, c0 = blockIdx.y;
 
@@ -712,6 +716,34 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
   for (int i = t; i < D.nsing * 64; i += kBlock) {
     const int k = D.act[D.sing[i / 64]];
     s_hoff[i] = tb.hoff[k * 64 + (i & 63)];
+  }
+  // the table pays off at complex128; at complex64 the per-row factors are faster
+  const int ctab = (!POW2 && sizeof(R) == 8) ? D.ctab : 0;
+  if (ctab > 0) {
+    if (t == 0) {
+      int o = 0;
+      for (int e = 0; e < npp; e++) {
+        s_toff[e] = o;
+        const int4 pe = pp[D.pp_off + e];
+        o += 4 * D.wrad[pe.y] * D.wrad[pe.z];
+      }
+      s_toff[npp] = o;
+    }
+    __syncthreads();
+    for (int idx = t; idx < ctab; idx += kBlock) {
+      int e = 0;
+      while (e + 1 < npp && s_toff[e + 1] <= idx) e++;
+      const int4 pe = pp[D.pp_off + e];
+      const int ai = pe.y, aj = pe.z, ri = D.wrad[ai], rj = D.wrad[aj];
+      const int loc = idx - s_toff[e], ty = loc & 3, dd = loc >> 2, di = dd / rj, dj = dd - di * rj;
+      const bool im_ = (ty >> 1) != 0, jm = (ty & 1) != 0;
+      const bool ok = (im_ ? (di <= ri - 2) : (di >= 1)) && (jm ? (dj <= rj - 2) : (dj >= 1));
+      const Cx<R> cq = tb.pc[4 * pe.x + ty];
+      const R f = ok ? (im_ ? tb.gm[D.act[ai] * 16 + di] : tb.gp[D.act[ai] * 16 + di]) *
+                           (jm ? tb.gm[D.act[aj] * 16 + dj] : tb.gp[D.act[aj] * 16 + dj])
+                     : R(0);
+      s_ct[idx] = Cx<R>{cq.re * f, cq.im * f};
+    }
   }
   // per-thread rows: packed active digits and offset within the full basis
   uint32_t dig[RPT], gof[RPT];
@@ -881,7 +913,39 @@ __global__ __launch_bounds__(kBlock) void hv_pass(HamGeom g, DevTables<R> tb, Pa
         }
       }
     } else {
-      for (int e = 0; e < npp; e++) {
+      for (int e = 0; e < npp && ctab > 0; e++) {
+        const int4 pi = s_pi[e];
+        const int rj = D.wrad[pi.y];
+        const Cx<R> *ct = s_ct + s_toff[e];
+        bool live[4];
+        uint32_t off[4];
+#pragma unroll
+        for (int ty = 0; ty < 4; ty++) {
+          const Cx<R> cq = s_pc[4 * e + ty];
+          live[ty] = !(cq.re == R(0) && cq.im == R(0));  // uniform: a ladder pair absent from the pair
+          off[ty] = ((ty >> 1) ? (uint32_t)pi.z : (uint32_t)(-pi.z)) + ((ty & 1) ? (uint32_t)pi.w : (uint32_t)(-pi.w));
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; q++) {
+          const uint32_t r = (uint32_t)(t + kBlock * q);
+          if (r >= ws) continue;
+          const int di = (int)digit(q, pi.x), dj = (int)digit(q, pi.y);
+          const Cx<R> *c4 = ct + 4 * (di * rj + dj);
+#pragma unroll
+          for (int ty = 0; ty < 4; ty++) {
+            if (!live[ty]) continue;
+            // a digit leaving its range has a zero coefficient; the clamped
+            // partner keeps that read inside the window
+            const Cx<R> c = c4[ty];
+            const uint32_t pr = min(r + off[ty], ws - 1u);
+            const Cx<R> x = win[pr];
+            acc[q].re = fma(c.re, x.re, fma(-c.im, x.im, acc[q].re));
+            acc[q].im = fma(c.re, x.im, fma(c.im, x.re, acc[q].im));
+          }
+        }
+      }
+      // without a table (large radices): the ladder factors per row
+      for (int e = 0; e < npp && ctab == 0; e++) {
         const int4 pi = s_pi[e];
         const int ri = D.wrad[pi.x], rj = D.wrad[pi.y];
         Cx<R> cq[4];
@@ -1807,8 +1871,12 @@ static size_t pass_rec_len(const PassDesc &D) {
 
 template <typename R>
 static size_t pass_smem(const PassDesc &D) {
-  return sizeof(Cx<R>) * ((size_t)D.wsize + 4 * (size_t)D.npp + kMaxPassSingles * 64) +
-         sizeof(R) * (pass_rec_len<R>(D) + 64 * (size_t)D.na) + sizeof(int4) * (size_t)D.npp;
+  size_t b = sizeof(Cx<R>) * ((size_t)D.wsize + 4 * (size_t)D.npp + kMaxPassSingles * 64) +
+             sizeof(R) * (pass_rec_len<R>(D) + 64 * (size_t)D.na) + sizeof(int4) * (size_t)D.npp;
+  b += sizeof(int) * ((size_t)D.npp + 1);
+  b = (b + 15) & ~size_t(15);
+  if (!pass_pow2(D) && sizeof(R) == 8) b += sizeof(Cx<R>) * (size_t)D.ctab;
+  return b;
 }
 
 template <typename R, bool POW2, int RPT>

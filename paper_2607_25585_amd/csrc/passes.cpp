@@ -272,6 +272,11 @@ int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std:
     D.pp_off = (int)plan.pairs.size();
     for (int p : best.pairs[ps]) plan.pairs.push_back(make_int4(p, pos[pi[p]], pos[pj[p]], 0));
     D.npp = (int)plan.pairs.size() - D.pp_off;
+    // the pair-coefficient table of a general-radix pass, if it fits 48 KB of
+    // LDS at complex128 (else 0: the kernel evaluates the factors per row)
+    D.ctab = 0;
+    for (int p : best.pairs[ps]) D.ctab += 4 * hh.radix[pi[p]] * hh.radix[pj[p]];
+    if ((size_t)D.ctab * 16 > 48 * 1024) D.ctab = 0;
     plan.passes.push_back(D);
   }
   if (plan.pairs.empty()) plan.pairs.push_back(make_int4(0, 0, 0, 0));
