@@ -37,6 +37,7 @@ struct BItem {
   DevTables<R> tb;   // instance pair tables + this field's one-site tables
   DevTables<R> tbo;  // moment operator (one-site tables only)
   int n, npair, has_z, half;
+  int pow2r;              // every radix a power of two: digits are bit fields
   uint32_t dim;
   uint32_t unit0, nunit;  // work units [unit0, unit0 + nunit)
   int col0;               // first column of the item in the wave's scalar arrays
@@ -231,7 +232,13 @@ __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb,
     return;
   }
   uint64_t dlo = 0, dhi = 0;
-  {
+  if (it.pow2r) {  // digit k = bits log2(stride_k) .. of the row
+    for (int k = 0; k < n; k++) {
+      const uint64_t dk = (row >> __builtin_ctz(it.stride[k])) & (uint32_t)(it.radix[k] - 1);
+      if (k < 16) dlo |= dk << (4 * k);
+      else dhi |= dk << (4 * (k - 16));
+    }
+  } else {
     uint32_t rem = row;
     for (int k = 0; k < n; k++) {
       const uint32_t r = (uint32_t)it.radix[k], qq = rem / r;
@@ -940,6 +947,9 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
         bi.npair = h->host.npair;
         bi.has_z = h->host.has_z;
         bi.half = h->host.spin_half;
+        bi.pow2r = 1;
+        for (int k = 0; k < h->host.n; k++)
+          if (h->host.radix[k] & (h->host.radix[k] - 1)) bi.pow2r = 0;
         bi.dim = dim;
         bi.unit0 = u0;
         bi.nunit = nunit;

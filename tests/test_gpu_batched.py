@@ -122,3 +122,23 @@ def test_batched_large_instances_default_columns():
             assert np.max(np.abs(b64[k][key] - pl[key])) <= 1e-9 * np.max(np.abs(pl[key])) + 1e-12, (k, key)
         assert curve_err(b32[k]["C"][0], pl["C"][0]) < 1e-3, k
         assert curve_err(b32[k]["M"][0], pl["M"][0]) < 1e-3, k
+
+
+def test_batched_power_of_two_radices_match_oracle():
+    """Instances whose radices are all powers of two (s = 3/2: digits are bit
+    fields) next to one with radix 3, FP64 batched against the oracle."""
+    rng = np.random.default_rng(777)
+    systems = []
+    for n, two_s in ((5, 3), (4, 3), (5, 2)):
+        s = W.random_small_system(rng, n, max_two_s=3)
+        s.two_s[:] = two_s
+        systems.append(s)
+    fields = [W.unit_vectors(rng, 2) * 0.7 for _ in systems]
+    T = W.t_grid(25)
+    hams = [F().Hamiltonian(s) for s in systems]
+    got = F().run_batched(hams, 4, 30, T, fields, seed=23, precision=0, columns=2)
+    for k, s in enumerate(systems):
+        ref = of.ftlm(s, 4, 30, T, seed=23, fields=fields[k], instance=k)
+        for f in range(len(fields[k])):
+            for key in ("lnZ", "E", "C", "M"):
+                assert curve_err(got[k][key][f], ref[f][key]) < 1e-8, (k, f, key)
