@@ -104,9 +104,11 @@ int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, con
  * tile walked over L2 windows (spin 1/2, N >= 12; 256 or 512 threads per tile,
  * given in the columns-per-lane field as 1 or 2 row groups), each at 512, 1024,
  * 2048 and 4096 blocks (variants 4, 5: at most 2048) --
- * with HIP events on the stream (blocking), and stores the fastest in the handle
- * for later ftlm_apply / ftlm_run launches of the same shape.  Outputs (may be
- * NULL): the chosen variant, grid size, columns per lane and its mean time. */
+ * with HIP events on the stream (blocking): three launches each, then the four
+ * fastest again with ten launches each.  Stores the fastest of that second
+ * round in the handle for later ftlm_apply / ftlm_run launches of the same
+ * shape.  Outputs (may be NULL): the chosen variant, grid size, columns per
+ * lane and its mean time over the ten launches. */
 int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, const void *v,
                               void *w, void *stream, int32_t *variant, int32_t *grid_cap,
                               int32_t *kc, float *best_ms);

@@ -136,6 +136,24 @@ static TableOffsets<R> pack_tables(const HostHam &hh, const std::vector<int> &pe
   return o;
 }
 
+// The spin-1/2 pair coefficients of a window plan's pair list, in list order:
+// entry e holds the four coefficients of device pair plist[e].x (the same
+// values as the pc_half table).
+template <typename R>
+static std::vector<Cx<R>> plist_coefs(const HostHam &hh, const std::vector<int> &perm, const std::vector<int4> &plist) {
+  std::vector<Cx<R>> c(4 * std::max<size_t>(plist.size(), 1), Cx<R>{0, 0});
+  for (size_t e = 0; e < plist.size(); e++) {
+    const int q = plist[e].x;
+    if (q < 0 || q >= (int)perm.size()) continue;
+    const int p = perm[q];
+    for (int a = 0; a < 4; a++) {
+      const Cx<double> v = hh.pc[4 * p + 3 - a];  // row bits (b_i, b_j) -> ladder pair, as in pc_half
+      c[4 * e + a] = Cx<R>{(R)v.re, (R)v.im};
+    }
+  }
+  return c;
+}
+
 template <typename R>
 static DevTables<R> resolve(const TableOffsets<R> &o, unsigned char *base) {
   DevTables<R> t;
@@ -257,6 +275,10 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   const size_t off_w32 = b.add(dh.win32.plist.data(), dh.win32.plist.size() * sizeof(int4));
   const size_t off_t64 = b.add(dh.tw64.plist.data(), dh.tw64.plist.size() * sizeof(int4));
   const size_t off_t32 = b.add(dh.tw32.plist.data(), dh.tw32.plist.size() * sizeof(int4));
+  const std::vector<Cx<double>> tc64 = plist_coefs<double>(hh, perm, dh.tw64.plist);
+  const std::vector<Cx<float>> tc32 = plist_coefs<float>(hh, perm, dh.tw32.plist);
+  const size_t off_c64 = b.add(tc64.data(), tc64.size() * sizeof(Cx<double>));
+  const size_t off_c32 = b.add(tc32.data(), tc32.size() * sizeof(Cx<float>));
   const size_t bytes = (b.bytes.size() + 255) & ~size_t(255);
   if (dh.block && dh.block_bytes != bytes) {
     (void)hipFree(dh.block);
@@ -283,6 +305,8 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   dh.win32.d_plist = reinterpret_cast<const int4 *>(base + off_w32);
   dh.tw64.d_plist = dh.tw64.plist.empty() ? nullptr : reinterpret_cast<const int4 *>(base + off_t64);
   dh.tw32.d_plist = dh.tw32.plist.empty() ? nullptr : reinterpret_cast<const int4 *>(base + off_t32);
+  dh.tw64.d_pcoef = dh.tw64.plist.empty() ? nullptr : base + off_c64;
+  dh.tw32.d_pcoef = dh.tw32.plist.empty() ? nullptr : base + off_c32;
   HamGeom &g = dh.geom;
   std::memset(&g, 0, sizeof(g));
   g.n = n;

@@ -177,6 +177,10 @@ struct WinPlan {
   std::vector<int4> plist;        // (pair index in device order, i, j, 0), pass by pass
   const int4 *d_plist = nullptr;  // device copy (inside the handle's table block)
   size_t window_rows = 0;
+  // tile plans: the spin-1/2 pair coefficients (four per pair, indexed by the
+  // row bits b_i << 1 | b_j) in plist order, in the plan's precision, so that
+  // an entry's coefficients are addressed by its position alone
+  const void *d_pcoef = nullptr;
 };
 
 struct DevHam {

@@ -1402,7 +1402,7 @@ __device__ __forceinline__ void outer_pairs(Cx<R> (&acc)[kRowsPerThread / G], co
 #pragma unroll
   for (int b = 0; b < NB; b++) {
     const int4 e = pe[b];
-    c[b] = pc[4 * e.x + ((((base >> e.y) & 1) << 1) | ((base >> e.z) & 1))];
+    c[b] = pc[4 * b + ((((base >> e.y) & 1) << 1) | ((base >> e.z) & 1))];
     const Cx<R> *vb = v + (size_t)(base ^ (1u << e.y) ^ (1u << e.z)) * K;
 #pragma unroll
     for (int q = 0; q < Q; q++) x[b][q] = vb[(size_t)q * kBlock * K + tk];
@@ -1413,14 +1413,16 @@ __device__ __forceinline__ void outer_pairs(Cx<R> (&acc)[kRowsPerThread / G], co
     for (int q = 0; q < Q; q++) fma_cx(acc[q], c[b], x[b][q]);
 }
 
-// plist and pch (the spin-1/2 pair coefficients, tb.pc_half) are read at
-// wave-uniform addresses; as __restrict__ kernel arguments they are known not
-// to be written by the kernel's stores, so these reads go through the scalar
-// data cache instead of becoming vector loads with a full wait in every trip.
+// plist and pcl (the spin-1/2 pair coefficients in plist order: entry e's four
+// at pcl[4 e]) are read at wave-uniform addresses; as __restrict__ kernel
+// arguments they are known not to be written by the kernel's stores, so these
+// reads go through the scalar data cache instead of becoming vector loads with
+// a full wait in every trip.  Addressed by list position, an entry's
+// coefficients are fetched together with the entry instead of after it.
 template <typename R, int G>
 __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevTables<R> tb, WinPass W,
                                                              const int4 *__restrict__ plist,
-                                                             const Cx<R> *__restrict__ pch, HvParams P) {
+                                                             const Cx<R> *__restrict__ pcl, HvParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NT = kBlock * G;           // threads per block
   constexpr int S = kRowsPerThread;        // slots per tile (row bits 8..10)
@@ -1443,7 +1445,8 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
   const int c0 = blockIdx.y;
   const int K = P.K;
   const int4 *pl = plist + W.p0;
-  for (int i = t; i < 4 * n_in; i += NT) s_pc[i] = pch[4 * pl[i >> 2].x + (i & 3)];
+  const Cx<R> *__restrict__ pch = pcl + 4 * (size_t)W.p0;  // the pass's entries
+  for (int i = t; i < 4 * n_in; i += NT) s_pc[i] = pch[i];
   for (int i = t; i < 2 * n; i += NT) {
     s_hf[i] = tb.hflip[i];
     s_hd[i] = tb.hdiag[(i >> 1) * 16 + (i & 1)];
@@ -1460,6 +1463,7 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
   }
   const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v);
   const bool zf = W.smask != 0u;
+  const int nsm = __builtin_popcount(W.smask);
   double red[3][1] = {{0.0}, {0.0}, {0.0}};
   const size_t tk = (size_t)tq * K;  // thread offset; the tile bases below are uniform
   constexpr size_t QS = (size_t)kBlock;  // row step between a thread's rows
@@ -1472,20 +1476,34 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
 #pragma unroll
       for (int q = 0; q < Q; q++) own[q * kBlock + tq] = vb[q * QS * K + tk];
     }
-    // per-tile uniform parts: rows of slot s have bits 8..10 = s and bits >= 11 = base
+    // per-tile uniform parts: rows of slot s have bits 8..10 = s and bits >= 11 = base;
+    // the z-field part only for the sites whose single flips this pass applies
     if (zf)
-      for (int e = t; e < 2 * S * n; e += NT) {
-        const int k = e / (2 * S), sel = (e / S) & 1, sl = e % S;
+      for (int e = t; e < 2 * S * nsm; e += NT) {
+        const int r = e / (2 * S), sel = (e / S) & 1, sl = e % S;
+        uint32_t m = W.smask;
+        for (int u = 0; u < r; u++) m &= m - 1u;
+        const int k = __builtin_ctz(m);
         const uint32_t rb = base | ((uint32_t)sl << kLowBits);
         R fr = 0, fi = 0;
-        for (int j = kLowBits; j < n; j++) {
-          if (j == k) continue;
-          const R mj = ((rb >> j) & 1) ? R(0.5) : R(-0.5);
-          const Cx<R> c = tb.cz_half[(k * n + j) * 2 + sel];
-          fr = fma(c.re, mj, fr);
-          fi = fma(c.im, mj, fi);
+        // four sites per trip, their loads issued together (a weight of zero
+        // stands for j = k and for j >= n)
+        for (int j0 = kLowBits; j0 < n; j0 += 4) {
+          Cx<R> c[4];
+          R mj[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int j = j0 + u < n ? j0 + u : n - 1;
+            c[u] = tb.cz_half[(k * n + j) * 2 + sel];
+            mj[u] = (j0 + u < n && j != k) ? (((rb >> j) & 1) ? R(0.5) : R(-0.5)) : R(0);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            fr = fma(c[u].re, mj[u], fr);
+            fi = fma(c[u].im, mj[u], fi);
+          }
         }
-        s_fmh[e] = Cx<R>{fr, fi};
+        s_fmh[(k * 2 + sel) * S + sl] = Cx<R>{fr, fi};
       }
     if (W.diag) {
       if (t < 24 * S) {
@@ -1494,14 +1512,34 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
           const uint32_t rb = base | ((uint32_t)sl << kLowBits);
           const R mk = ((rb >> k) & 1) ? R(0.5) : R(-0.5);
           R acc = s_hd[2 * k + ((rb >> k) & 1)];
-          for (int j = k + 1; j < n; j++) acc = fma(tb.zz[k * n + j] * mk, ((rb >> j) & 1) ? R(0.5) : R(-0.5), acc);
+          for (int j0 = k + 1; j0 < n; j0 += 4) {  // loads four at a time; weight 0 past n
+            R z[4], mj[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              const int j = j0 + u < n ? j0 + u : n - 1;
+              z[u] = tb.zz[k * n + j];
+              mj[u] = j0 + u < n ? (((rb >> j) & 1) ? R(0.5) : R(-0.5)) : R(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) acc = fma(z[u] * mk, mj[u], acc);
+          }
           s_term[(k - kLowBits) * S + sl] = acc;
         }
       } else if (t < 24 * S + 8 * S) {
         const int i = (t - 24 * S) / S, sl = (t - 24 * S) % S;
         const uint32_t rb = base | ((uint32_t)sl << kLowBits);
         R ph = 0;
-        for (int j = kLowBits; j < n; j++) ph = fma(tb.zz[i * n + j], ((rb >> j) & 1) ? R(0.5) : R(-0.5), ph);
+        for (int j0 = kLowBits; j0 < n; j0 += 4) {
+          R z[4], mj[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int j = j0 + u < n ? j0 + u : n - 1;
+            z[u] = tb.zz[i * n + j];
+            mj[u] = j0 + u < n ? (((rb >> j) & 1) ? R(0.5) : R(-0.5)) : R(0);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) ph = fma(z[u], mj[u], ph);
+        }
         s_phi[i * S + sl] = ph;
       }
     }
@@ -1640,12 +1678,12 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
         const int4 pe = pl[e];
         if (pe.z != a) break;
         const int i = pe.y;
-        const Cx<R> clo = pch[4 * pe.x + ba], chi = pch[4 * pe.x + 2 + ba];
+        const Cx<R> clo = pch[4 * e + ba], chi = pch[4 * e + 2 + ba];
         if (i < kLowBits && e + 1 < e_out) {
           // two lane-bit mixed pairs of site a together when the next one is one
           const int4 pe2 = pl[e + 1];
           if (pe2.z == a && pe2.y < kLowBits) {
-            const Cx<R> clo2 = pch[4 * pe2.x + ba], chi2 = pch[4 * pe2.x + 2 + ba];
+            const Cx<R> clo2 = pch[4 * (e + 1) + ba], chi2 = pch[4 * (e + 1) + 2 + ba];
             const Cx<R> c = ((l >> i) & 1) ? chi : clo, c2 = ((l >> pe2.y) & 1) ? chi2 : clo2;
             const int tf = tq ^ (1 << i), tf2 = tq ^ (1 << pe2.y);
             Cx<R> x[Q], x2[Q];
@@ -1684,8 +1722,8 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
       const Cx<R> *vc = v + c0;
       int e2 = e_out;
 #pragma unroll 1
-      for (; e2 + NB <= np; e2 += NB) outer_pairs<NB, G>(acc, pl + e2, base, pch, vc, (size_t)K, tk);
-      if (e2 < np) outer_pairs<1, G>(acc, pl + e2, base, pch, vc, (size_t)K, tk);
+      for (; e2 + NB <= np; e2 += NB) outer_pairs<NB, G>(acc, pl + e2, base, pch + 4 * e2, vc, (size_t)K, tk);
+      if (e2 < np) outer_pairs<1, G>(acc, pl + e2, base, pch + 4 * e2, vc, (size_t)K, tk);
     }
 #pragma unroll
     for (int q = 0; q < Q; q++) {
@@ -2129,21 +2167,22 @@ static int tile_win_groups(int want, bool f32) {
 
 template <typename R, int G>
 static void launch_tile_win_g(dim3 grid, size_t sm, hipStream_t s, const HamGeom &g, const DevTables<R> &tb,
-                              const WinPass &W, const int4 *plist, const HvParams &P) {
+                              const WinPass &W, const int4 *plist, const Cx<R> *pcl, const HvParams &P) {
   static size_t granted = 0;  // per instantiation
   if (sm > granted) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_tile_win<R, G>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     granted = sm;
   }
-  hipLaunchKernelGGL((hv_tile_win<R, G>), grid, dim3(kBlock * G), sm, s, g, tb, W, plist, tb.pc_half, P);
+  hipLaunchKernelGGL((hv_tile_win<R, G>), grid, dim3(kBlock * G), sm, s, g, tb, W, plist, pcl, P);
 }
 
 template <typename R>
 static int launch_tile_win(const DevHam &dh, const DevTables<R> &tb, const WinPlan &plan, const HvParams &P,
                            int cap, int groups, unsigned *last_gx, hipStream_t s) {
   const HamGeom &g = dh.geom;
-  if (!plan.d_plist || plan.passes.empty() || !g.spin_half || g.n <= kTileBits) return FTLM_EINVAL;
+  if (!plan.d_plist || !plan.d_pcoef || plan.passes.empty() || !g.spin_half || g.n <= kTileBits) return FTLM_EINVAL;
+  const Cx<R> *pcl = reinterpret_cast<const Cx<R> *>(plan.d_pcoef);
   const int G = tile_win_groups(groups, sizeof(R) == 4);
   for (const WinPass &W : plan.passes) {
     const uint64_t items = (uint64_t)W.nwin * W.nin;
@@ -2154,8 +2193,8 @@ static int launch_tile_win(const DevHam &dh, const DevTables<R> &tb, const WinPl
     const size_t sm = hv_tile_win_smem<R>(g, W);
     if (sm > 160 * 1024) return FTLM_ERANGE;
     const dim3 grid(gx, P.K);
-    if (G == 2) launch_tile_win_g<R, 2>(grid, sm, s, g, tb, W, plan.d_plist, Pp);
-    else launch_tile_win_g<R, 1>(grid, sm, s, g, tb, W, plan.d_plist, Pp);
+    if (G == 2) launch_tile_win_g<R, 2>(grid, sm, s, g, tb, W, plan.d_plist, pcl, Pp);
+    else launch_tile_win_g<R, 1>(grid, sm, s, g, tb, W, plan.d_plist, pcl, Pp);
     *last_gx = gx;
   }
   return FTLM_OK;

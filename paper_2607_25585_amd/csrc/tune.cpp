@@ -1,11 +1,14 @@
 // Autotuner of the H*v launch: times every admissible (variant, grid size,
-// columns per lane) on the caller's buffers with HIP events and keeps the fastest
-// in the handle; subsequent ftlm_apply / ftlm_run launches with the same
+// columns per lane) on the caller's buffers with HIP events, times the four
+// fastest again with more launches, and keeps the fastest in the handle; subsequent ftlm_apply / ftlm_run launches with the same
 // precision and column count use it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
+#include <cmath>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ftlm_internal.hpp"
@@ -61,7 +64,9 @@ int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_
   float best = FLT_MAX;
   Cand bestc{0, 0, 0};
   int rc = FTLM_OK;
-  for (const Cand &c : cands) {
+  // mean time of reps launches after one warm-up launch; < 0 if the shape is
+  // inadmissible, NaN on a HIP error
+  auto time_cand = [&](const Cand &c, int reps) -> float {
     HvLaunch L{};
     L.precision = precision;
     L.K = n_cols;
@@ -70,16 +75,30 @@ int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_
     L.variant = c.variant;
     L.grid_cap = c.cap;
     L.kc = c.kc;
-    if (launch_hv(h->dev, L, s) != FTLM_OK) continue;  // warm-up; skips inadmissible shapes
-    if (hipEventRecord(e0, s) != hipSuccess) { rc = FTLM_EHIP; break; }
-    for (int r = 0; r < 3; r++) launch_hv(h->dev, L, s);
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = FTLM_EHIP; break; }
+    if (launch_hv(h->dev, L, s) != FTLM_OK) return -1.0f;
+    if (hipEventRecord(e0, s) != hipSuccess) return NAN;
+    for (int r = 0; r < reps; r++) launch_hv(h->dev, L, s);
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return NAN;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    ms /= 3.0f;
-    if (ms < best) {
+    return ms / (float)reps;
+  };
+  // a quick pass over every candidate, then the four fastest again with more
+  // launches each (neighbouring grid sizes often differ by a few per cent,
+  // within the noise of three launches)
+  std::vector<std::pair<float, int>> timed;
+  for (size_t i = 0; i < cands.size() && !rc; i++) {
+    const float ms = time_cand(cands[i], 3);
+    if (std::isnan(ms)) rc = FTLM_EHIP;
+    else if (ms >= 0) timed.push_back({ms, (int)i});
+  }
+  std::sort(timed.begin(), timed.end());
+  for (size_t r = 0; r < timed.size() && r < 4 && !rc; r++) {
+    const float ms = time_cand(cands[timed[r].second], 10);
+    if (std::isnan(ms)) rc = FTLM_EHIP;
+    else if (ms >= 0 && ms < best) {
       best = ms;
-      bestc = c;
+      bestc = cands[timed[r].second];
     }
   }
   (void)hipEventDestroy(e0);
