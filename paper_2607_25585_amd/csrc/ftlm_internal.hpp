@@ -174,7 +174,9 @@ struct WinPass {
 
 struct WinPlan {
   std::vector<WinPass> passes;
-  std::vector<int4> plist;        // (pair index in device order, i, j, 0), pass by pass
+  std::vector<int4> plist;        // (pair index in device order, i, j, w), pass by pass; w = 0, or
+                                  // for a pair with one site outside the low bits the end of
+                                  // its run of pairs with that site (from the pass's first entry)
   const int4 *d_plist = nullptr;  // device copy (inside the handle's table block)
   size_t window_rows = 0;
   // tile plans: the spin-1/2 pair coefficients (four per pair, indexed by the

@@ -1389,6 +1389,22 @@ __device__ __forceinline__ void slot_flip_any(int sb, Cx<R> (&acc)[kRowsPerThrea
   else slot_flip<2, G>(acc, src, gg, tq, c0, c1);
 }
 
+// One mixed pair (i < 11, outer site a) read from the staged partner tile:
+// acc[q] += (bit i of the row ? chi : clo) * part[row with bit i flipped].
+template <int G, typename R>
+__device__ __forceinline__ void mixed_pair(Cx<R> (&acc)[kRowsPerThread / G], const Cx<R> *part, int gg, int tq,
+                                           int l, int i, Cx<R> clo, Cx<R> chi) {
+  constexpr int Q = kRowsPerThread / G;
+  if (i < kLowBits) {
+    const Cx<R> c = ((l >> i) & 1) ? chi : clo;
+    const int tf = tq ^ (1 << i);
+#pragma unroll
+    for (int q = 0; q < Q; q++) fma_cx(acc[q], c, part[q * kBlock + tf]);
+  } else {
+    slot_flip_any<G>(i - kLowBits, acc, part, gg, tq, clo, chi);
+  }
+}
+
 // NB pairs of two outer sites: every partner tile row is loaded before the
 // first FMA, so NB Q loads per lane are in flight at once.  The FMAs run in
 // pair order, as a one-at-a-time loop would.
@@ -1672,43 +1688,45 @@ __global__ __launch_bounds__(kBlock * G, 2 * G) void hv_tile_win(HamGeom g, DevT
           fma_cx(acc[q], Cx<R>{a1.re + a2.re + a3.re, a1.im + a2.im + a3.im}, part[q * kBlock + tq]);
         }
       }
+      // the mixed pairs (i < 11, a): a run of entries whose first one gives
+      // the run's end, taken two at a time, so that both entries and their
+      // coefficients are fetched with no wait in between
+      int eend = e;
+      if (e < e_out) {
+        const int4 p0 = pl[e];
+        if (p0.z == a) eend = p0.w;
+      }
+      eend = __builtin_amdgcn_readfirstlane(eend);
 #pragma unroll 1
-      for (; e < e_out; e++) {
+      for (; e + 1 < eend; e += 2) {
         e = __builtin_amdgcn_readfirstlane(e);
-        const int4 pe = pl[e];
-        if (pe.z != a) break;
-        const int i = pe.y;
+        const int i = pl[e].y, i2 = pl[e + 1].y;
         const Cx<R> clo = pch[4 * e + ba], chi = pch[4 * e + 2 + ba];
-        if (i < kLowBits && e + 1 < e_out) {
-          // two lane-bit mixed pairs of site a together when the next one is one
-          const int4 pe2 = pl[e + 1];
-          if (pe2.z == a && pe2.y < kLowBits) {
-            const Cx<R> clo2 = pch[4 * (e + 1) + ba], chi2 = pch[4 * (e + 1) + 2 + ba];
-            const Cx<R> c = ((l >> i) & 1) ? chi : clo, c2 = ((l >> pe2.y) & 1) ? chi2 : clo2;
-            const int tf = tq ^ (1 << i), tf2 = tq ^ (1 << pe2.y);
-            Cx<R> x[Q], x2[Q];
+        const Cx<R> clo2 = pch[4 * e + 4 + ba], chi2 = pch[4 * e + 6 + ba];
+        if (i < kLowBits && i2 < kLowBits) {
+          // two lane-bit pairs: the second one's LDS reads go out with the first's
+          const Cx<R> c = ((l >> i) & 1) ? chi : clo, c2 = ((l >> i2) & 1) ? chi2 : clo2;
+          const int tf = tq ^ (1 << i), tf2 = tq ^ (1 << i2);
+          Cx<R> x[Q], x2[Q];
 #pragma unroll
-            for (int q = 0; q < Q; q++) {
-              x[q] = part[q * kBlock + tf];
-              x2[q] = part[q * kBlock + tf2];
-            }
-#pragma unroll
-            for (int q = 0; q < Q; q++) {
-              fma_cx(acc[q], c, x[q]);
-              fma_cx(acc[q], c2, x2[q]);
-            }
-            e++;
-            continue;
+          for (int q = 0; q < Q; q++) {
+            x[q] = part[q * kBlock + tf];
+            x2[q] = part[q * kBlock + tf2];
           }
-        }
-        if (i < kLowBits) {
-          const Cx<R> c = ((l >> i) & 1) ? chi : clo;
-          const int tf = tq ^ (1 << i);
 #pragma unroll
-          for (int q = 0; q < Q; q++) fma_cx(acc[q], c, part[q * kBlock + tf]);
+          for (int q = 0; q < Q; q++) {
+            fma_cx(acc[q], c, x[q]);
+            fma_cx(acc[q], c2, x2[q]);
+          }
         } else {
-          slot_flip_any<G>(i - kLowBits, acc, part, gg, tq, clo, chi);
+          mixed_pair<G>(acc, part, gg, tq, l, i, clo, chi);
+          mixed_pair<G>(acc, part, gg, tq, l, i2, clo2, chi2);
         }
+      }
+      if (e < eend) {
+        e = __builtin_amdgcn_readfirstlane(e);
+        mixed_pair<G>(acc, part, gg, tq, l, pl[e].y, pch[4 * e + ba], pch[4 * e + 2 + ba]);
+        e++;
       }
     }
     // the earlier passes' partial sums of these rows, loaded now so that they

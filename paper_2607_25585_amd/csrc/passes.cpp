@@ -393,6 +393,16 @@ int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::ve
           W.xmask |= 1u << pj[p];
         }
       }
+      // entries with one site outside the low bits come in runs of the same
+      // outer site: .w = the end of the entry's run, counted from the pass's
+      // first entry, so that a kernel knows a run's length from its first entry
+      const int q0 = W.p0 + W.np_ll, q1 = q0 + W.np_lh;
+      for (int q = q0; q < q1;) {
+        int r = q;
+        while (r < q1 && plan.plist[r].z == plan.plist[q].z) r++;
+        for (int u = q; u < r; u++) plan.plist[u].w = r - W.p0;
+        q = r;
+      }
     }
     W.np = (int)plan.plist.size() - W.p0;
     for (int k = 0; k < n; k++)
