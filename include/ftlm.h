@@ -122,7 +122,9 @@ int ftlm_hamiltonian_set_tuning(ftlm_hamiltonian *h, int32_t precision, int32_t 
  * Philox4x32-10 (Salmon et al., SC'11) with key (seed low 32, seed high 32) and
  * counter (nu, r, field, instance); two 53-bit uniforms u1 in (0,1], u2 in [0,1)
  * give x + i y = sqrt(-2 ln u1) (cos 2 pi u2 + i sin 2 pi u2) (Box-Muller).
- * out: device complex128 [dim][n_cols].  Not normalised. */
+ * out: device complex128 [dim][n_cols].  Not normalised.  The first call on a
+ * device (per host thread) allocates a private 1 MB buffer for the kernel's norm
+ * partials, kept until the process ends. */
 int ftlm_gaussian_vectors(uint64_t seed, uint32_t instance, uint32_t field, uint32_t r0,
                           int32_t n_cols, uint64_t dim, void *out, void *stream);
 

@@ -454,16 +454,18 @@ int ftlm_gaussian_vectors(uint64_t seed, uint32_t instance, uint32_t field, uint
   if (!out) { set_error("out is NULL"); return FTLM_EINVAL; }
   if (n_cols < 1 || n_cols > 64) { set_error("n_cols must be in [1, 64]"); return FTLM_ERANGE; }
   if (dim < 1 || dim >= (1ull << 32)) { set_error("dim out of range"); return FTLM_ERANGE; }
-  // scratch for the norm partials is not needed here: use a small private buffer
-  static thread_local double *scratch = nullptr;
-  static thread_local int scratch_dev = -1;
+  // the start kernel also writes norm partials, which are not returned here:
+  // a private buffer per device (and host thread), kept until the process ends
+  constexpr int kMaxDev = 64;
+  static thread_local double *scratch_by_dev[kMaxDev] = {};
   int dev = 0;
   HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDev) { set_error("device index out of range"); return FTLM_ERANGE; }
   const size_t need = sizeof(double) * (2048 * 64 + 64) + sizeof(unsigned) * kCounterWords;
-  if (!scratch || scratch_dev != dev) {
+  double *&scratch = scratch_by_dev[dev];
+  if (!scratch) {
     HIP_OK(hipMalloc(&scratch, need));
     HIP_OK(hipMemset(scratch, 0, need));
-    scratch_dev = dev;
   }
   unsigned *counter = reinterpret_cast<unsigned *>(scratch + 2048 * 64 + 64);
   int rc = launch_gaussian(seed, instance, field, r0, n_cols, (uint32_t)dim, FTLM_C128, out,

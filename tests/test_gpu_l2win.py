@@ -141,6 +141,28 @@ def test_tile_window_full_size_sampled_rows(groups, monkeypatch):
     _sampled(sysm, F().FTLM_C64, 2e-5)
 
 
+def test_tile_window_lanczos_full_size_matches_oracle(monkeypatch):
+    """cfg2 at its full size (2^24 rows), in the launch the curve benchmark
+    times (tile-window kernel, 512-thread tiles, 2048 blocks, 2 MB windows):
+    the Lanczos coefficients of the first two steps, produced by the fused
+    epilogue of the last pass and the update kernel, against the oracle's
+    recursion from the same seeded start vector (oracle H*v on every row)."""
+    monkeypatch.setenv("FTLM_HV_VARIANT", "5")
+    monkeypatch.setenv("FTLM_TILE_GROUPS", "2")
+    monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "2048")
+    sysm, _ = W.cfg2()
+    print("case tile-window Lanczos at full size: cfg2, seed 11, 2 steps", flush=True)
+    ham = F().Hamiltonian(sysm)
+    got = F().run(ham, 1, 2, np.array([1.0, 10.0]), seed=11, columns=1, return_tridiagonals=True)
+    rv = of.gaussian_vector(11, 0, 0, 0, ham.dim)
+    a, b, _, k = of.lanczos(of.Ham(sysm), of.Moment(sysm, of.field_direction(sysm.B)), rv, 2)
+    assert k == 2 and int(got["n_lanczos_used"][0, 0]) == 2
+    # absolute error on the spectral scale (the first alpha is close to zero)
+    scale = float(np.max(np.abs(b)))
+    assert np.max(np.abs(got["alpha"][0, 0, :2] - a)) < 1e-10 * scale
+    assert np.max(np.abs(got["beta"][0, 0, :2] - b)) < 1e-10 * scale
+
+
 @pytest.mark.parametrize("K", [2, 4, 8])
 def test_l2win_columns_general_radix(K):
     """Variant 4 with K interleaved columns (general radix: K/kc column blocks of
