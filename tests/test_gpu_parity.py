@@ -211,6 +211,28 @@ def test_run_small_matches_oracle():
     assert np.array_equal(got["n_lanczos_used"][0], ref["n_lanczos_used"])
 
 
+@pytest.mark.parametrize("columns", [1, 3])
+def test_run_tridiagonals_match_oracle(columns):
+    """alpha_j and beta_j of the first 10 Lanczos steps of every random vector
+    against the oracle's recursion on the same seeded vectors (later steps
+    drift apart by rounding once the Krylov basis loses orthogonality; the
+    curves built from all steps are compared in the other run tests)."""
+    rng = np.random.default_rng(41)
+    sysm = W.random_small_system(rng, 5, max_two_s=3)
+    T = W.t_grid(20)
+    dim = W.dimension(sysm.two_s)
+    print("case tridiagonals dim", dim, "columns", columns, flush=True)
+    assert dim >= 64
+    ham, got = _run_pair(sysm, 3, 30, T, 17, columns=columns, return_tridiagonals=True)
+    ref = of.ftlm(sysm, 3, 30, T, seed=17, return_columns=True)[0]
+    for r in range(3):
+        a, b = ref["columns"][r]["alpha"], ref["columns"][r]["beta"]
+        assert len(a) >= 10 and int(got["n_lanczos_used"][0, r]) == len(a)
+        scale = max(np.max(np.abs(a)), np.max(np.abs(b)))
+        assert np.max(np.abs(got["alpha"][0, r, :10] - a[:10])) < 1e-10 * scale, r
+        assert np.max(np.abs(got["beta"][0, r, :10] - b[:10])) < 1e-10 * scale, r
+
+
 def test_run_cfg1_matches_oracle():
     """The exact-check workload (N=8, s=1 ring, dim 6561, R=20, N_L=100)."""
     sysm, spec = W.cfg1()
