@@ -4,7 +4,7 @@ INFRASTRUCTURE ONLY.
 
 Plain CPU FP64 steps:
 
-1. spectral bounds: N_B Lanczos steps (the driver's Paige-order recursion,
+1. spectral bounds: N_B Lanczos steps (the oracle's Paige-order recursion,
    ``ftlm.lanczos``) from the first random vector; [lo, hi] = [min, max] of the
    Ritz values widened by 2 % of their spread (reading: the margin);
    a = (hi - lo)/2, b = (hi + lo)/2, H~ = (H - b)/a;

@@ -2,7 +2,7 @@
 // Sec. 2.2, Eqs. (E-2-G), (E-2-H).
 //
 // For each random vector r (the R vectors are R/2 Gaussian vectors and their
-// time reverses) the driver runs N_L Lanczos steps keeping every Krylov vector
+// time reverses) the host code runs N_L Lanczos steps keeping every Krylov vector
 // (slot j of the workspace holds the unnormalised X_j with scale sx_j), applies
 // O = -sum_i g_i s_i.B_hat to every slot, forms O_K = V^H O V (Gram kernel),
 // and diagonalises the tridiagonal with the full eigenvector matrix Q.  The
