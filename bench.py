@@ -336,6 +336,8 @@ def main():
                     help="random vectors iterated together (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched-FP32 vs plain-FP64 comparison on the cfg3 subset")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning cache: reuse a stored choice instead of timing the candidates")
@@ -366,6 +368,12 @@ def main():
         out = {"metric": "curves/s of sFTLM, Chebyshev and powder-averaged FTLM", "n_gpus": 1,
                "data": "synthetic", "config": {"workload": "ring6 / cfg1 / mn9"}}
         out.update(extras_report())
+        print(json.dumps(out), flush=True)
+        return
+    if args.batched_only:
+        out = {"metric": "FTLM curves/s batched-FP32 vs plain FP64 at C(T) <=1e-3 rel", "n_gpus": 1,
+               "data": "synthetic", "config": {"workload": "cfg3 subset: 8 instances x 4 field directions"}}
+        out["batched_fp32_vs_plain_fp64"] = batched_vs_plain()
         print(json.dumps(out), flush=True)
         return
     if args.surrogate:
