@@ -44,9 +44,13 @@ struct BItem {
   uint32_t rng_inst, rng_field, rng_r0;
   Cx<R> *x[3];            // rotating Lanczos buffers [dim][K]
   Cx<R> *ov1;             // O v_1
+  R *diag;                // H's diagonal [dim]: written by the first Lanczos step, read by the rest
   int radix[kMaxSites];
   uint32_t stride[kMaxSites];
 };
+
+// the host packs the item array at the stride of BItem<double> for both precisions
+static_assert(sizeof(BItem<float>) == sizeof(BItem<double>), "BItem must not depend on R in size");
 
 struct BStep {
   int K, step, n_lanczos, mode;  // mode 0: O v_1 (plain, scaled); 1: Lanczos H*v
@@ -188,9 +192,11 @@ __device__ void stage_tables(const BItem<R> &it, bool moment, unsigned char *lds
 }
 
 // One row of H v (or O v) for KC columns; tb holds the operator's tables.
+// dmode: 0 computes the diagonal element, 1 computes and stores it in dcache[row],
+// 2 reads it from there (H does not change between the steps of a run).
 template <typename R, int KC>
 __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb, bool moment, uint32_t row,
-                                     const Cx<R> *__restrict__ v, BAcc<R, KC> &acc) {
+                                     const Cx<R> *__restrict__ v, BAcc<R, KC> &acc, R *dcache, int dmode) {
   const int n = it.n;
   const int npair = moment ? 0 : it.npair;
   const bool has_z = !moment && it.has_z;
@@ -198,10 +204,15 @@ __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb,
   for (int q = 0; q < KC; q++) acc.re[q] = acc.im[q] = R(0);
   if (it.half) {
     R diag = 0;
-    for (int k = 0; k < n; k++) diag += tb.hdiag[k * 16 + ((row >> k) & 1)];
-    for (int p = 0; p < npair; p++) {
-      const int2 ij = tb.pij[p];
-      diag = fma(tb.pzz[p], (((row >> ij.x) ^ (row >> ij.y)) & 1) ? R(-0.25) : R(0.25), diag);
+    if (dmode == 2) {
+      diag = dcache[row];
+    } else {
+      for (int k = 0; k < n; k++) diag += tb.hdiag[k * 16 + ((row >> k) & 1)];
+      for (int p = 0; p < npair; p++) {
+        const int2 ij = tb.pij[p];
+        diag = fma(tb.pzz[p], (((row >> ij.x) ^ (row >> ij.y)) & 1) ? R(-0.25) : R(0.25), diag);
+      }
+      if (dmode == 1) dcache[row] = diag;
     }
     {
       const Cx<R> *x = v + (size_t)row * KC;
@@ -252,10 +263,15 @@ __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb,
     return (int)(((k < 16) ? (dlo >> (4 * k)) : (dhi >> (4 * (k - 16)))) & 15u);
   };
   R diag = 0;
-  for (int k = 0; k < n; k++) diag += tb.hdiag[k * 16 + digit(k)];
-  for (int p = 0; p < npair; p++) {
-    const int2 ij = tb.pij[p];
-    diag = fma(tb.pzz[p], tb.mval[ij.x * 16 + digit(ij.x)] * tb.mval[ij.y * 16 + digit(ij.y)], diag);
+  if (dmode == 2) {
+    diag = dcache[row];
+  } else {
+    for (int k = 0; k < n; k++) diag += tb.hdiag[k * 16 + digit(k)];
+    for (int p = 0; p < npair; p++) {
+      const int2 ij = tb.pij[p];
+      diag = fma(tb.pzz[p], tb.mval[ij.x * 16 + digit(ij.x)] * tb.mval[ij.y * 16 + digit(ij.y)], diag);
+    }
+    if (dmode == 1) dcache[row] = diag;
   }
   {
     const Cx<R> *x = v + (size_t)row * KC;
@@ -399,6 +415,7 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       __syncthreads();
     }
     const bool moment = S.mode == 0;
+    const int dmode = (moment || !it.diag) ? 0 : (j == 0 ? 1 : 2);  // uniform
     const Cx<R> *v = moment ? it.x[0] : it.x[j % 3];
     Cx<R> *w = moment ? it.ov1 : it.x[(j + 1) % 3];
     const Cx<R> *xp = (!moment && j > 0) ? it.x[(j + 2) % 3] : nullptr;
@@ -415,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       for (int q = 0; q < KC; q++) red[a][q] = 0.0;
     for (uint32_t row = r0 + threadIdx.x; row < r1; row += kBlock) {
       BAcc<R, KC> acc;
-      brow<R, KC>(it, lt, moment, row, v, acc);
+      brow<R, KC>(it, lt, moment, row, v, acc, it.diag, dmode);
       const size_t o = (size_t)row * KC;
 #pragma unroll
       for (int q = 0; q < KC; q++) {
@@ -682,7 +699,8 @@ void make_plan_b(const ftlm_hamiltonian *const *hs, int n_inst, const ftlm_run_p
   pl.all_vec_bytes = 0;
   for (size_t ci = 0; ci < ncurve; ci++) {
     const uint64_t dim = hs[pl.curves[ci].inst]->host.dim;
-    const size_t per_item = 4 * (size_t)dim * pl.K * pl.es + 4 * 256;
+    // four vectors [dim][K] and the diagonal of H [dim], each 256-byte aligned
+    const size_t per_item = 4 * (size_t)dim * pl.K * pl.es + (size_t)dim * (pl.es / 2) + 5 * 256;
     pl.max_vec_bytes = std::max(pl.max_vec_bytes, per_item);
     pl.all_vec_bytes += per_item * (size_t)(pl.R / pl.K);
   }
@@ -889,7 +907,8 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
     size_t end = next, vec = 0, units = 0;
     while (end < items.size()) {
       const uint64_t dim = hs[pl.curves[items[end].curve].inst]->host.dim;
-      const size_t iv = 4 * (((size_t)dim * K * pl.es + 255) & ~size_t(255));
+      const size_t iv = 4 * (((size_t)dim * K * pl.es + 255) & ~size_t(255)) +
+                        (((size_t)dim * (pl.es / 2) + 255) & ~size_t(255));
       const size_t iu = (dim + kUnitRows - 1) / kUnitRows;
       const size_t meta = wave_meta_bytes(end + 1 - next, units + iu, K, NL);
       if (vec + iv + meta > avail && end > next) break;
@@ -926,6 +945,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       const uint32_t dim = (uint32_t)h->host.dim;
       const uint32_t nunit = (dim + kUnitRows - 1) / kUnitRows;
       const size_t vb = ((size_t)dim * K * pl.es + 255) & ~size_t(255);
+      const size_t vbd = ((size_t)dim * (pl.es / 2) + 255) & ~size_t(255);
       auto fill = [&](auto tag) {
         using R = decltype(tag);
         BItem<R> bi;
@@ -959,6 +979,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
         bi.rng_r0 = (uint32_t)(itm.group * K);
         for (int q = 0; q < 3; q++) bi.x[q] = reinterpret_cast<Cx<R> *>(vbase + voff + q * vb);
         bi.ov1 = reinterpret_cast<Cx<R> *>(vbase + voff + 3 * vb);
+        bi.diag = reinterpret_cast<R *>(vbase + voff + 4 * vb);
         for (int k = 0; k < h->host.n; k++) {
           bi.radix[k] = h->host.radix[k];
           bi.stride[k] = h->host.stride[k];
@@ -969,7 +990,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       else fill(double(0));
       for (uint32_t v2 = 0; v2 < nunit; v2++) umap[u0 + v2] = (int)i;
       u0 += nunit;
-      voff += 4 * vb;
+      voff += 4 * vb + vbd;
     }
     if (hipMemcpy(wbase + o_items, hitems.data(), hitems.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(wbase + o_umap, umap.data(), sizeof(int) * units, hipMemcpyHostToDevice) != hipSuccess) {
