@@ -71,17 +71,34 @@ struct BAcc {
   R re[KC], im[KC];
 };
 
+// a += c x for KC loaded columns
 template <typename R, int KC>
-__device__ __forceinline__ void bmac(BAcc<R, KC> &a, R cr, R ci, const Cx<R> *__restrict__ x) {
-  Cx<R> xv[KC];
-#pragma unroll
-  for (int q = 0; q < KC; q++) xv[q] = x[q];
+__device__ __forceinline__ void bfma(BAcc<R, KC> &a, R cr, R ci, const Cx<R> (&xv)[KC]) {
 #pragma unroll
   for (int q = 0; q < KC; q++) {
     a.re[q] = fma(cr, xv[q].re, fma(-ci, xv[q].im, a.re[q]));
     a.im[q] = fma(cr, xv[q].im, fma(ci, xv[q].re, a.im[q]));
   }
 }
+
+template <typename R, int KC>
+__device__ __forceinline__ void bmac(BAcc<R, KC> &a, R cr, R ci, const Cx<R> *__restrict__ x) {
+  Cx<R> xv[KC];
+#pragma unroll
+  for (int q = 0; q < KC; q++) xv[q] = x[q];
+  bfma<R, KC>(a, cr, ci, xv);
+}
+
+// a vector in global memory, for loads that the compiler would otherwise issue
+// as generic (flat) loads (the host pass of the compiler only parses device
+// code, and has no such address space)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename R>
+using GPtr = const __attribute__((address_space(1))) Cx<R> *;
+#else
+template <typename R>
+using GPtr = const Cx<R> *;
+#endif
 
 // LDS bytes of one item's staged tables (see stage_tables).
 __host__ __device__ inline size_t staged_bytes(int n, int npair, bool half, size_t rs) {
@@ -234,7 +251,28 @@ __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb,
       }
       bmac<R, KC>(acc, c.re, c.im, v + (size_t)(row ^ (1u << k)) * KC);
     }
-    for (int p = 0; p < npair; p++) {
+    // two pairs per trip: both partner rows are loaded before the first FMA
+    // (the accumulation order is that of one pair at a time); the vectors are
+    // read through global (not generic) pointers, so that waiting for an LDS
+    // table read does not also wait for the gathers in flight
+    const GPtr<R> gv = (GPtr<R>)v;  // generic -> global: the vectors are device memory
+    int p = 0;
+    for (; p + 1 < npair; p += 2) {
+      const int2 ij0 = tb.pij[p], ij1 = tb.pij[p + 1];
+      const GPtr<R> p0 = gv + (size_t)(row ^ ((1u << ij0.x) | (1u << ij0.y))) * KC;
+      const GPtr<R> p1 = gv + (size_t)(row ^ ((1u << ij1.x) | (1u << ij1.y))) * KC;
+      Cx<R> x0[KC], x1[KC];
+#pragma unroll
+      for (int q = 0; q < KC; q++) {
+        x0[q] = p0[q];
+        x1[q] = p1[q];
+      }
+      const Cx<R> c0 = tb.pc_half[4 * p + ((((row >> ij0.x) & 1) << 1) | ((row >> ij0.y) & 1))];
+      const Cx<R> c1 = tb.pc_half[4 * (p + 1) + ((((row >> ij1.x) & 1) << 1) | ((row >> ij1.y) & 1))];
+      bfma<R, KC>(acc, c0.re, c0.im, x0);
+      bfma<R, KC>(acc, c1.re, c1.im, x1);
+    }
+    if (p < npair) {
       const int2 ij = tb.pij[p];
       const int type = (((row >> ij.x) & 1) << 1) | ((row >> ij.y) & 1);
       const Cx<R> c = tb.pc_half[4 * p + type];
