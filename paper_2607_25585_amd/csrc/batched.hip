@@ -81,24 +81,30 @@ __device__ __forceinline__ void bfma(BAcc<R, KC> &a, R cr, R ci, const Cx<R> (&x
   }
 }
 
-template <typename R, int KC>
-__device__ __forceinline__ void bmac(BAcc<R, KC> &a, R cr, R ci, const Cx<R> *__restrict__ x) {
-  Cx<R> xv[KC];
-#pragma unroll
-  for (int q = 0; q < KC; q++) xv[q] = x[q];
-  bfma<R, KC>(a, cr, ci, xv);
-}
-
 // a vector in global memory, for loads that the compiler would otherwise issue
 // as generic (flat) loads (the host pass of the compiler only parses device
 // code, and has no such address space)
 #if defined(__HIP_DEVICE_COMPILE__)
 template <typename R>
 using GPtr = const __attribute__((address_space(1))) Cx<R> *;
+template <typename R>
+using GPtrW = __attribute__((address_space(1))) Cx<R> *;
 #else
 template <typename R>
 using GPtr = const Cx<R> *;
+template <typename R>
+using GPtrW = Cx<R> *;
 #endif
+
+// a += c x[0..KC), x a row of a Lanczos vector (device memory: read as global)
+template <typename R, int KC>
+__device__ __forceinline__ void bmac(BAcc<R, KC> &a, R cr, R ci, const Cx<R> *__restrict__ x) {
+  const GPtr<R> gx = (GPtr<R>)x;
+  Cx<R> xv[KC];
+#pragma unroll
+  for (int q = 0; q < KC; q++) xv[q] = gx[q];
+  bfma<R, KC>(a, cr, ci, xv);
+}
 
 // LDS bytes of one item's staged tables (see stage_tables).
 __host__ __device__ inline size_t staged_bytes(int n, int npair, bool half, size_t rs) {
@@ -472,19 +478,23 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       BAcc<R, KC> acc;
       brow<R, KC>(it, lt, moment, row, v, acc, it.diag, dmode);
       const size_t o = (size_t)row * KC;
+      // the item's vectors are device memory: global (not generic) accesses
+      const GPtr<R> gxp = (GPtr<R>)xp, gv = (GPtr<R>)v, gov = (GPtr<R>)it.ov1;
+      const GPtrW<R> gw = (GPtrW<R>)w;
 #pragma unroll
       for (int q = 0; q < KC; q++) {
         double wr = (double)acc.re[q] * sx[q], wi = (double)acc.im[q] * sx[q];
         if (xp) {
-          const Cx<R> a = xp[o + q];
+          const Cx<R> a = gxp[o + q];
           wr -= bp[q] * (double)a.re;
           wi -= bp[q] * (double)a.im;
         }
         const Cx<R> out{(R)wr, (R)wi};
-        w[o + q] = out;
+        gw[o + q].re = out.re;
+        gw[o + q].im = out.im;
         if (!moment) {
-          const Cx<R> xo = v[o + q];
-          const Cx<R> ov = it.ov1[o + q];
+          const Cx<R> xo = gv[o + q];
+          const Cx<R> ov = gov[o + q];
           red[0][q] += (double)xo.re * (double)out.re + (double)xo.im * (double)out.im;
           red[1][q] += (double)ov.re * (double)xo.re + (double)ov.im * (double)xo.im;
           red[2][q] += (double)ov.re * (double)xo.im - (double)ov.im * (double)xo.re;
