@@ -203,6 +203,46 @@ void sort_pairs(const HostHam &hh, std::vector<int> &perm, int &n_ll, int &n_lh,
   for (int a = n; a <= kMaxSites; a++) mx_off[a] = q;
 }
 
+namespace {
+// FNV-1a over the bytes an H*v launch takes by value.
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void *p, size_t n) {
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; i++) h = (h ^ b[i]) * 1099511628211ull;
+  }
+  template <typename T>
+  void pod(const T &x) { add(&x, sizeof(T)); }
+  template <typename T>
+  void vec(const std::vector<T> &v) {
+    pod(v.size());
+    if (!v.empty()) add(v.data(), v.size() * sizeof(T));
+  }
+};
+
+uint64_t launch_signature(const DevHam &dh) {
+  Fnv f;
+  f.pod(dh.geom);
+  f.pod(dh.t64);
+  f.pod(dh.t32);
+  for (const PassPlan *pl : {&dh.plan64, &dh.plan32}) {
+    f.vec(pl->passes);
+    f.pod(pl->d_pairs);
+    f.pod(pl->rec_block);
+    f.vec(pl->rec_off);
+    f.vec(pl->base_off);
+    f.vec(pl->lane_off);
+  }
+  for (const WinPlan *pl : {&dh.win64, &dh.win32, &dh.tw64, &dh.tw32}) {
+    f.vec(pl->passes);
+    f.pod(pl->d_plist);
+    f.pod(pl->d_pcoef);
+  }
+  f.pod(dh.block);
+  return f.h;
+}
+}  // namespace
+
 // Packs every table of hh for both precisions and copies it to the device.
 // Reuses dh.block when its size matches (so captured graphs stay valid).
 int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
@@ -325,7 +365,13 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
     g.stride[k] = hh.stride[k];
     g.s[k] = 0.5f * hh.two_s[k];
   }
-  return build_pass_records(dh, err);
+  const int rc = build_pass_records(dh, err);
+  const uint64_t sig = launch_signature(dh);
+  if (sig != dh.launch_sig) {
+    dh.launch_sig = sig;
+    dh.generation++;
+  }
+  return rc;
 }
 
 size_t window_bytes_setting() {

@@ -199,6 +199,12 @@ struct DevHam {
   size_t plan_wb = 0, plan_l2b = 0, plan_tb = 0, plan_tb32 = 0;
   void *block = nullptr;  // device allocation holding every table
   size_t block_bytes = 0;
+  // Launch layout: everything an H*v launch copies by value (geometry, table
+  // addresses, pass and window plans).  A captured graph replays these values,
+  // so a field change that alters any of them bumps the generation and the run
+  // drivers capture again.
+  uint64_t launch_sig = 0;
+  uint64_t generation = 0;
 };
 
 // pi/pj: pair sites in the device (sorted) order.

@@ -227,6 +227,7 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
   hipGraph_t graph = nullptr;
   hipStream_t cap = nullptr;
   int exec_K = 0;
+  uint64_t exec_gen = 0;  // launch-layout generation the graph was captured with
   // eigenpairs of a finished wave run on s2 (default priority) while the next
   // wave iterates on s; ev[0..1]: slot's inputs staged, ev[2..3]: slot's
   // eigenpairs done, ev[4]: join before the Boltzmann sums
@@ -289,6 +290,14 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
       L.scale = at<double>(ws, pl.sx);
       if (launch_hv(h->mom_dev, L, s)) return fail(FTLM_EHIP, "O v1 launch failed");
       if (use_graph && K == pl.K) {
+        if (exec && exec_gen != h->dev.generation) {
+          // the field change re-planned the H*v launches or moved their tables:
+          // the captured graph holds the old values
+          (void)hipGraphExecDestroy(exec);
+          (void)hipGraphDestroy(graph);
+          exec = nullptr;
+          graph = nullptr;
+        }
         if (!exec) {
           if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
             return fail(FTLM_EHIP, "stream create failed");
@@ -300,6 +309,7 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
           if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
             return fail(FTLM_EHIP, "graph instantiate failed");
           exec_K = K;
+          exec_gen = h->dev.generation;
         }
         if (hipGraphLaunch(exec, s) != hipSuccess) return fail(FTLM_EHIP, "graph launch failed");
       } else {

@@ -79,7 +79,9 @@ def test_batched_waves_give_identical_results():
     for k, h in enumerate(hams):
         for _f in range(len(fields[k])):
             for _g in range(4 // 2):
-                items.append(4 * (((h.dim * 2 * 16) + 255) // 256 * 256))
+                # four column-interleaved vectors of 2 columns (c128) plus the
+                # item's cached diagonal of H (one FP64 value per row)
+                items.append(4 * (((h.dim * 2 * 16) + 255) // 256 * 256) + (h.dim * 8 + 255) // 256 * 256)
     small = int(nb.value) - sum(items) + 2 * max(items)
     b = F().run_batched(hams, 4, 30, T, fields, seed=3, precision=0, columns=2, workspace_bytes=small)
     for k in range(len(hams)):
@@ -142,3 +144,26 @@ def test_batched_power_of_two_radices_match_oracle():
         for f in range(len(fields[k])):
             for key in ("lnZ", "E", "C", "M"):
                 assert curve_err(got[k][key][f], ref[f][key]) < 1e-8, (k, f, key)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-3)])
+def test_batched_largest_cfg3_instances_match_oracle(prec, tol):
+    """The two largest sizes of the batched workload (spin-1/2 dipolar rings of
+    21 and 22 sites, 2^21 and 2^22 rows: many 2048-row units per item, the
+    per-unit z-field table of the row bits from 8 up and the cached diagonal of
+    H at full width) in one batched run, one field direction each, against the
+    oracle with the same seeded vectors."""
+    systems, spec, fields = W.cfg3()
+    pick = [22, 15]  # N = 21 and N = 22
+    sysl = [systems[k] for k in pick]
+    assert [s.n_sites for s in sysl] == [21, 22]
+    fl = [fields[k][:1] for k in pick]
+    T = W.t_grid(24)
+    R, NL = 2, 8
+    hams = [F().Hamiltonian(s) for s in sysl]
+    print("case batched cfg3 N=21,22 prec", prec, flush=True)
+    got = F().run_batched(hams, R, NL, T, fl, seed=spec.seed, precision=prec, columns=2)
+    for k, s in enumerate(sysl):
+        ref = of.ftlm(s, R, NL, T, seed=spec.seed, fields=fl[k], instance=k)
+        for key in ("lnZ", "E", "C", "M"):
+            assert curve_err(got[k][key][0], ref[0][key]) < tol, (k, key)

@@ -288,6 +288,29 @@ def test_run_fields_ragged_waves_and_r_init():
         assert curve_err(got2["C"][f], ref2[f]["C"]) < 1e-8
 
 
+@pytest.mark.parametrize("columns", [1, 2])
+def test_run_field_scan_replans_captured_graph(columns):
+    """One run over fields that change which sites have single-site flips: an
+    isotropic spin-1/2 ring with B along z has none, with B along x every site
+    has them, so the H*v plan and its launch arguments change between fields.
+    Every field must match the oracle (the Lanczos graph is captured again when
+    the launch layout changes)."""
+    n = 12
+    sysm = W.System(two_s=np.ones(n, np.int32), J=W.ring_couplings(n, 1.0), d=None,
+                    e=np.tile([0.0, 0.0, 1.0], (n, 1)), g=np.full(n, 2.0),
+                    B=np.array([0.0, 0.0, 0.5]), pos=None, name="ring12")
+    T = W.t_grid(30)
+    fields = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.5], [0.5, 0.0, 0.0], [0.0, 0.0, 0.5],
+                       [0.0, 0.3, 0.4]])
+    print("case field scan ring12 columns", columns, flush=True)
+    ham = F().Hamiltonian(sysm)
+    got = F().run(ham, 2, 40, T, seed=21, fields=fields, columns=columns)
+    ref = of.ftlm(sysm, 2, 40, T, seed=21, fields=fields)
+    for f in range(len(fields)):
+        for key in ("lnZ", "E", "C", "M"):
+            assert curve_err(got[key][f], ref[f][key]) < 1e-8, (f, key)
+
+
 def test_breakdown_reported():
     """dim < N_L: the recursion stops in an invariant subspace."""
     sysm = W.random_small_system(np.random.default_rng(5), 2, max_two_s=1)

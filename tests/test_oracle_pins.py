@@ -422,6 +422,48 @@ def test_adam_first_step_closed_form():
     assert np.allclose(p[0], -0.01 * g[0] / (np.abs(g[0]) + 1e-8), rtol=1e-12)
 
 
+def test_adam_bias_correction_over_five_steps():
+    """Kingma and Ba's bias correction divides the moments by 1 - beta^t.  With
+    a constant gradient g, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so every
+    bias-corrected step is exactly -lr g/(|g| + eps).  Steps 2..5 separate the
+    exponent t from a factor t (1 - b^t and 1 - b t agree only at t = 1), and
+    the moments themselves are checked against their closed forms."""
+    from oracle import mlp
+    g = np.array([0.3, -2.0, 1e-3, 7.5])
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    p, m, v = [np.zeros(4)], [np.zeros(4)], [np.zeros(4)]
+    for t in range(1, 6):
+        p_old = p[0].copy()
+        p, m, v = mlp.adam_step(p, [g], m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        assert np.allclose(m[0], (1 - b1 ** t) * g, rtol=1e-13, atol=0)
+        assert np.allclose(v[0], (1 - b2 ** t) * g * g, rtol=1e-12, atol=0)
+        step = p[0] - p_old
+        assert np.allclose(step, -lr * g / (np.abs(g) + eps), rtol=1e-9, atol=0), t
+    assert np.allclose(p[0], -5 * lr * g / (np.abs(g) + eps), rtol=1e-9)
+
+
+@pytest.mark.parametrize("seed,max_two_s", [(71, 1), (72, 3), (73, 5), (74, 5)])
+def test_c_hv_rows_equal_full_product_rows(seed, max_two_s):
+    """The sampled-row product that the full-size parity tests use as reference
+    (``Ham.apply_rows``) equals the pinned full product (``Ham.apply``, itself
+    pinned elementwise to the dense Kronecker H) bit for bit, on random
+    mixed-spin systems with every term switched on, for the first and last
+    rows, duplicates and random rows."""
+    rng = np.random.default_rng(seed)
+    sysm = W.random_small_system(rng, 5 if max_two_s < 5 else 4, max_two_s=max_two_s)
+    ham = of.Ham(sysm)
+    v = rng.standard_normal(ham.dim) + 1j * rng.standard_normal(ham.dim)
+    full = ham.apply(v)
+    rows = np.concatenate([[0, ham.dim - 1, 0, ham.dim - 1, ham.dim // 2, ham.dim // 2],
+                           rng.integers(0, ham.dim, 40)]).astype(np.int64)
+    got = ham.apply_rows(v, rows)
+    assert got.shape == rows.shape
+    assert np.array_equal(got.view(np.float64), full[rows].view(np.float64))
+    # every row at once, in reverse order
+    allr = np.arange(ham.dim - 1, -1, -1, dtype=np.int64)
+    assert np.array_equal(ham.apply_rows(v, allr).view(np.float64), full[allr].view(np.float64))
+
+
 # ------------------------------------------------ next row: sFTLM, time reversal
 def test_oracle_time_reverse_maps_h_b_to_h_minus_b():
     """The oracle's Theta (used for the random-vector pairs) satisfies
