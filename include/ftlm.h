@@ -128,6 +128,19 @@ int ftlm_hamiltonian_set_tuning(ftlm_hamiltonian *h, int32_t precision, int32_t 
 int ftlm_gaussian_vectors(uint64_t seed, uint32_t instance, uint32_t field, uint32_t r0,
                           int32_t n_cols, uint64_t dim, void *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, loops that must not call hipMalloc): the same start vectors as
+ * ftlm_gaussian_vectors (same arguments, same kernels, bitwise the same out),
+ * with the kernel's norm partials kept in a file-scope device array of the
+ * library instead of a buffer it allocates.  The array holds the partials of
+ * at most 2048 blocks x 64 columns (1 MiB per GPU, held until the process
+ * ends); n_cols > 64 is FTLM_ERANGE.  Calls no hipMalloc, hipFree or
+ * allocating library routine.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU race on the partials (not on out).  The first
+ * call on a device looks up the array's address there (hipGetSymbolAddress). */
+int ftlm_gaussian_vectors_noalloc(uint64_t seed, uint32_t instance, uint32_t field, uint32_t r0,
+                                  int32_t n_cols, uint64_t dim, void *out, void *stream);
+
 /* Run parameters for ftlm_run / ftlm_run_batched. */
 typedef struct {
   int32_t R;            /* random vectors per field, >= 1 */

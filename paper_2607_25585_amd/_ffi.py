@@ -63,6 +63,7 @@ def lib():
         L.ftlm_gaussian_vectors.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                             ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64, vp,
                                             vp]
+        L.ftlm_gaussian_vectors_noalloc.argtypes = L.ftlm_gaussian_vectors.argtypes
         L.ftlm_run_sftlm_workspace_size.argtypes = [vp, ctypes.POINTER(FtlmRunParams),
                                                      ctypes.POINTER(ctypes.c_size_t)]
         L.ftlm_run_workspace_size.argtypes = [vp, ctypes.POINTER(FtlmRunParams),
