@@ -245,12 +245,17 @@ def ring6(B: float = 0.1) -> tuple[System, RunSpec]:
     ring radius 0.5 nm in the xy-plane; non-collinear easy axes tilted 30 deg from
     z towards the radial directions (phi_i = 2 pi i/6); g = 2.  sFTLM with
     time-reversed pairs (R counts vectors)."""
-    n = 6
+    return ring_sftlm(6, B)
+
+
+def ring_sftlm(n: int, B: float = 0.1) -> tuple[System, RunSpec]:
+    """The ring of Sec. 3.2 with n sites (n = 6 is the paper's; n = 5, dim
+    7776, is small enough for a dense exact spectrum), same readings."""
     ang = 2 * np.pi * np.arange(n) / n
     pos = 0.5 * np.stack([np.cos(ang), np.sin(ang), np.zeros(n)], axis=1)
     sysm = System(two_s=np.full(n, 5, np.int32), J=ring_couplings(n, 0.02), d=np.full(n, -20.0),
                   e=_tilted_axes(ang, math.radians(30.0)), g=np.full(n, 2.0),
-                  B=np.array([0.0, 0.0, float(B)]), pos=pos, name="ring6")
+                  B=np.array([0.0, 0.0, float(B)]), pos=pos, name="ring%d" % n)
     return sysm, RunSpec(R=20, n_lanczos=100, seed=6000, T=t_grid())
 
 

@@ -221,10 +221,12 @@ int ftlm_run_kpm_workspace_size(const ftlm_hamiltonian *h, const ftlm_run_params
 int ftlm_run_kpm(const ftlm_hamiltonian *h, const ftlm_run_params *p, int32_t n_moments, void *workspace,
                  size_t bytes, void *stream, ftlm_result *out, double *bounds);
 
-/* Batched form: many Hamiltonian instances (uneven dimensions) and their field
- * directions run together; every Lanczos step is one persistent launch over a
- * work queue of (curve, row tile) units for all curves of a wave, replayed as a
- * HIP graph.  per_inst[k] describes instance k (R, N_L, n_T, precision and
+/* Batched form (grouping random vectors, field directions and instances so
+ * that one launch applies H to many vectors: the paper's proposal against the
+ * random access of H*v, Secs. 3.1 and 4): many Hamiltonian instances (uneven
+ * dimensions) and their field directions run together; every Lanczos step is
+ * one persistent launch over a work queue of (curve, row tile) units for all
+ * curves of a wave, replayed as a HIP graph.  per_inst[k] describes instance k (R, N_L, n_T, precision and
  * columns must agree across instances).  columns = random vectors per work item,
  * one of 16, 8, 4, 2, 1 dividing R; 0 = automatic (4 when the largest instance
  * has >= 2^17 rows, else the largest dividing R).  out[k] receives instance k's
@@ -234,6 +236,20 @@ int ftlm_run_batched_workspace_size(const ftlm_hamiltonian *const *hs, int32_t n
 int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst,
                      const ftlm_run_params *per_inst, void *workspace, size_t bytes,
                      void *stream, ftlm_result *out);
+
+/* Launch choices of ftlm_run_batched on the calling host thread (the batched
+ * autotuner's knobs; applying H to groups of random vectors at once is the
+ * paper's remedy for the random access of H*v, Secs. 3.1 and 4): grid_cap =
+ * blocks of the per-step launch (64..65536; 0 = 1024), unit_bits = log2 of the
+ * rows of a work unit (11 or 12; 0 = 11), order = the order in which a wave's
+ * items take their work units (0 = curve order, 1 = largest instance first).
+ * Results are bitwise independent of grid_cap and order (every work unit's
+ * partial sums are formed alike and summed per item in unit order); unit_bits
+ * changes the summation tree of the dot products (rounding only).  If out[0].hv_ms is
+ * non-NULL, ftlm_run_batched stores there the summed duration of the Lanczos
+ * step launches (HIP events around each wave's step graph) and in
+ * out[0].hv_launches the number of steps timed. */
+int ftlm_batched_set_tuning(int32_t grid_cap, int32_t unit_bits, int32_t order);
 
 /* Krylov eigen-decomposition step on the device (the tridiagonal eigenproblem of
  * Sec. 2.2): for every column c, the symmetric tridiagonal with diagonal

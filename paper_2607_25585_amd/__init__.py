@@ -18,7 +18,7 @@ import numpy as np
 from . import _ffi
 from ._ffi import FTLM_C128, FTLM_C64, FtlmError, check
 
-__all__ = ["Hamiltonian", "gaussian_vectors", "run", "run_batched", "tridiag_eigen",
+__all__ = ["Hamiltonian", "gaussian_vectors", "run", "run_batched", "batched_set_tuning", "tridiag_eigen",
            "boltzmann", "FTLM_C128", "FTLM_C64", "FtlmError", "library_path"]
 
 
@@ -146,6 +146,12 @@ class Hamiltonian:
         b = _f64(B, (3,))
         check(_ffi.lib().ftlm_hamiltonian_set_field(self._h, _dptr(b)), "set_field")
         self._B = b
+
+    def set_tuning(self, precision: int, n_cols: int, variant: int, grid_cap: int = 0, kc: int = 0) -> None:
+        """Fixes the H*v launch for (precision, n_cols): variant 0 restores the
+        built-in choice (see ``ftlm_hamiltonian_set_tuning``)."""
+        check(_ffi.lib().ftlm_hamiltonian_set_tuning(self._h, int(precision), int(n_cols), int(variant),
+                                                     int(grid_cap), int(kc)), "ftlm_hamiltonian_set_tuning")
 
     def apply(self, v, out=None):
         """w = H v for a device tensor v of shape [dim] or [dim, K]
@@ -294,12 +300,21 @@ def run_kpm(ham: Hamiltonian, R: int, n_moments: int, T, seed: int = 0, fields=N
     return out
 
 
+def batched_set_tuning(grid_cap: int = 0, unit_bits: int = 0, order: int = 0) -> None:
+    """Launch choices of later run_batched calls on this thread
+    (``ftlm_batched_set_tuning``; zeros restore the defaults)."""
+    check(_ffi.lib().ftlm_batched_set_tuning(int(grid_cap), int(unit_bits), int(order)),
+          "ftlm_batched_set_tuning")
+
+
 def run_batched(hams, R: int, n_lanczos: int, T, fields_per_inst, seed: int = 0,
                 precision: int = FTLM_C64, workspace=None, columns: int = 0,
-                workspace_bytes: Optional[int] = None):
+                workspace_bytes: Optional[int] = None, time_steps: bool = False):
     """Batched FTLM over many instances and field directions (one persistent
     launch per Lanczos step).  fields_per_inst[k] is an [n_dirs, 3] array.
-    Returns a list of result dicts like :func:`run`."""
+    Returns a list of result dicts like :func:`run`; with time_steps the first
+    dict also holds "step_ms" (summed duration of the Lanczos step launches)
+    and "steps"."""
     torch = _torch()
     n = len(hams)
     ps = (_ffi.FtlmRunParams * n)()
@@ -323,9 +338,16 @@ def run_batched(hams, R: int, n_lanczos: int, T, fields_per_inst, seed: int = 0,
         o = {kk: np.zeros((nf, nT)) for kk in ("lnZ", "E", "C", "M")}
         o["n_lanczos_used"] = np.zeros((nf, R), np.int32)
         o["E_min"] = np.zeros(nf)
+        hv = None
+        nl = None
+        if time_steps and k == 0:
+            o["step_ms"] = np.zeros(1)
+            o["steps"] = np.zeros(1, np.int32)
+            hv = _dptr(o["step_ms"])
+            nl = o["steps"].ctypes.data_as(_ffi.c_int32_p)
         resarr[k] = _ffi.FtlmResult(_dptr(o["lnZ"]), _dptr(o["E"]), _dptr(o["C"]), _dptr(o["M"]),
                                     o["n_lanczos_used"].ctypes.data_as(_ffi.c_int32_p),
-                                    _dptr(o["E_min"]), None, None, None, None)
+                                    _dptr(o["E_min"]), None, None, hv, nl)
         outs.append(o)
     check(_ffi.lib().ftlm_run_batched(hs, n, ps, ctypes.c_void_p(ws.data_ptr()),
                                       ctypes.c_size_t(need), _stream(), resarr),

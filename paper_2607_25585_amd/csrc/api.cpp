@@ -238,6 +238,16 @@ uint64_t launch_signature(const DevHam &dh) {
     f.pod(pl->d_plist);
     f.pod(pl->d_pcoef);
   }
+  for (const StreamPlan *sp : {&dh.sp64, &dh.sp32}) {
+    f.pod(sp->ok);
+    f.pod(sp->pow2);
+    f.pod(sp->cplx);
+    f.pod(sp->geom);
+    f.pod(sp->d_pij);
+    f.pod(sp->d_pc);
+    f.pod(sp->d_pzz);
+    f.pod(sp->d_tdiag);
+  }
   f.pod(dh.block);
   return f.h;
 }
@@ -319,6 +329,41 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   const std::vector<Cx<float>> tc32 = plist_coefs<float>(hh, perm, dh.tw32.plist);
   const size_t off_c64 = b.add(tc64.data(), tc64.size() * sizeof(Cx<double>));
   const size_t off_c32 = b.add(tc32.data(), tc32.size() * sizeof(Cx<float>));
+  // single-pass tile plans (64 KB tiles); field dependent (single flips,
+  // complex coefficients, the tile diagonal)
+  plan_stream(hh, 65536 / sizeof(Cx<double>), dh.sp64);
+  plan_stream(hh, 65536 / sizeof(Cx<float>), dh.sp32);
+  size_t off_s[2][4] = {{0}};
+  {
+    StreamPlan *sps[2] = {&dh.sp64, &dh.sp32};
+    for (int q = 0; q < 2; q++) {
+      const StreamPlan &sp = *sps[q];
+      const size_t npq = std::max<size_t>(sp.order.size(), 1);
+      std::vector<int2> sij(npq, make_int2(0, 0));
+      std::vector<Cx<double>> sc(4 * npq, Cx<double>{0, 0});
+      std::vector<double> sz(npq, 0.0);
+      for (size_t e = 0; e < sp.order.size(); e++) {
+        const int p = sp.order[e];
+        sij[e] = make_int2(hh.pi[p], hh.pj[p]);
+        for (int a = 0; a < 4; a++) sc[4 * e + a] = hh.pc[4 * p + a];
+        sz[e] = hh.pzz[p];
+      }
+      const std::vector<double> td = sp.tdiag.empty() ? std::vector<double>(1, 0.0) : sp.tdiag;
+      off_s[q][0] = b.add(sij.data(), sij.size() * sizeof(int2));
+      if (q == 0) {
+        off_s[q][1] = b.add(sc.data(), sc.size() * sizeof(Cx<double>));
+        off_s[q][2] = b.add(sz.data(), sz.size() * sizeof(double));
+        off_s[q][3] = b.add(td.data(), td.size() * sizeof(double));
+      } else {
+        std::vector<Cx<float>> sc32(sc.size());
+        for (size_t e = 0; e < sc.size(); e++) sc32[e] = Cx<float>{(float)sc[e].re, (float)sc[e].im};
+        std::vector<float> sz32(sz.begin(), sz.end()), td32(td.begin(), td.end());
+        off_s[q][1] = b.add(sc32.data(), sc32.size() * sizeof(Cx<float>));
+        off_s[q][2] = b.add(sz32.data(), sz32.size() * sizeof(float));
+        off_s[q][3] = b.add(td32.data(), td32.size() * sizeof(float));
+      }
+    }
+  }
   const size_t bytes = (b.bytes.size() + 255) & ~size_t(255);
   if (dh.block && dh.block_bytes != bytes) {
     (void)hipFree(dh.block);
@@ -347,6 +392,15 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
   dh.tw32.d_plist = dh.tw32.plist.empty() ? nullptr : reinterpret_cast<const int4 *>(base + off_t32);
   dh.tw64.d_pcoef = dh.tw64.plist.empty() ? nullptr : base + off_c64;
   dh.tw32.d_pcoef = dh.tw32.plist.empty() ? nullptr : base + off_c32;
+  {
+    StreamPlan *sps[2] = {&dh.sp64, &dh.sp32};
+    for (int q = 0; q < 2; q++) {
+      sps[q]->d_pij = reinterpret_cast<const int2 *>(base + off_s[q][0]);
+      sps[q]->d_pc = base + off_s[q][1];
+      sps[q]->d_pzz = base + off_s[q][2];
+      sps[q]->d_tdiag = base + off_s[q][3];
+    }
+  }
   HamGeom &g = dh.geom;
   std::memset(&g, 0, sizeof(g));
   g.n = n;

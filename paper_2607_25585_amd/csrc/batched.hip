@@ -23,14 +23,24 @@
 
 namespace ftlm {
 
-// Rows per work unit (8 tiles of 256).  Units are laid out item by item and the
-// grid is kept small enough that the units in flight at any time cover about
-// two large items, so the partners an item's gathers touch stay in the caches.
-constexpr uint32_t kUnitRows = 2048;
-constexpr int kUnitBits = 11;  // log2(kUnitRows): a unit's rows share their bits >= 11
-// the z-field tables split a spin-1/2 row into bits 0..7 (two nibbles), 8..10
-// (the unit table's index) and >= 11 (the unit's)
-static_assert(kUnitRows == (1u << kUnitBits) && kUnitBits == 11, "z-field table split assumes 2048-row units");
+// Rows per work unit: 2^ubits with ubits = 11 (2048 rows, 8 tiles of 256) or
+// 12, a tuning choice.  Units are laid out item by item and the grid is kept
+// small enough that the units in flight at any time cover a few large items, so
+// the partners an item's gathers touch stay in the caches.  The spin-1/2 z-field
+// tables split a row into bits 0..7 (two nibbles), 8..ubits-1 (the unit table's
+// index) and >= ubits (the unit's).
+constexpr uint32_t kUnitRows = 2048;  // smallest unit: sizes the workspace's unit arrays
+constexpr int kMaxUnitSub = 16;       // unit-table entries per (site, ladder) at ubits = 12
+
+// Launch choices of the batched run (the batched autotuner sets them): grid
+// cap, unit size and the order in which a wave's items take their units
+// (0: curve order, 1: largest instance first).
+struct BatchTuning {
+  int grid_cap = 1024;
+  int ubits = 11;
+  int order = 0;
+};
+static thread_local BatchTuning g_btune;
 
 template <typename R>
 struct BItem {
@@ -63,6 +73,7 @@ struct BStep {
   double *part;                        // [n_units][3][K]
   uint32_t n_items;                    // items of the wave (blocks of the finishing launch)
   uint32_t lds;                        // dynamic LDS of the H*v launch (largest item's tables)
+  int ubits;                           // log2 of the rows per work unit (11 or 12)
   const int *unit_item;                // [n_units]
 };
 
@@ -112,8 +123,8 @@ __host__ __device__ inline size_t staged_bytes(int n, int npair, bool half, size
   auto a16 = [](size_t b) { return (b + 15) & ~size_t(15); };
   size_t b = a16((size_t)n * 16 * rs) + 2 * a16((size_t)n * n * cs) + a16((size_t)npair * 8) +
              a16((size_t)npair * rs) + a16((size_t)npair * 4 * cs);
-  // hflip; lane-bit z-field tables [2 nibbles][k][b][16]; unit table [k][b][8]
-  if (half) b += a16((size_t)n * 2 * cs) + a16((size_t)2 * n * 2 * 16 * cs) + a16((size_t)n * 2 * 8 * cs);
+  // hflip; lane-bit z-field tables [2 nibbles][k][b][16]; unit table [k][b][<= 16]
+  if (half) b += a16((size_t)n * 2 * cs) + a16((size_t)2 * n * 2 * 16 * cs) + a16((size_t)n * 2 * kMaxUnitSub * cs);
   else b += 3 * a16((size_t)n * 16 * rs) + a16((size_t)n * 64 * cs);
   return b;
 }
@@ -147,7 +158,7 @@ __device__ __forceinline__ DevTables<R> table_layout(const BItem<R> &it, bool mo
     // z-field F_k^b(row) = sum_{l != k} C^b_kl m_l(row) split by row bits:
     // cz_half [nibble j < 2][k][b][v]: the sites 4j..4j+3 (lane bits) for
     // nibble value v (staged per item); lowf [k][b][i]: the sites >= 8 for row
-    // bits 8..10 = i and the current unit's bits >= 11 (filled per unit)
+    // bits 8..ubits-1 = i and the current unit's bits >= ubits (filled per unit)
     d.cz_half = reinterpret_cast<const Cx<R> *>(lds + off);
     off += a16((size_t)2 * n * 2 * 16 * cs);
     d.lowf = reinterpret_cast<const Cx<R> *>(lds + off);
@@ -219,7 +230,8 @@ __device__ void stage_tables(const BItem<R> &it, bool moment, unsigned char *lds
 // 2 reads it from there (H does not change between the steps of a run).
 template <typename R, int KC>
 __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb, bool moment, uint32_t row,
-                                     const Cx<R> *__restrict__ v, BAcc<R, KC> &acc, R *dcache, int dmode) {
+                                     const Cx<R> *__restrict__ v, BAcc<R, KC> &acc, R *dcache, int dmode,
+                                     int usb) {
   const int n = it.n;
   const int npair = moment ? 0 : it.npair;
   const bool has_z = !moment && it.has_z;
@@ -251,7 +263,7 @@ __device__ __forceinline__ void brow(const BItem<R> &it, const DevTables<R> &tb,
       if (has_z) {  // three table reads: row bits 0..3, 4..7, and 8.. (unit table)
         const Cx<R> f0 = tb.cz_half[((size_t)k * 2 + b) * 16 + (row & 15u)];
         const Cx<R> f1 = tb.cz_half[((size_t)(n + k) * 2 + b) * 16 + ((row >> 4) & 15u)];
-        const Cx<R> f2 = tb.lowf[((size_t)k * 2 + b) * 8 + ((row >> 8) & 7u)];
+        const Cx<R> f2 = tb.lowf[(((size_t)k * 2 + b) << usb) + ((row >> 8) & ((1u << usb) - 1u))];
         c.re += f0.re + f1.re + f2.re;
         c.im += f0.im + f1.im + f2.im;
       }
@@ -384,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void bstart_kernel(const BItem<R> *__restri
   for (uint32_t u = blockIdx.x; u < S.n_units; u += gridDim.x) {
     const int ii = S.unit_item[u];
     const BItem<R> &it = items[ii];
-    const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
+    const uint32_t r0 = (u - it.unit0) << S.ubits, r1 = min(it.dim, r0 + (1u << S.ubits));
     double red[1][KC];
 #pragma unroll
     for (int q = 0; q < KC; q++) red[0][q] = 0.0;
@@ -438,13 +450,14 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       staged = ii;
     }
     const DevTables<R> lt = table_layout(it, S.mode == 0, smem);
-    const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
+    const uint32_t r0 = (u - it.unit0) << S.ubits, r1 = min(it.dim, r0 + (1u << S.ubits));
+    const int usb = S.ubits - 8;
     if (it.half && it.has_z && S.mode != 0) {
-      // z-field of the sites >= 8 for the unit's rows with bits 8..10 = i:
+      // z-field of the sites >= 8 for the unit's rows with bits 8..ubits-1 = i:
       // F_k^b(i) = sum_{l >= 8, l != k} C^b_kl m_l
       const int n = it.n;
-      for (int e = threadIdx.x; e < n * 16; e += kBlock) {
-        const int i = e & 7, b = (e >> 3) & 1, k = e >> 4;
+      for (int e = threadIdx.x; e < (n * 2) << usb; e += kBlock) {
+        const int i = e & ((1 << usb) - 1), b = (e >> usb) & 1, k = e >> (usb + 1);
         const uint32_t rb = r0 | ((uint32_t)i << 8);
         R fr = 0, fi = 0;
         for (int l = 8; l < n; l++) {
@@ -476,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       for (int q = 0; q < KC; q++) red[a][q] = 0.0;
     for (uint32_t row = r0 + threadIdx.x; row < r1; row += kBlock) {
       BAcc<R, KC> acc;
-      brow<R, KC>(it, lt, moment, row, v, acc, it.diag, dmode);
+      brow<R, KC>(it, lt, moment, row, v, acc, it.diag, dmode, usb);
       const size_t o = (size_t)row * KC;
       // the item's vectors are device memory: global (not generic) accesses
       const GPtr<R> gxp = (GPtr<R>)xp, gv = (GPtr<R>)v, gov = (GPtr<R>)it.ov1;
@@ -513,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void bupdate_kernel(const BItem<R> *__restr
   for (uint32_t u = blockIdx.x; u < S.n_units; u += gridDim.x) {
     const int ii = S.unit_item[u];
     const BItem<R> &it = items[ii];
-    const uint32_t r0 = (u - it.unit0) * kUnitRows, r1 = min(it.dim, r0 + kUnitRows);
+    const uint32_t r0 = (u - it.unit0) << S.ubits, r1 = min(it.dim, r0 + (1u << S.ubits));
     Cx<R> *w = it.x[(j + 1) % 3];
     const Cx<R> *x = it.x[j % 3];
     double coef[KC], red[1][KC];
@@ -948,7 +961,24 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
   for (size_t ci = 0; ci < ncurve; ci++)
     for (int g = 0; g < R / K; g++) items.push_back({ci, g});
   const size_t avail = bytes - pl.fixed;
-  const bool use_graph = std::getenv("FTLM_NO_GRAPH") == nullptr;
+  const bool timing = out[0].hv_ms != nullptr;
+  const bool use_graph = timing || std::getenv("FTLM_NO_GRAPH") == nullptr;
+  const BatchTuning bt = g_btune;
+  const uint32_t urows = 1u << bt.ubits;
+  hipEvent_t tev[2] = {nullptr, nullptr};
+  double step_ms = 0.0;
+  int step_launches = 0;
+  if (timing && (hipEventCreate(&tev[0]) != hipSuccess || hipEventCreate(&tev[1]) != hipSuccess)) {
+    set_error("hipEventCreate failed");
+    return FTLM_EHIP;
+  }
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      for (int i = 0; i < 2; i++)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_guard{tev};
   size_t next = 0;
   while (next < items.size()) {
     // greedy wave: as many items as fit with their metadata
@@ -957,7 +987,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       const uint64_t dim = hs[pl.curves[items[end].curve].inst]->host.dim;
       const size_t iv = 4 * (((size_t)dim * K * pl.es + 255) & ~size_t(255)) +
                         (((size_t)dim * (pl.es / 2) + 255) & ~size_t(255));
-      const size_t iu = (dim + kUnitRows - 1) / kUnitRows;
+      const size_t iu = (dim + urows - 1) / urows;
       const size_t meta = wave_meta_bytes(end + 1 - next, units + iu, K, NL);
       if (vec + iv + meta > avail && end > next) break;
       vec += iv;
@@ -981,17 +1011,35 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
     const size_t meta_end = (c.off + 255) & ~size_t(255);
     unsigned char *wbase = base + pl.fixed;
     unsigned char *vbase = wbase + meta_end;
-    // item descriptors
+    // item descriptors (curve order); their units are laid out in the tuned
+    // order: curve order, or largest instance first (the long items start
+    // first and the small ones fill the launch's tail)
     std::vector<unsigned char> hitems(sizeof(BItem<double>) * nit);
     std::vector<int> umap(units);
+    std::vector<uint32_t> unit0_of(nit, 0);
+    {
+      std::vector<size_t> uord(nit);
+      for (size_t i = 0; i < nit; i++) uord[i] = i;
+      if (bt.order == 1)
+        std::stable_sort(uord.begin(), uord.end(), [&](size_t a, size_t b) {
+          return hs[pl.curves[items[next + a].curve].inst]->host.dim > hs[pl.curves[items[next + b].curve].inst]->host.dim;
+        });
+      uint32_t uu = 0;
+      for (size_t i : uord) {
+        const uint32_t dim = (uint32_t)hs[pl.curves[items[next + i].curve].inst]->host.dim;
+        const uint32_t nunit = (dim + urows - 1) / urows;
+        unit0_of[i] = uu;
+        for (uint32_t v2 = 0; v2 < nunit; v2++) umap[uu + v2] = (int)i;
+        uu += nunit;
+      }
+    }
     size_t voff = 0;
-    uint32_t u0 = 0;
     for (size_t i = 0; i < nit; i++) {
       const Item &itm = items[next + i];
       const CurveInfo &cv = pl.curves[itm.curve];
       const ftlm_hamiltonian *h = hs[cv.inst];
       const uint32_t dim = (uint32_t)h->host.dim;
-      const uint32_t nunit = (dim + kUnitRows - 1) / kUnitRows;
+      const uint32_t nunit = (dim + urows - 1) / urows;
       const size_t vb = ((size_t)dim * K * pl.es + 255) & ~size_t(255);
       const size_t vbd = ((size_t)dim * (pl.es / 2) + 255) & ~size_t(255);
       auto fill = [&](auto tag) {
@@ -1019,7 +1067,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
         for (int k = 0; k < h->host.n; k++)
           if (h->host.radix[k] & (h->host.radix[k] - 1)) bi.pow2r = 0;
         bi.dim = dim;
-        bi.unit0 = u0;
+        bi.unit0 = unit0_of[i];
         bi.nunit = nunit;
         bi.col0 = (int)(i * K);
         bi.rng_inst = pp[cv.inst].instance;
@@ -1036,8 +1084,6 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       };
       if (f32) fill(float(0));
       else fill(double(0));
-      for (uint32_t v2 = 0; v2 < nunit; v2++) umap[u0 + v2] = (int)i;
-      u0 += nunit;
       voff += 4 * vb + vbd;
     }
     if (hipMemcpy(wbase + o_items, hitems.data(), hitems.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1045,9 +1091,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       set_error("copy of wave descriptors failed");
       return FTLM_EHIP;
     }
-    uint32_t gcap = 1024;
-    if (const char *e = std::getenv("FTLM_BATCH_GRID")) gcap = (uint32_t)std::max(64, std::atoi(e));
-    const uint32_t gx = (uint32_t)std::min<size_t>(units, gcap);
+    const uint32_t gx = (uint32_t)std::min<size_t>(units, (size_t)bt.grid_cap);
     BStep S{};
     S.K = K;
     S.n_lanczos = NL;
@@ -1055,6 +1099,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
     S.seed = pp[0].seed;
     S.part = reinterpret_cast<double *>(wbase + o_part);
     S.n_items = (uint32_t)nit;
+    S.ubits = bt.ubits;
     {
       size_t lds = 16;
       for (size_t i = 0; i < nit; i++) {
@@ -1127,8 +1172,16 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       bool issued = ok && issue(cap);
       if (ok) ok = hipStreamEndCapture(cap, &graph) == hipSuccess && issued;
       if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (ok && timing) ok = hipEventRecord(tev[0], s) == hipSuccess;
       if (ok) ok = hipGraphLaunch(exec, s) == hipSuccess;
+      if (ok && timing) ok = hipEventRecord(tev[1], s) == hipSuccess;
       if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
+      if (ok && timing) {
+        float ms = 0;
+        ok = hipEventElapsedTime(&ms, tev[0], tev[1]) == hipSuccess;
+        step_ms += ms;
+        step_launches += NL;
+      }
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);
       if (cap) (void)hipStreamDestroy(cap);
@@ -1203,6 +1256,29 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
       std::memcpy(out[k].n_lanczos_used, hn.data() + (size_t)pl.curve0[k] * R, sizeof(int) * nf * R);
     if (out[k].E_min) std::memcpy(out[k].E_min, hemin.data() + pl.curve0[k], sizeof(double) * nf);
   }
+  if (timing) {
+    *out[0].hv_ms = step_ms;
+    if (out[0].hv_launches) *out[0].hv_launches = step_launches;
+  }
+  return FTLM_OK;
+}
+
+int ftlm_batched_set_tuning(int32_t grid_cap, int32_t unit_bits, int32_t order) {
+  if (grid_cap != 0 && (grid_cap < 64 || grid_cap > 65536)) {
+    set_error("grid_cap must be 0 or in [64, 65536]");
+    return FTLM_EINVAL;
+  }
+  if (unit_bits != 0 && unit_bits != 11 && unit_bits != 12) {
+    set_error("unit_bits must be 0, 11 or 12");
+    return FTLM_EINVAL;
+  }
+  if (order < 0 || order > 1) {
+    set_error("order must be 0 (curve order) or 1 (largest first)");
+    return FTLM_EINVAL;
+  }
+  g_btune.grid_cap = grid_cap ? grid_cap : 1024;
+  g_btune.ubits = unit_bits ? unit_bits : 11;
+  g_btune.order = order;
   return FTLM_OK;
 }
 

@@ -141,7 +141,8 @@ struct PassPlan {
 };
 
 struct HvTuning {
-  int variant = 0;   // 0 = heuristic, 1 = direct gather, 2 = windowed passes, 3 = LDS tile, 4 = L2 windows
+  int variant = 0;   // 0 = heuristic, 1 = direct gather, 2 = windowed passes, 3 = LDS tile, 4 = L2 windows,
+                     // 5 = LDS tile over L2 windows, 6 = single-pass tiles (stream)
   int grid_cap = 0;  // 0 = default
   int kc = 0;        // columns per lane of the direct kernels (0 = widest dividing K)
 };
@@ -185,6 +186,43 @@ struct WinPlan {
   const void *d_pcoef = nullptr;
 };
 
+// Single-pass H*v for one column ("stream" kernel, variant 6).  Rows are walked
+// in tiles of the low digits: a tile is the T = st_t consecutive rows that share
+// the digits of every site >= t, so it is contiguous in memory and is staged in
+// LDS once.  Terms on tile sites only read the tile from LDS; terms that move an
+// outer digit read their partner rows straight from the vector (coalesced: the
+// partner rows of a tile are contiguous up to a shift within the tile), so v is
+// read from HBM about once and w written once, with the partner reads served by
+// L2 and the last-level cache.  Needs has_z == 0 (no row-dependent single-flip
+// coefficients).
+struct StreamGeom {
+  int n, t;                 // sites, tile sites (0..t-1)
+  int np_in, np_mx, np_out;  // pairs in stream order: both sites < t | i < t <= j | t <= i
+  uint32_t T, ntile, dim;   // rows per tile, tiles
+  uint32_t smask;           // sites with single-site flips
+  int radix[kMaxSites];
+  uint32_t st[kMaxSites];
+  int lg[kMaxSites];        // log2 of the stride of a tile site (tile radices all powers of two)
+  float s[kMaxSites];
+};
+
+struct StreamPlan {
+  bool ok = false;          // the kernel applies (has_z == 0)
+  bool pow2 = false;        // every tile radix is a power of two (digits are bit fields of the row)
+  bool cplx = true;         // some pair or single-site coefficient is complex
+  StreamGeom geom{};
+  std::vector<int> order;   // stream order -> host pair index
+  std::vector<double> tdiag;  // [T] diagonal of H restricted to the tile sites
+  // device copies (inside the handle's table block), in the plan's precision
+  const int2 *d_pij = nullptr;   // [np] (i, j), i < j
+  const void *d_pc = nullptr;    // [np][4] (++, +-, -+, --)
+  const void *d_pzz = nullptr;   // [np]
+  const void *d_tdiag = nullptr; // [T]
+};
+
+// Host part of the stream plan for tiles of at most tile_rows rows.
+void plan_stream(const HostHam &hh, uint32_t tile_rows, StreamPlan &pl);
+
 struct DevHam {
   HamGeom geom;
   HvTuning tune[2][65];  // [precision][columns]
@@ -193,6 +231,7 @@ struct DevHam {
   PassPlan plan64, plan32;  // windowed-pass plans for complex128 / complex64
   WinPlan win64, win32;     // L2-window plans for complex128 / complex64
   WinPlan tw64, tw32;       // L2-window plans of the LDS tile kernel (spin 1/2, N >= 12)
+  StreamPlan sp64, sp32;    // single-pass tile plans (complex128 / complex64)
   // key of the plans above (recomputed only when it changes)
   bool plan_valid = false;
   uint32_t plan_smask = 0;
@@ -268,6 +307,12 @@ struct HvLaunch {
 };
 
 int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s);
+struct HvParams;
+// Variant 6 (stream.hip): one launch of grid <= cap blocks; *gx receives its grid.
+// kc: bits 0..3 the block size (0: 1024 threads, 1: 256, 2: 512), bits 4..7 the
+// log2 of the tiles per XCD chunk.
+int launch_stream(const DevHam &dh, int precision, const HvParams &P, int cap, int kc, unsigned *gx,
+                  hipStream_t s);
 // (Re)computes the per-window records of both pass plans (allocates rec_block on
 // first use).  Synchronous.
 int build_pass_records(DevHam &dh, std::string &err);

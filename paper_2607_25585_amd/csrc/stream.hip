@@ -1,0 +1,450 @@
+// Single-pass H*v for one column (variant 6): w = H v in gather form (Sec. 2.1,
+// Eq. mce-hamop, in the ladder form of ftlm_internal.hpp), one launch, every
+// row of w written once.
+//
+// Rows are walked in tiles of the low digits (sites 0..t-1, T = st_t rows,
+// contiguous in memory).  A block stages its tile of v in LDS with coalesced
+// loads, then for each of its rows
+//   - the diagonal: a per-row table over the tile sites, plus the tile-uniform
+//     part of the outer sites and the z-z couplings between tile and outer sites
+//     (phi_i = sum_j zz_ij m_j over outer j, per tile);
+//   - single flips and pair flips whose sites are all tile sites: partner rows
+//     from LDS;
+//   - terms that move an outer digit: partner rows read straight from v.  For a
+//     given term the partner rows of a tile are the tile's rows shifted by one
+//     offset (plus, for a pair with one tile site, a shift inside the tile), so
+//     the loads are coalesced; their validity and coefficient are uniform over
+//     the tile except for the tile site's ladder factor.
+// Coefficients of invalid moves are zero in the site tables (the ladder factor
+// of a digit that would leave its range is 0), and such a move reads the row's
+// own element instead of an out-of-range one.
+//
+// Tile walk: with a grid that is a multiple of 8, block b runs on XCD b % 8
+// (workgroups are dispatched to the XCDs round robin).  Chunks of consecutive
+// tiles go to the XCDs in turn and each XCD's blocks walk its chunks in order:
+// inside a chunk a partner tile a few tiles away is in the XCD's L2, and since
+// all XCDs sweep the vector together, partner tiles further away were read
+// recently by some XCD and are found in the last-level cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "device_reduce.hpp"
+#include "ftlm_internal.hpp"
+#include "hv_common.hpp"
+
+namespace ftlm {
+
+namespace {
+
+template <typename R, bool CPLX>
+__device__ __forceinline__ void cfma(R &ar, R &ai, const Cx<R> c, const Cx<R> x) {
+  ar = fma(c.re, x.re, ar);
+  ai = fma(c.re, x.im, ai);
+  if (CPLX) {
+    ar = fma(-c.im, x.im, ar);
+    ai = fma(c.im, x.re, ai);
+  }
+}
+
+template <typename R, bool POW2, bool CPLX, int RPT, int NT>
+__global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, const int2 *__restrict__ pij,
+                                                const Cx<R> *__restrict__ pcs, const R *__restrict__ pzz,
+                                                const R *__restrict__ tdiag, const Cx<R> *__restrict__ hoffg,
+                                                uint32_t chunk, HvParams P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int t = G.t, n = G.n, tid = threadIdx.x;
+  const int np = G.np_in + G.np_mx + G.np_out;
+  const uint32_t T = G.T;
+  // LDS: the tile, then the tables every row reads at uniform indices
+  Cx<R> *tile = reinterpret_cast<Cx<R> *>(smem);    // [T]
+  Cx<R> *s_hoff = tile + T;                           // [t][4][16] single flips of tile sites
+  Cx<R> *s_pc = s_hoff + 64 * t;                      // [np][4]
+  R *s_gp = reinterpret_cast<R *>(s_pc + 4 * np);     // [n][16]
+  R *s_gm = s_gp + 16 * n;                            // [n][16]
+  R *s_hd = s_gm + 16 * n;                            // [n][16]
+  R *s_pzz = s_hd + 16 * n;                           // [np]
+  R *s_phi = s_pzz + np;                              // [t] phi_i, then the outer diagonal part
+  int2 *s_pij = reinterpret_cast<int2 *>(s_phi + t + 1 + ((t + 1) & 1));  // [np] (8-byte aligned)
+  for (int i = tid; i < 64 * t; i += NT) s_hoff[i] = tb.hoff[i];
+  for (int i = tid; i < 4 * np; i += NT) s_pc[i] = pcs[i];
+  for (int i = tid; i < 16 * n; i += NT) {
+    s_gp[i] = tb.gp[i];
+    s_gm[i] = tb.gm[i];
+    s_hd[i] = tb.hdiag[i];
+  }
+  for (int i = tid; i < np; i += NT) {
+    s_pzz[i] = pzz[i];
+    s_pij[i] = pij[i];
+  }
+  // digits of the thread's rows inside a tile (the same in every tile): bit
+  // fields of the row when every radix is a power of two, else 4-bit digits
+  // packed here once
+  uint32_t dig[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; k++) {
+    const uint32_t r = tid + (uint32_t)k * NT;
+    uint32_t pk = 0;
+    if (!POW2 && r < T) {
+      uint32_t rem = r;
+      for (int i = 0; i < t; i++) {
+        const uint32_t rd = (uint32_t)G.radix[i], q = rem / rd;
+        pk |= (rem - q * rd) << (4 * i);
+        rem = q;
+      }
+    }
+    dig[k] = POW2 ? r : pk;
+  }
+  auto digit = [&](int k, int i) -> int {
+    return POW2 ? (int)((dig[k] >> G.lg[i]) & (uint32_t)(G.radix[i] - 1)) : (int)((dig[k] >> (4 * i)) & 15u);
+  };
+  const Cx<R> *__restrict__ v = reinterpret_cast<const Cx<R> *>(P.v);
+  double red[3][1] = {{0.0}, {0.0}, {0.0}};
+  __syncthreads();
+
+  // tile walk: chunks of `chunk` consecutive tiles are dealt to the XCDs in
+  // turn (chunk c to XCD c % 8), and the blocks of an XCD walk its chunks in
+  // order, so all XCDs sweep the vector together
+  const bool xcd = gridDim.x >= 8 && (gridDim.x & 7u) == 0;
+  const uint32_t nbx = xcd ? gridDim.x >> 3 : gridDim.x, x = xcd ? blockIdx.x & 7u : 0u;
+  const uint32_t stride_c = xcd ? 8u : 1u;
+  for (uint32_t l = xcd ? blockIdx.x >> 3 : blockIdx.x;; l += nbx) {
+    const uint64_t tl64 = ((uint64_t)(l / chunk) * stride_c + x) * chunk + l % chunk;
+    if (tl64 >= G.ntile) break;
+    const uint32_t tl = (uint32_t)tl64;
+    const uint32_t base = tl * T;
+    // outer digits of this tile: bit fields of the row when every radix is a
+    // power of two, else 4 bits each (sites t..n-1 at bit 4 (k - t), n - t <= 16)
+    uint64_t od = 0;
+    if (!POW2) {
+      uint32_t rem = tl;
+      for (int k = t; k < n; k++) {
+        const uint32_t rd = (uint32_t)G.radix[k], q = rem / rd;
+        od |= (uint64_t)(rem - q * rd) << (4 * (k - t));
+        rem = q;
+      }
+    }
+    auto odig = [&](int k) -> int {
+      return POW2 ? (int)((base >> G.lg[k]) & (uint32_t)(G.radix[k] - 1)) : (int)((od >> (4 * (k - t))) & 15u);
+    };
+    auto om = [&](int k) -> R { return (R)odig(k) - (R)G.s[k]; };
+    // stage the tile
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+      const uint32_t r = tid + (uint32_t)k * NT;
+      if (r < T) tile[r] = v[base + r];
+    }
+    // tile-uniform diagonal parts: phi_i = sum over mixed pairs (i, j) of
+    // zz m_j (lane i < t), and the outer sites' own and mutual terms (lane t)
+    if (tid < t) {
+      R ph = 0;
+      for (int p = G.np_in; p < G.np_in + G.np_mx; p++) {
+        const int2 ij = s_pij[p];
+        if (ij.x == tid) ph = fma(s_pzz[p], om(ij.y), ph);
+      }
+      s_phi[tid] = ph;
+    } else if (tid == t) {
+      R d0 = 0;
+      for (int k = t; k < n; k++) d0 += s_hd[k * 16 + odig(k)];
+      for (int p = G.np_in + G.np_mx; p < np; p++) {
+        const int2 ij = s_pij[p];
+        d0 = fma(s_pzz[p] * om(ij.x), om(ij.y), d0);
+      }
+      s_phi[t] = d0;
+    }
+    __syncthreads();
+    R ar[RPT], ai[RPT];
+    const R d0 = s_phi[t];
+    // diagonal and the terms inside the tile (LDS)
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+      ar[k] = ai[k] = 0;
+      const uint32_t r = tid + (uint32_t)k * NT;
+      if (r >= T) continue;
+      R dg = tdiag[r] + d0;
+      for (int i = 0; i < t; i++) dg = fma((R)digit(k, i) - (R)G.s[i], s_phi[i], dg);
+      const Cx<R> xo = tile[r];
+      ar[k] = dg * xo.re;
+      ai[k] = dg * xo.im;
+      uint32_t sm = G.smask & ((t < 32) ? ((1u << t) - 1u) : 0xffffffffu);
+      while (sm) {
+        const int i = __builtin_ctz(sm);
+        sm &= sm - 1u;
+        const int d = digit(k, i), rd = G.radix[i];
+        const int st = (int)G.st[i];
+#pragma unroll
+        for (int di = 0; di < 4; di++) {
+          const int D = (di < 2) ? di - 2 : di - 1;
+          const bool ok = (unsigned)(d + D) < (unsigned)rd;
+          const Cx<R> c = s_hoff[(i * 4 + di) * 16 + d];
+          const uint32_t pr = ok ? (uint32_t)((int)r + D * st) : r;
+          cfma<R, CPLX>(ar[k], ai[k], c, tile[pr]);
+        }
+      }
+      for (int p = 0; p < G.np_in; p++) {
+        const int2 ij = s_pij[p];
+        const int di = digit(k, ij.x), dj = digit(k, ij.y);
+        const int si = (int)G.st[ij.x], sj = (int)G.st[ij.y];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const Cx<R> c = s_pc[4 * p + q];
+          if (c.re == R(0) && c.im == R(0)) continue;
+          const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;  // '-' ladder on site i / j
+          const R f = (im_ ? s_gm[ij.x * 16 + di] : s_gp[ij.x * 16 + di]) *
+                      (jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj]);
+          const uint32_t pr = (f != R(0)) ? (uint32_t)((int)r + (im_ ? si : -si) + (jm ? sj : -sj)) : r;
+          cfma<R, CPLX>(ar[k], ai[k], Cx<R>{c.re * f, c.im * f}, tile[pr]);
+        }
+      }
+    }
+    // single flips of outer sites: uniform coefficient and validity
+    {
+      uint32_t sm = G.smask & ~((t < 32) ? ((1u << t) - 1u) : 0xffffffffu);
+      while (sm) {
+        const int j = __builtin_ctz(sm);
+        sm &= sm - 1u;
+        const int d = odig(j), rd = G.radix[j];
+#pragma unroll
+        for (int di = 0; di < 4; di++) {
+          const int D = (di < 2) ? di - 2 : di - 1;
+          if ((unsigned)(d + D) >= (unsigned)rd) continue;
+          const Cx<R> c = hoffg[(j * 4 + di) * 16 + d];
+          const int64_t off = (int64_t)base + (int64_t)D * (int64_t)G.st[j];
+          Cx<R> y[RPT];
+#pragma unroll
+          for (int k = 0; k < RPT; k++) {
+            const uint32_t r = tid + (uint32_t)k * NT;
+            if (r < T) y[k] = v[off + r];
+          }
+#pragma unroll
+          for (int k = 0; k < RPT; k++)
+            if (tid + (uint32_t)k * NT < T) cfma<R, CPLX>(ar[k], ai[k], c, y[k]);
+        }
+      }
+    }
+    // pairs with one tile site i and one outer site j: the outer move is uniform,
+    // the tile site's ladder factor and validity are per row
+    for (int p = G.np_in; p < G.np_in + G.np_mx; p++) {
+      const int2 ij = s_pij[p];
+      const int dj = odig(ij.y), rj = G.radix[ij.y];
+      const int64_t si = (int64_t)G.st[ij.x], sj = (int64_t)G.st[ij.y];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const Cx<R> c = s_pc[4 * p + q];
+        if (c.re == R(0) && c.im == R(0)) continue;
+        const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;
+        if (jm ? (dj > rj - 2) : (dj < 1)) continue;
+        const R fj = jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj];
+        const Cx<R> cu{c.re * fj, c.im * fj};
+        const int64_t off = (int64_t)base + (jm ? sj : -sj) + (im_ ? si : -si);
+        const R *gi = (im_ ? s_gm : s_gp) + ij.x * 16;
+        Cx<R> y[RPT];
+        R fi[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; k++) {
+          const uint32_t r = tid + (uint32_t)k * NT;
+          fi[k] = 0;
+          if (r < T) {
+            fi[k] = gi[digit(k, ij.x)];
+            // an invalid move reads the row's own element (its factor is 0)
+            const int64_t idx = (fi[k] != R(0)) ? off + (int64_t)r : (int64_t)base + (int64_t)r;
+            y[k] = v[idx];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; k++)
+          if (tid + (uint32_t)k * NT < T) cfma<R, CPLX>(ar[k], ai[k], Cx<R>{cu.re * fi[k], cu.im * fi[k]}, y[k]);
+      }
+    }
+    // pairs of two outer sites: partner rows are the tile shifted by one offset
+    for (int p = G.np_in + G.np_mx; p < np; p++) {
+      const int2 ij = s_pij[p];
+      const int di = odig(ij.x), dj = odig(ij.y);
+      const int ri = G.radix[ij.x], rj = G.radix[ij.y];
+      const int64_t si = (int64_t)G.st[ij.x], sj = (int64_t)G.st[ij.y];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const Cx<R> c = s_pc[4 * p + q];
+        if (c.re == R(0) && c.im == R(0)) continue;
+        const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;
+        if (im_ ? (di > ri - 2) : (di < 1)) continue;
+        if (jm ? (dj > rj - 2) : (dj < 1)) continue;
+        const R f = (im_ ? s_gm[ij.x * 16 + di] : s_gp[ij.x * 16 + di]) *
+                    (jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj]);
+        const Cx<R> cf{c.re * f, c.im * f};
+        const int64_t off = (int64_t)base + (im_ ? si : -si) + (jm ? sj : -sj);
+        Cx<R> y[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; k++) {
+          const uint32_t r = tid + (uint32_t)k * NT;
+          if (r < T) y[k] = v[off + r];
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; k++)
+          if (tid + (uint32_t)k * NT < T) cfma<R, CPLX>(ar[k], ai[k], cf, y[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+      const uint32_t r = tid + (uint32_t)k * NT;
+      if (r >= T) continue;
+      Acc<R, 1> a;
+      a.re[0] = ar[k];
+      a.im[0] = ai[k];
+      hv_epilogue<R, 1, true>(P, base + r, 0, a, tile + r, red);
+    }
+    __syncthreads();  // the next tile overwrites the LDS
+  }
+  hv_finish<1, NT>(P, red);
+}
+
+template <typename R>
+size_t stream_smem(const StreamGeom &g) {
+  const size_t np = (size_t)(g.np_in + g.np_mx + g.np_out);
+  size_t b = sizeof(Cx<R>) * ((size_t)g.T + 64 * (size_t)g.t + 4 * np) +
+             sizeof(R) * (48 * (size_t)g.n + np + (size_t)g.t + 2);
+  b = (b + 7) & ~size_t(7);
+  return b + sizeof(int2) * np;
+}
+
+// kc of the tuning: bits 0..3 select the block (0: 1024 threads, 1: 256,
+// 2: 512), bits 4..7 the log2 of the tiles per XCD chunk
+inline int stream_threads(int kc) { return (kc & 15) == 1 ? 256 : (kc & 15) == 2 ? 512 : 1024; }
+inline uint32_t stream_chunk(int kc) { return 1u << ((kc >> 4) & 15); }
+
+template <typename R, bool POW2, bool CPLX, int RPT, int NT>
+void launch_stream_t(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
+                     hipStream_t s) {
+  static size_t granted = 0;  // per instantiation
+  const size_t sm = stream_smem<R>(sp.geom);
+  if (sm > granted) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_stream<R, POW2, CPLX, RPT, NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    granted = sm;
+  }
+  hipLaunchKernelGGL((hv_stream<R, POW2, CPLX, RPT, NT>), dim3(gx), dim3(NT), sm, s, sp.geom, tb, sp.d_pij,
+                     reinterpret_cast<const Cx<R> *>(sp.d_pc), reinterpret_cast<const R *>(sp.d_pzz),
+                     reinterpret_cast<const R *>(sp.d_tdiag), tb.hoff, chunk, P);
+}
+
+template <typename R, bool POW2, bool CPLX, int NT>
+void launch_stream_rpt(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
+                       hipStream_t s) {
+  // tiles hold at most 8192 rows: 8, 16 or 32 rows per thread at 1024, 512 or 256 threads
+  const uint32_t rpt = (sp.geom.T + NT - 1) / NT;
+  if (rpt <= 2) launch_stream_t<R, POW2, CPLX, 2, NT>(sp, tb, P, gx, chunk, s);
+  else if (rpt <= 4) launch_stream_t<R, POW2, CPLX, 4, NT>(sp, tb, P, gx, chunk, s);
+  else if (rpt <= 8) launch_stream_t<R, POW2, CPLX, 8, NT>(sp, tb, P, gx, chunk, s);
+  else if constexpr (NT <= 512) {
+    if (rpt <= 16) launch_stream_t<R, POW2, CPLX, 16, NT>(sp, tb, P, gx, chunk, s);
+    else if constexpr (NT <= 256) launch_stream_t<R, POW2, CPLX, 32, NT>(sp, tb, P, gx, chunk, s);
+  }
+}
+
+template <typename R, int NT>
+void launch_stream_nt(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
+                      hipStream_t s) {
+  if (sp.pow2) {
+    if (sp.cplx) launch_stream_rpt<R, true, true, NT>(sp, tb, P, gx, chunk, s);
+    else launch_stream_rpt<R, true, false, NT>(sp, tb, P, gx, chunk, s);
+  } else {
+    if (sp.cplx) launch_stream_rpt<R, false, true, NT>(sp, tb, P, gx, chunk, s);
+    else launch_stream_rpt<R, false, false, NT>(sp, tb, P, gx, chunk, s);
+  }
+}
+
+template <typename R>
+int launch_stream_r(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, int cap, int kc,
+                    unsigned *gx_out, hipStream_t s) {
+  if (!sp.ok || !sp.d_pij || !sp.d_tdiag) return FTLM_EINVAL;
+  const int nt = stream_threads(kc);
+  if (sp.geom.T > 8192u || (sp.geom.T + nt - 1) / nt > 8192u / nt) return FTLM_ERANGE;
+  if (stream_smem<R>(sp.geom) > 160 * 1024) return FTLM_ERANGE;
+  uint32_t gx = sp.geom.ntile < (uint32_t)cap ? sp.geom.ntile : (uint32_t)cap;
+  if (gx >= 8) gx &= ~7u;
+  const uint32_t chunk = stream_chunk(kc);
+  if (nt == 256) launch_stream_nt<R, 256>(sp, tb, P, gx, chunk, s);
+  else if (nt == 512) launch_stream_nt<R, 512>(sp, tb, P, gx, chunk, s);
+  else launch_stream_nt<R, 1024>(sp, tb, P, gx, chunk, s);
+  *gx_out = gx;
+  return FTLM_OK;
+}
+
+}  // namespace
+
+int launch_stream(const DevHam &dh, int precision, const HvParams &P, int cap, int kc, unsigned *gx, hipStream_t s) {
+  if (P.K != 1) return FTLM_EINVAL;
+  return precision == FTLM_C64 ? launch_stream_r<float>(dh.sp32, dh.t32, P, cap, kc, gx, s)
+                               : launch_stream_r<double>(dh.sp64, dh.t64, P, cap, kc, gx, s);
+}
+
+// Host plan: the tile takes the low sites while their rows fit tile_rows (and,
+// unless every tile radix is a power of two, at most 8 sites so that a row's
+// tile digits pack into 32 bits); pairs are ordered inside | mixed | outer.
+void plan_stream(const HostHam &hh, uint32_t tile_rows, StreamPlan &pl) {
+  pl = StreamPlan();
+  const int n = hh.n;
+  if (hh.has_z || n < 1) return;
+  bool pow2 = true;
+  for (int k = 0; k < n; k++) pow2 = pow2 && (hh.radix[k] & (hh.radix[k] - 1)) == 0;
+  uint64_t T = 1;
+  int t = 0;
+  while (t < n && T * (uint64_t)hh.radix[t] <= tile_rows && (pow2 || t < 8)) T *= (uint64_t)hh.radix[t++];
+  // digits of rows and tiles are bit fields when every radix is a power of two,
+  // else 4-bit fields packed in 32 (tile) and 64 (outer) bits
+  if (t < 1 || (!pow2 && n - t > 16)) return;
+  StreamGeom &g = pl.geom;
+  std::memset(&g, 0, sizeof(g));
+  g.n = n;
+  g.t = t;
+  g.T = (uint32_t)T;
+  g.dim = (uint32_t)hh.dim;
+  g.ntile = (uint32_t)(hh.dim / T);
+  for (int k = 0; k < n; k++) {
+    g.radix[k] = hh.radix[k];
+    g.st[k] = hh.stride[k];
+    g.s[k] = 0.5f * (float)hh.two_s[k];
+    int lg = 0;
+    while ((1u << lg) < hh.stride[k]) lg++;
+    g.lg[k] = lg;
+    if (site_has_singles(hh, k)) g.smask |= 1u << k;
+  }
+  auto cls = [&](int p) { return (hh.pi[p] >= t) + (hh.pj[p] >= t); };
+  pl.order.resize(hh.npair);
+  for (int p = 0; p < hh.npair; p++) pl.order[p] = p;
+  std::stable_sort(pl.order.begin(), pl.order.end(), [&](int a, int b) { return cls(a) < cls(b); });
+  for (int p = 0; p < hh.npair; p++) {
+    const int c = cls(p);
+    (c == 0 ? g.np_in : c == 1 ? g.np_mx : g.np_out)++;
+  }
+  bool cplx = false;
+  for (int p = 0; p < hh.npair; p++)
+    for (int a = 0; a < 4; a++) cplx = cplx || hh.pc[4 * p + a].im != 0.0;
+  for (int k = 0; k < n; k++)
+    for (int a = 0; a < hh.radix[k]; a++)
+      for (int b = 0; b < hh.radix[k]; b++)
+        if (a != b) cplx = cplx || hh.h[(size_t)k * 256 + a * 16 + b].im != 0.0;
+  pl.cplx = cplx;
+  pl.pow2 = pow2;
+  // diagonal over the tile sites, per tile row
+  pl.tdiag.assign(T, 0.0);
+  for (uint32_t r = 0; r < T; r++) {
+    int d[kMaxSites];
+    uint32_t rem = r;
+    for (int k = 0; k < t; k++) {
+      d[k] = (int)(rem % (uint32_t)hh.radix[k]);
+      rem /= (uint32_t)hh.radix[k];
+    }
+    double s = 0;
+    for (int k = 0; k < t; k++) s += hh.h[(size_t)k * 256 + d[k] * 16 + d[k]].re;
+    for (int p = 0; p < hh.npair; p++)
+      if (hh.pi[p] < t && hh.pj[p] < t)
+        s += hh.pzz[p] * (d[hh.pi[p]] - 0.5 * hh.two_s[hh.pi[p]]) * (d[hh.pj[p]] - 0.5 * hh.two_s[hh.pj[p]]);
+    pl.tdiag[r] = s;
+  }
+  pl.ok = true;
+}
+
+}  // namespace ftlm

@@ -167,3 +167,59 @@ def test_batched_largest_cfg3_instances_match_oracle(prec, tol):
         ref = of.ftlm(s, R, NL, T, seed=spec.seed, fields=fl[k], instance=k)
         for key in ("lnZ", "E", "C", "M"):
             assert curve_err(got[k][key][0], ref[0][key]) < tol, (k, key)
+
+
+@pytest.mark.parametrize("grid,ubits,order", [(512, 12, 1), (64, 11, 1), (4096, 12, 0)])
+def test_batched_tuned_launches_match_oracle(grid, ubits, order):
+    """Every launch choice of the batched autotuner keeps oracle parity: 4096-row
+    work units (the spin-1/2 z-field unit table over row bits 8..11), units laid
+    out largest instance first, small and large grids; a 13-site spin-1/2
+    dipolar instance (two 4096-row units) next to smaller ones of general
+    radix."""
+    rng = np.random.default_rng(515)
+    systems = []
+    for n, two_s in ((13, 1), (9, 1), (4, 2), (3, 3)):
+        s = W.random_small_system(rng, n, max_two_s=3)
+        s.two_s[:] = two_s
+        systems.append(s)
+    fields = [W.unit_vectors(rng, 2) * 0.8 for _ in systems]
+    T = W.t_grid(24)
+    hams = [F().Hamiltonian(s) for s in systems]
+    print("case batched tuning grid", grid, "unit bits", ubits, "order", order, flush=True)
+    F().batched_set_tuning(grid, ubits, order)
+    try:
+        got = F().run_batched(hams, 4, 30, T, fields, seed=29, precision=0, columns=2, time_steps=True)
+    finally:
+        F().batched_set_tuning(0, 0, 0)
+    assert got[0]["steps"][0] >= 30 and got[0]["step_ms"][0] > 0
+    for k, s in enumerate(systems):
+        ref = of.ftlm(s, 4, 30, T, seed=29, fields=fields[k], instance=k)
+        for f in range(len(fields[k])):
+            for key in ("lnZ", "E", "C", "M"):
+                assert curve_err(got[k][key][f], ref[f][key]) < 1e-8, (k, f, key)
+
+
+def test_batched_autotuner_choice_keeps_parity():
+    """The batched autotuner on a small uneven set: its choice (columns, grid,
+    unit rows, unit order) is applied and the tuned run matches the oracle."""
+    from paper_2607_25585_amd import autotune
+    rng = np.random.default_rng(616)
+    systems = []
+    for n in (12, 10, 8):
+        s = W.random_small_system(rng, n, max_two_s=1)
+        s.two_s[:] = 1
+        systems.append(s)
+    fields = [W.unit_vectors(rng, 1) * 1.0 for _ in systems]
+    T = W.t_grid(24)
+    hams = [F().Hamiltonian(s) for s in systems]
+    try:
+        c = autotune.tune_batched(hams, 4, T, fields, seed=31, precision=0, n_steps=4)
+        print("tuned batched launch", c, flush=True)
+        assert c["columns"] in (1, 2, 4) and c["unit_bits"] in (11, 12) and c["order"] in (0, 1)
+        got = F().run_batched(hams, 4, 25, T, fields, seed=31, precision=0, columns=c["columns"])
+    finally:
+        F().batched_set_tuning(0, 0, 0)
+    for k, s in enumerate(systems):
+        ref = of.ftlm(s, 4, 25, T, seed=31, fields=fields[k], instance=k)
+        for key in ("lnZ", "E", "C", "M"):
+            assert curve_err(got[k][key][0], ref[0][key]) < 1e-8, (k, key)

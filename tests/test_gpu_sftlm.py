@@ -93,3 +93,85 @@ def test_ring6_sftlm_matches_oracle():
         assert np.max(np.abs(got["lnZ"][f] - ref[f]["lnZ"])) < 1e-8
         for key in ("E", "C", "M"):
             assert curve_err(got[key][f], ref[f][key]) < 1e-7, key
+
+
+def _ring5_exact():
+    import json
+    import os
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ring5_exact.json")
+    with open(p) as f:
+        return json.load(f)
+
+
+def _blocks(ham, n_blocks, r_block, T, field, seed):
+    """n_blocks independent sFTLM estimates of r_block vectors each (distinct
+    generator instances), returned as per-block Z, <eps>, <eps^2> and M."""
+    out = []
+    for b in range(n_blocks):
+        g = F().run_sftlm(ham, r_block, 100, T, seed=seed, fields=[field], instance=b)
+        E = g["E"][0]
+        E2 = g["C"][0] * T ** 2 + E ** 2
+        out.append((g["lnZ"][0], E, E2, g["M"][0]))
+    # Z of each block relative to the largest at each T (ln Z reaches ~6000 at 0.1 K)
+    top = np.max([b[0] for b in out], axis=0)
+    return [(np.exp(b[0] - top),) + b[1:] for b in out]
+
+
+def _combine(blocks, T):
+    Z = np.sum([b[0] for b in blocks], axis=0)
+    E = np.sum([b[0] * b[1] for b in blocks], axis=0) / Z
+    E2 = np.sum([b[0] * b[2] for b in blocks], axis=0) / Z
+    M = np.sum([b[0] * b[3] for b in blocks], axis=0) / Z
+    return (E2 - E ** 2) / T ** 2, M
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("fi", [0, 1])
+def test_sftlm_ring5_against_exact_diagonalisation(fi):
+    """sFTLM with time-reversed pairs on the five-site s=5/2 ring of Sec. 3.2
+    (dim 7776) at 0.1 T and 1 T against its exact spectrum
+    (tests/golden/ring5_exact.json, written by make_ring5_exact.py from the
+    dense oracle): the exact C and M lie inside a 4-sigma jackknife band over
+    16 independent blocks of 8 vectors, and the error of the estimate shrinks
+    from 32 to 512 vectors."""
+    ex = _ring5_exact()
+    T = np.asarray(ex["T"])
+    B = ex["fields_T"][fi]
+    cex, mex = np.asarray(ex["curves"][fi]["C"]), np.asarray(ex["curves"][fi]["M"])
+    sysm, spec = W.ring_sftlm(5, B)
+    ham = F().Hamiltonian(sysm)
+    print("case sFTLM ring5 vs exact, B", B, flush=True)
+    blocks = _blocks(ham, 16, 8, T, [0.0, 0.0, B], spec.seed)
+    C, M = _combine(blocks, T)
+    loo = [_combine(blocks[:b] + blocks[b + 1:], T) for b in range(16)]
+    lc, lm = np.array([x[0] for x in loo]), np.array([x[1] for x in loo])
+    sc = np.sqrt(15 / 16 * ((lc - lc.mean(0)) ** 2).sum(0))
+    sm = np.sqrt(15 / 16 * ((lm - lm.mean(0)) ** 2).sum(0))
+    assert np.all(np.abs(C - cex) <= 4 * sc + 1e-3 * cex.max()), np.max(np.abs(C - cex) / (sc + 1e-30))
+    assert np.all(np.abs(M - mex) <= 4 * sm + 1e-3 * np.abs(mex).max())
+    # R scan: the error of one estimate of R vectors falls as R grows
+    errs = {}
+    for R in (32, 128, 512):
+        g = F().run_sftlm(ham, R, 100, T, seed=spec.seed + 1, fields=[[0.0, 0.0, B]])
+        errs[R] = (float(np.sqrt(np.mean((g["C"][0] - cex) ** 2))),
+                   float(np.sqrt(np.mean((g["M"][0] - mex) ** 2))))
+    print("ring5 B", B, "rms errors (C, M) by R", errs, flush=True)
+    assert errs[512][0] < errs[32][0] and errs[512][1] < errs[32][1]
+
+
+def test_sftlm_field_reversal_on_gpu():
+    """With time-reversed pairs, the moment along the field is even under
+    B -> -B (the vector set maps to itself under Theta, which takes H(B) to
+    H(-B)): M(-B) = M(B), ln Z, E and C unchanged, on the GPU path.  The two
+    fields run separately so that both use the vectors of field index 0 (the
+    generator's counter holds the field index)."""
+    rng = np.random.default_rng(2600)
+    sysm = W.random_small_system(rng, 4, max_two_s=3)
+    T = W.t_grid(40)
+    ham = F().Hamiltonian(sysm)
+    B = np.asarray(sysm.B)
+    a = F().run_sftlm(ham, 6, 40, T, seed=17, fields=[B])
+    b = F().run_sftlm(ham, 6, 40, T, seed=17, fields=[-B])
+    assert np.max(np.abs(a["lnZ"][0] - b["lnZ"][0])) < 1e-9
+    for key in ("E", "C", "M"):
+        assert curve_err(b[key][0], a[key][0]) < 1e-8, key
