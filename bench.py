@@ -37,7 +37,7 @@ def _kernel_sha():
     """Hash of the sources that define the H*v kernels (kernels, their shared
     device helpers and internal header)."""
     h = hashlib.sha256()
-    for name in ("kernels.hip", "device_reduce.hpp", "ftlm_internal.hpp"):
+    for name in ("kernels.hip", "stream.hip", "hv_common.hpp", "device_reduce.hpp", "ftlm_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2607_25585_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -91,43 +91,122 @@ def curve_err(x, ref):
     return float(np.max(np.abs(np.asarray(x) - ref) / np.maximum(np.abs(ref), max(floor, 1e-300))))
 
 
-def batched_vs_plain(n_inst=8, n_dirs=4):
-    """Batched FP32-storage FTLM against plain FP64 FTLM on the same curves: the
-    first n_inst instances of the 64-instance batched workload, n_dirs of its 50
-    field directions each, R = 16, N_L = 120, same seeded random vectors."""
+def stratified_cfg3(systems):
+    """Indices of the first instance of each spin count 14..22 of the batched
+    workload (one instance per size, as the batched protocol's subset asks)."""
+    pick = []
+    for n in range(14, 23):
+        ks = [k for k, s in enumerate(systems) if s.n_sites == n]
+        if ks:
+            pick.append(ks[0])
+    return pick
+
+
+def batched_vs_plain(n_dirs=4, tune=True):
+    """Batched FP32-storage FTLM against plain FP64 FTLM on the same curves: a
+    stratified subset of the 64-instance batched workload (the first instance
+    of every spin count 14..22), n_dirs of its 50 field directions each, R = 16,
+    N_L = 120, same seeded random vectors.  The batched launch (columns per
+    item, grid, unit rows, unit order) comes from the batched autotuner, timed
+    outside the measured region."""
     import numpy as np
     import torch
 
     import ftlm_workloads as W
     import paper_2607_25585_amd as F
     systems, spec, fields = W.cfg3()
-    systems = systems[:n_inst]
-    fl = [fields[k][:n_dirs] for k in range(n_inst)]
+    pick = stratified_cfg3(systems)
+    systems = [systems[k] for k in pick]
+    n_inst = len(systems)
+    fl = [fields[k][:n_dirs] for k in pick]
     hams = [F.Hamiltonian(s) for s in systems]
+    btune = None
+    if tune:
+        from paper_2607_25585_amd import autotune
+        btune = autotune.tune_batched(hams, spec.R, spec.T, fl, seed=spec.seed, precision=F.FTLM_C64)
+        print("batched autotune done", btune, file=sys.stderr, flush=True)
     # warm-up on a tiny run (kernel loading), outside the timed region
     F.run_batched(hams[:1], spec.R, 4, spec.T, [fl[0][:1]], seed=spec.seed, precision=F.FTLM_C64)
     F.run(hams[0], spec.R, 4, spec.T, seed=spec.seed, fields=fl[0][:1])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    bat = F.run_batched(hams, spec.R, spec.n_lanczos, spec.T, fl, seed=spec.seed, precision=F.FTLM_C64)
+    bat = F.run_batched(hams, spec.R, spec.n_lanczos, spec.T, fl, seed=spec.seed, precision=F.FTLM_C64,
+                        columns=btune["columns"] if btune else 0)
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     print("batched fp32 subset done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     plain = [F.run(h, spec.R, spec.n_lanczos, spec.T, seed=spec.seed, fields=fl[k], instance=k)
              for k, h in enumerate(hams)]
+    F.batched_set_tuning(0, 0, 0)
     torch.cuda.synchronize()
     t_p = time.perf_counter() - t0
     print("plain fp64 subset done", file=sys.stderr, flush=True)
     n_curves = n_inst * n_dirs
     err_c = max(curve_err(bat[k]["C"][f], plain[k]["C"][f]) for k in range(n_inst) for f in range(n_dirs))
     err_m = max(curve_err(bat[k]["M"][f], plain[k]["M"][f]) for k in range(n_inst) for f in range(n_dirs))
-    return {"curves": n_curves, "subset": "instances 0..%d (N=%s) x %d field directions, R=%d, N_L=%d"
-            % (n_inst - 1, [s.n_sites for s in systems], n_dirs, spec.R, spec.n_lanczos),
+    return {"curves": n_curves, "subset": "instances %s (N=%s, one per spin count) x field directions "
+            "0..%d, R=%d, N_L=%d" % (pick, [s.n_sites for s in systems], n_dirs - 1, spec.R, spec.n_lanczos),
+            "batched_tuning": btune,
             "batched_fp32_curves_per_s": round(n_curves / t_b, 4),
             "plain_fp64_curves_per_s": round(n_curves / t_p, 4),
             "speedup": round(t_p / t_b, 3), "max_C_err_vs_plain_fp64": err_c,
             "max_M_err_vs_plain_fp64": err_m, "C_within_1e-3": bool(err_c <= 1e-3)}
+
+
+def hv_rate(ham, dt, reps):
+    """Median of reps H*v launches, each bracketed by HIP events on the current
+    stream (the one ham.apply launches on)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    v = torch.randn((ham.dim,), dtype=dt, device="cuda", generator=g)
+    w = torch.empty_like(v)
+    ham.apply(v, w)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ham.apply(v, w)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del v, w
+    torch.cuda.empty_cache()
+    return float(sorted(times)[len(times) // 2]), float(min(times))
+
+
+def hv_hbm(workloads=("cfg4_hb", "cfg2_hb"), reps=20):
+    """H*v GB/s where the HBM roofline binds: the short-range variants (nearest
+    and next-nearest Heisenberg exchange, field along z, real coefficients) at
+    full size, complex128, one column, tuned launch.  algorithmic bytes = read v
+    + write w once (32 B per row); traffic = calibrated rocprofv3 FETCH_SIZE +
+    WRITE_SIZE per product from profiles/hv_traffic.json (null when the kernel
+    sources changed since the counters were taken)."""
+    import torch
+
+    import ftlm_workloads as W
+    import paper_2607_25585_amd as F
+    from paper_2607_25585_amd import autotune
+    out = {}
+    for wl in workloads:
+        sysm = W.WORKLOADS[wl]()[0]
+        ham = F.Hamiltonian(sysm)
+        tuning = autotune.tune(ham, F.FTLM_C128, 1, use_cache=False)
+        ms, ms_min = hv_rate(ham, torch.complex128, reps)
+        alg = 32.0 * ham.dim
+        gbps = alg / (ms * 1e-3) / 1e9
+        out[wl] = {"dim": ham.dim, "nnz_per_row": round(ham.nnz_per_row, 3), "precision": "c128",
+                   "hv_ms_median": round(ms, 4), "hv_ms_min": round(ms_min, 4),
+                   "algorithmic_bytes": alg, "achieved_GBps": round(gbps, 1), "peak_GBps": HBM_PEAK_GBPS,
+                   "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": _traffic(wl, "c128"),
+                   "tuning": tuning}
+        print("hv_hbm %s done" % wl, file=sys.stderr, flush=True)
+        ham.close()
+        del ham
+        torch.cuda.empty_cache()
+    return out
 
 
 def hv_only(args, sysm, spec, ham, prec, K):
@@ -172,11 +251,15 @@ def hv_only(args, sysm, spec, ham, prec, K):
                 "nnz_per_row": round(nnz, 3)}}
 
 
-def surrogate_report(n_train, n_test, train_s):
+def surrogate_report(n_train, n_test, train_s, n_val=1000, tol=0.05, n_powder_sets=8, n_dirs=50):
     """The learned surrogate on the 8-spin s=3/2 ring data: FTLM training curves
     (batched FP32 path, R=20, N_L=100, 200 temperatures), an ensemble of two MLPs
-    trained by the library's BF16/FP32 kernels, held-out errors against plain FP64
-    FTLM curves of the same parameters, and curves/s of both."""
+    trained by the library's BF16/FP32 kernels, a gate calibrated on a validation
+    split (FP64 FTLM truth) so that the accepted curves have their 90th
+    percentile of C error above 1 K at most tol, held-out errors and acceptance
+    against plain FP64 FTLM curves of other parameters, and the powder-average
+    protocol: n_dirs field directions x 200 T per set, surrogate against batched
+    FTLM, curves/s and the error of the powder average."""
     import numpy as np
     import torch
 
@@ -186,6 +269,7 @@ def surrogate_report(n_train, n_test, train_s):
     spec = W.cfg5_runspec()
     ptrain = W.cfg5_params(n_train, seed=5000)
     ptest = W.cfg5_params(n_test, seed=5001)
+    pval = W.cfg5_params(n_val, seed=5002)
     t0 = time.perf_counter()
     parts = []
     for a in range(0, n_train, 1024):  # chunk seeds depend only on the row offset
@@ -202,6 +286,9 @@ def surrogate_report(n_train, n_test, train_s):
     torch.cuda.synchronize()
     t_ftlm64 = time.perf_counter() - t0
     print("surrogate: %d held-out FP64 curves in %.1f s" % (n_test, t_ftlm64), file=sys.stderr, flush=True)
+    _lv, _mv, ccv = S.generate_dataset(pval, T, spec.R, spec.n_lanczos, seed=spec.seed + 1999, chunk=256,
+                                       precision=0)
+    print("surrogate: %d validation FP64 curves" % n_val, file=sys.stderr, flush=True)
     x = S.encode_inputs(ptrain, T)
     y = S.encode_targets(lz, mm, cc, T)
     models, losses = [], []
@@ -220,8 +307,9 @@ def surrogate_report(n_train, n_test, train_s):
         print("surrogate: member %d trained" % seed, file=sys.stderr, flush=True)
     t_train = time.perf_counter() - t0
     print("surrogate: trained in %.1f s" % t_train, file=sys.stderr, flush=True)
-    ens = S.Surrogate(models, disagreement=0.05)
-    plz, pm, pc, spread = ens.predict(ptest, T)
+    ens = S.Surrogate(models)
+    acc_val = ens.calibrate(pval, ccv, T, tol=tol, quantile=0.9)
+    plz, pm, pc, score = ens.predict(ptest, T)
     torch.cuda.synchronize()
     reps = 20
     t0 = time.perf_counter()
@@ -238,20 +326,58 @@ def surrogate_report(n_train, n_test, train_s):
     eZ = np.max(np.abs(plz - lzt), axis=1)
     hi = T >= 1.0
     eC1, eM1 = rel(pc, cct, hi), rel(pm, mmt, hi)
-    acc = spread <= ens.disagreement
+    acc = ens.in_domain(ptest, T) & (score <= ens.threshold)
     q = lambda a: {"median": float(np.median(a)), "p90": float(np.quantile(a, 0.9)), "max": float(np.max(a))} if len(a) else None  # noqa: E731
     rms = lambda a, b: float(np.sqrt(np.mean((a - b) ** 2)))  # noqa: E731
-    return {"train_sets": n_train, "test_sets": n_test, "T_points": len(T),
+
+    # powder average: every held-out set's |B| over n_dirs directions uniform on the sphere
+    rng = np.random.default_rng(5003)
+    dirs = W.unit_vectors(rng, n_dirs)
+    theta, phi = np.arccos(np.clip(dirs[:, 2], -1, 1)), np.mod(np.arctan2(dirs[:, 1], dirs[:, 0]), 2 * np.pi)
+    pp = np.repeat(ptest, n_dirs, axis=0)
+    pp[:, 4] = np.tile(theta, n_test)
+    pp[:, 5] = np.tile(phi, n_test)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _l, pm_p, pc_p, sc_p = ens.predict(pp, T)
+    torch.cuda.synchronize()
+    t_sur_p = time.perf_counter() - t0
+    acc_p = (sc_p <= ens.threshold).reshape(n_test, n_dirs)
+    sub = pp[: n_powder_sets * n_dirs]
+    t0 = time.perf_counter()
+    _l, pm_f, pc_f = S.generate_dataset(sub, T, spec.R, spec.n_lanczos, seed=spec.seed + 2999, chunk=200,
+                                        precision=1)
+    torch.cuda.synchronize()
+    t_ftlm_p = time.perf_counter() - t0
+    print("surrogate: powder protocol done", file=sys.stderr, flush=True)
+    cs = pc_p[: n_powder_sets * n_dirs].reshape(n_powder_sets, n_dirs, -1).mean(1)
+    cf = pc_f.reshape(n_powder_sets, n_dirs, -1).mean(1)
+    ms_ = pm_p[: n_powder_sets * n_dirs].reshape(n_powder_sets, n_dirs, -1).mean(1)
+    mf = pm_f.reshape(n_powder_sets, n_dirs, -1).mean(1)
+    return {"train_sets": n_train, "validation_sets": n_val, "test_sets": n_test, "T_points": len(T),
             "rmse_all_T": {"lnZ": rms(plz, lzt), "M_muB": rms(pm, mmt), "C_kB": rms(pc, cct)},
             "heldout_C_relerr_A12_T_ge_1K": q(eC1), "heldout_M_relerr_A12_T_ge_1K": q(eM1),
-            "gate_accepted_C_relerr_A12_T_ge_1K": q(eC1[acc]),
+            "gate": {"score": "ensemble disagreement on C above 1 K (relative measure)",
+                     "tolerance": "p90 of C relative error above 1 K <= %g" % tol,
+                     "threshold": ens.threshold, "validation_acceptance": acc_val,
+                     "heldout_acceptance": float(np.mean(acc)),
+                     "heldout_accepted_C_relerr_A12_T_ge_1K": q(eC1[acc]),
+                     "heldout_accepted_M_relerr_A12_T_ge_1K": q(eM1[acc]),
+                     "powder_directions_accepted": float(np.mean(acc_p))},
             "ftlm_fp32_batched_curves_per_s": round(n_train / t_gen, 3),
             "ftlm_fp64_batched_curves_per_s": round(n_test / t_ftlm64, 3),
             "surrogate_curves_per_s": round(n_test / t_sur, 1),
             "speedup_vs_fp64_ftlm": round((n_test / t_sur) / (n_test / t_ftlm64), 1),
+            "powder": {"directions": n_dirs, "T_points": len(T),
+                       "surrogate_curves_per_s": round(len(pp) / t_sur_p, 1),
+                       "ftlm_fp32_curves_per_s": round(len(sub) / t_ftlm_p, 2),
+                       "surrogate_powder_sets_per_s": round(n_test / t_sur_p, 2),
+                       "ftlm_powder_sets_per_s": round(n_powder_sets / t_ftlm_p, 4),
+                       "powder_C_relerr_A12_T_ge_1K": q(rel(cs, cf, hi)),
+                       "powder_M_relerr_A12_T_ge_1K": q(rel(ms_, mf, hi)),
+                       "ftlm_sets": n_powder_sets},
             "train_s": round(t_train, 1), "final_losses": [float(v) for v in losses],
-            "heldout_C_relerr_A12": q(eC), "heldout_M_abserr_muB": q(eM), "heldout_lnZ_abserr": q(eZ),
-            "gate_accepts": float(np.mean(spread <= ens.disagreement))}
+            "heldout_C_relerr_A12": q(eC), "heldout_M_abserr_muB": q(eM), "heldout_lnZ_abserr": q(eZ)}
 
 
 def extras_report():
@@ -336,6 +462,8 @@ def main():
                     help="random vectors iterated together (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-hbm", action="store_true",
+                    help="skip the short-range H*v GB/s object (cfg4_hb, cfg2_hb)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched-FP32 vs plain-FP64 comparison on the cfg3 subset")
     ap.add_argument("--no-tune", action="store_true")
@@ -372,7 +500,8 @@ def main():
         return
     if args.batched_only:
         out = {"metric": "FTLM curves/s batched-FP32 vs plain FP64 at C(T) <=1e-3 rel", "n_gpus": 1,
-               "data": "synthetic", "config": {"workload": "cfg3 subset: 8 instances x 4 field directions"}}
+               "data": "synthetic",
+               "config": {"workload": "cfg3 stratified subset: one instance per N=14..22 x 4 field directions"}}
         out["batched_fp32_vs_plain_fp64"] = batched_vs_plain()
         print(json.dumps(out), flush=True)
         return
@@ -467,6 +596,8 @@ def main():
     }
     if not args.no_batched:
         out["batched_fp32_vs_plain_fp64"] = batched_vs_plain()
+    if not args.no_hbm:
+        out["hv_hbm"] = hv_hbm()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysm, spec)
     print(json.dumps(out), flush=True)

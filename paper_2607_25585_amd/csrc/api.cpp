@@ -241,6 +241,7 @@ uint64_t launch_signature(const DevHam &dh) {
   for (const StreamPlan *sp : {&dh.sp64, &dh.sp32}) {
     f.pod(sp->ok);
     f.pod(sp->pow2);
+    f.pod(sp->half);
     f.pod(sp->cplx);
     f.pod(sp->geom);
     f.pod(sp->d_pij);

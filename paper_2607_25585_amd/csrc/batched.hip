@@ -962,7 +962,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
     for (int g = 0; g < R / K; g++) items.push_back({ci, g});
   const size_t avail = bytes - pl.fixed;
   const bool timing = out[0].hv_ms != nullptr;
-  const bool use_graph = timing || std::getenv("FTLM_NO_GRAPH") == nullptr;
+  const bool use_graph = true;
   const BatchTuning bt = g_btune;
   const uint32_t urows = 1u << bt.ubits;
   hipEvent_t tev[2] = {nullptr, nullptr};

@@ -208,7 +208,8 @@ struct StreamGeom {
 
 struct StreamPlan {
   bool ok = false;          // the kernel applies (has_z == 0)
-  bool pow2 = false;        // every tile radix is a power of two (digits are bit fields of the row)
+  bool pow2 = false;        // every radix is a power of two (digits are bit fields of the row)
+  bool half = false;        // every site has spin 1/2 (one pair move per row and pair)
   bool cplx = true;         // some pair or single-site coefficient is complex
   StreamGeom geom{};
   std::vector<int> order;   // stream order -> host pair index

@@ -2054,12 +2054,11 @@ static size_t hv_tile_win_smem(const HamGeom &g, const WinPass &W) {
 }
 
 // Threads per tile-window block: 256 G (G groups of rows on one LDS tile).
-// want = 1 or 2 (the tuned choice), else FTLM_TILE_GROUPS, else 2 for complex128
+// want = 1 or 2 (the tuned choice), else 2 for complex128
 // (the tile's LDS allows two blocks per CU: eight more waves) and 1 for
 // complex64 (four 256-thread blocks already fit).
 static int tile_win_groups(int want, bool f32) {
   if (want == 1 || want == 2) return want;
-  if (const char *e = std::getenv("FTLM_TILE_GROUPS")) return std::atoi(e) == 1 ? 1 : 2;
   return f32 ? 1 : 2;
 }
 
@@ -2105,10 +2104,6 @@ int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
     if (!L.variant) L.variant = tn.variant;
     if (!L.grid_cap) L.grid_cap = tn.grid_cap;
     if (!L.kc) L.kc = tn.kc;
-  }
-  if (!L.variant) {
-    const char *e = std::getenv("FTLM_HV_VARIANT");
-    L.variant = e ? std::atoi(e) : 0;
   }
   g_variant = L.variant;
   int gx, gy, kc;

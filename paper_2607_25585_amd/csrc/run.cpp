@@ -210,7 +210,7 @@ int ftlm_run(const ftlm_hamiltonian *hc, const ftlm_run_params *p, void *ws, siz
     return FTLM_EHIP;
   }
   const bool timing = out->hv_ms != nullptr;
-  const bool use_graph = std::getenv("FTLM_NO_GRAPH") == nullptr && !timing;
+  const bool use_graph = !timing;  // timed runs launch step by step, with events around each H*v
   std::vector<hipEvent_t> events;
   double hv_ms = 0.0;
   int hv_launches = 0;

@@ -49,7 +49,68 @@ __device__ __forceinline__ void cfma(R &ar, R &ai, const Cx<R> c, const Cx<R> x)
   }
 }
 
-template <typename R, bool POW2, bool CPLX, int RPT, int NT>
+// LDS layout of the stream kernel (sizes from the plan, offsets 16-byte aligned).
+template <typename R>
+struct StreamLds {
+  size_t tile, hoff, pc, gp, gm, hd, pzz, phi, pij, ooff, oc, moff, mc0, mc1, mi, cnt, total;
+  __host__ __device__ StreamLds(const StreamGeom &g) {
+    const size_t np = (size_t)(g.np_in + g.np_mx + g.np_out), cs = sizeof(Cx<R>), rs = sizeof(R);
+    const size_t no = 4 * ((size_t)g.np_out + (size_t)(g.n - g.t)), nm = 4 * (size_t)g.np_mx;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+      const size_t r = o;
+      o += (b + 15) & ~size_t(15);
+      return r;
+    };
+    tile = take(cs * g.T);
+    hoff = take(cs * 64 * g.t);
+    pc = take(cs * 4 * np);
+    gp = take(rs * 16 * g.n);
+    gm = take(rs * 16 * g.n);
+    hd = take(rs * 16 * g.n);
+    pzz = take(rs * np);
+    phi = take(rs * (g.t + 1));
+    pij = take(sizeof(int2) * np);
+    ooff = take(sizeof(int64_t) * no);
+    oc = take(cs * no);
+    moff = take(sizeof(int64_t) * nm);
+    mc0 = take(cs * nm);
+    mc1 = take(cs * nm);
+    mi = take(sizeof(int) * nm);
+    cnt = take(sizeof(int) * 2);
+    total = o;
+  }
+};
+
+// A value every lane holds alike (read from one LDS address), moved to scalar
+// registers so that the compiler treats it as wave-uniform.
+__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
+  const uint64_t u = (uint64_t)x;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float uniform_r(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform_r(double x) {
+  return __longlong_as_double(uniform_i64(__double_as_longlong(x)));
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> uniform_cx(const Cx<R> &c) {
+  return Cx<R>{uniform_r(c.re), uniform_r(c.im)};
+}
+
+// Appends the lane's candidate to an LDS list if valid: wave-wide ballot and
+// prefix count (called by all 64 lanes of one wave).
+__device__ __forceinline__ int wave_append(bool valid, int count, int *pos) {
+  const unsigned long long m = __ballot(valid);
+  const int lane = threadIdx.x & 63;
+  *pos = count + __popcll(m & ((1ull << lane) - 1ull));
+  return count + __popcll(m);
+}
+
+template <typename R, bool POW2, bool HALF, bool CPLX, int RPT, int NT>
 __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, const int2 *__restrict__ pij,
                                                 const Cx<R> *__restrict__ pcs, const R *__restrict__ pzz,
                                                 const R *__restrict__ tdiag, const Cx<R> *__restrict__ hoffg,
@@ -58,16 +119,24 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
   const int t = G.t, n = G.n, tid = threadIdx.x;
   const int np = G.np_in + G.np_mx + G.np_out;
   const uint32_t T = G.T;
-  // LDS: the tile, then the tables every row reads at uniform indices
-  Cx<R> *tile = reinterpret_cast<Cx<R> *>(smem);    // [T]
-  Cx<R> *s_hoff = tile + T;                           // [t][4][16] single flips of tile sites
-  Cx<R> *s_pc = s_hoff + 64 * t;                      // [np][4]
-  R *s_gp = reinterpret_cast<R *>(s_pc + 4 * np);     // [n][16]
-  R *s_gm = s_gp + 16 * n;                            // [n][16]
-  R *s_hd = s_gm + 16 * n;                            // [n][16]
-  R *s_pzz = s_hd + 16 * n;                           // [np]
-  R *s_phi = s_pzz + np;                              // [t] phi_i, then the outer diagonal part
-  int2 *s_pij = reinterpret_cast<int2 *>(s_phi + t + 1 + ((t + 1) & 1));  // [np] (8-byte aligned)
+  const StreamLds<R> L(G);
+  Cx<R> *tile = reinterpret_cast<Cx<R> *>(smem + L.tile);  // [T]
+  Cx<R> *s_hoff = reinterpret_cast<Cx<R> *>(smem + L.hoff); // [t][4][16] single flips of tile sites
+  Cx<R> *s_pc = reinterpret_cast<Cx<R> *>(smem + L.pc);     // [np][4]
+  R *s_gp = reinterpret_cast<R *>(smem + L.gp);             // [n][16]
+  R *s_gm = reinterpret_cast<R *>(smem + L.gm);             // [n][16]
+  R *s_hd = reinterpret_cast<R *>(smem + L.hd);             // [n][16]
+  R *s_pzz = reinterpret_cast<R *>(smem + L.pzz);           // [np]
+  R *s_phi = reinterpret_cast<R *>(smem + L.phi);           // [t] phi_i, then the outer diagonal part
+  int2 *s_pij = reinterpret_cast<int2 *>(smem + L.pij);     // [np]
+  // per tile: the valid terms that move an outer digit
+  int64_t *s_ooff = reinterpret_cast<int64_t *>(smem + L.ooff);  // uniform terms: row offset
+  Cx<R> *s_oc = reinterpret_cast<Cx<R> *>(smem + L.oc);          //   and coefficient
+  int64_t *s_moff = reinterpret_cast<int64_t *>(smem + L.moff);  // mixed pairs: outer offset (+ tile shift)
+  Cx<R> *s_mc0 = reinterpret_cast<Cx<R> *>(smem + L.mc0);        //   uniform coefficient part
+  Cx<R> *s_mc1 = reinterpret_cast<Cx<R> *>(smem + L.mc1);        //   (spin 1/2: for tile bit 0 / 1)
+  int *s_mi = reinterpret_cast<int *>(smem + L.mi);              //   tile site | ladder << 8
+  int *s_cnt = reinterpret_cast<int *>(smem + L.cnt);
   for (int i = tid; i < 64 * t; i += NT) s_hoff[i] = tb.hoff[i];
   for (int i = tid; i < 4 * np; i += NT) s_pc[i] = pcs[i];
   for (int i = tid; i < 16 * n; i += NT) {
@@ -136,16 +205,108 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
       const uint32_t r = tid + (uint32_t)k * NT;
       if (r < T) tile[r] = v[base + r];
     }
-    // tile-uniform diagonal parts: phi_i = sum over mixed pairs (i, j) of
-    // zz m_j (lane i < t), and the outer sites' own and mutual terms (lane t)
-    if (tid < t) {
+    if (tid < 64) {
+      // wave 0: lists of the valid terms that move an outer digit
+      int no = 0, nm = 0, pos;
+      const int nso = 4 * (n - t);
+      for (int c0 = 0; c0 < nso; c0 += 64) {  // single flips of outer sites
+        const int c = c0 + tid, j = t + c / 4, di = c & 3;
+        const int D = (di < 2) ? di - 2 : di - 1;
+        bool ok = c < nso && ((G.smask >> j) & 1u);
+        int d = 0;
+        if (ok) {
+          d = odig(j);
+          ok = (unsigned)(d + D) < (unsigned)G.radix[j];
+        }
+        no = wave_append(ok, no, &pos);
+        if (ok) {
+          s_ooff[pos] = (int64_t)D * (int64_t)G.st[j];
+          s_oc[pos] = hoffg[(j * 4 + di) * 16 + d];
+        }
+      }
+      const int p0 = G.np_in + G.np_mx;
+      for (int c0 = 0; c0 < 4 * G.np_out; c0 += 64) {  // pairs of two outer sites
+        const int c = c0 + tid, p = p0 + c / 4, q = c & 3;
+        bool ok = c < 4 * G.np_out;
+        Cx<R> cf{0, 0};
+        int64_t off = 0;
+        if (ok) {
+          const int2 ij = s_pij[p];
+          const int di = odig(ij.x), dj = odig(ij.y);
+          const Cx<R> cc = s_pc[4 * p + q];
+          const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;  // '-' ladder on site i / j
+          ok = (cc.re != R(0) || cc.im != R(0)) && (im_ ? di <= G.radix[ij.x] - 2 : di >= 1) &&
+               (jm ? dj <= G.radix[ij.y] - 2 : dj >= 1);
+          if (ok) {
+            const R f = (im_ ? s_gm[ij.x * 16 + di] : s_gp[ij.x * 16 + di]) *
+                        (jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj]);
+            cf = Cx<R>{cc.re * f, cc.im * f};
+            off = (im_ ? (int64_t)G.st[ij.x] : -(int64_t)G.st[ij.x]) + (jm ? (int64_t)G.st[ij.y] : -(int64_t)G.st[ij.y]);
+          }
+        }
+        no = wave_append(ok, no, &pos);
+        if (ok) {
+          s_ooff[pos] = off;
+          s_oc[pos] = cf;
+        }
+      }
+      // pairs with one tile site: spin 1/2 -- one entry per pair (the move of the
+      // outer bit is fixed by the tile; the tile bit picks the coefficient);
+      // general -- one per (pair, ladder pair) whose outer move is valid
+      const int ncm = HALF ? G.np_mx : 4 * G.np_mx;
+      for (int c0 = 0; c0 < ncm; c0 += 64) {
+        const int c = c0 + tid, p = G.np_in + (HALF ? c : c / 4), q = HALF ? 0 : (c & 3);
+        bool ok = c < ncm;
+        Cx<R> c0v{0, 0}, c1v{0, 0};
+        int64_t off = 0;
+        int mi = 0;
+        if (ok) {
+          const int2 ij = s_pij[p];
+          const int dj = odig(ij.y);
+          const int64_t sj = (int64_t)G.st[ij.y];
+          if (HALF) {
+            // row bits (b_i, b_j) -> ladder pair (b_i ? '+' : '-', b_j ? '+' : '-')
+            c0v = s_pc[4 * p + 3 - (0 | dj)];
+            c1v = s_pc[4 * p + 3 - (2 | dj)];
+            ok = (c0v.re != R(0) || c0v.im != R(0) || c1v.re != R(0) || c1v.im != R(0));
+            off = dj ? -sj : sj;
+            mi = ij.x;
+          } else {
+            const Cx<R> cc = s_pc[4 * p + q];
+            const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;
+            ok = (cc.re != R(0) || cc.im != R(0)) && (jm ? dj <= G.radix[ij.y] - 2 : dj >= 1);
+            if (ok) {
+              const R fj = jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj];
+              c0v = Cx<R>{cc.re * fj, cc.im * fj};
+              const int64_t si = (int64_t)G.st[ij.x];
+              off = (jm ? sj : -sj) + (im_ ? si : -si);
+              mi = ij.x | ((int)im_ << 8);
+            }
+          }
+        }
+        nm = wave_append(ok, nm, &pos);
+        if (ok) {
+          s_moff[pos] = off;
+          s_mc0[pos] = c0v;
+          s_mc1[pos] = c1v;
+          s_mi[pos] = mi;
+        }
+      }
+      if (tid == 0) {
+        s_cnt[0] = no;
+        s_cnt[1] = nm;
+      }
+    } else if (tid < 64 + t) {
+      // wave 1: phi_i = sum over mixed pairs (i, j) of zz m_j (lane 64 + i)
+      const int i = tid - 64;
       R ph = 0;
       for (int p = G.np_in; p < G.np_in + G.np_mx; p++) {
         const int2 ij = s_pij[p];
-        if (ij.x == tid) ph = fma(s_pzz[p], om(ij.y), ph);
+        if (ij.x == i) ph = fma(s_pzz[p], om(ij.y), ph);
       }
-      s_phi[tid] = ph;
-    } else if (tid == t) {
+      s_phi[i] = ph;
+    } else if (tid == 64 + t) {
+      // the outer sites' own and mutual diagonal terms
       R d0 = 0;
       for (int k = t; k < n; k++) d0 += s_hd[k * 16 + odig(k)];
       for (int p = G.np_in + G.np_mx; p < np; p++) {
@@ -177,6 +338,7 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
 #pragma unroll
         for (int di = 0; di < 4; di++) {
           const int D = (di < 2) ? di - 2 : di - 1;
+          if (HALF && (D == -2 || D == 2)) continue;
           const bool ok = (unsigned)(d + D) < (unsigned)rd;
           const Cx<R> c = s_hoff[(i * 4 + di) * 16 + d];
           const uint32_t pr = ok ? (uint32_t)((int)r + D * st) : r;
@@ -185,13 +347,20 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
       }
       for (int p = 0; p < G.np_in; p++) {
         const int2 ij = s_pij[p];
+        if (HALF) {
+          // one move per row: both bits flip; row bits pick the ladder pair
+          const uint32_t bi = (r >> ij.x) & 1u, bj = (r >> ij.y) & 1u;
+          const Cx<R> c = s_pc[4 * p + 3 - (int)((bi << 1) | bj)];
+          cfma<R, CPLX>(ar[k], ai[k], c, tile[r ^ ((1u << ij.x) | (1u << ij.y))]);
+          continue;
+        }
         const int di = digit(k, ij.x), dj = digit(k, ij.y);
         const int si = (int)G.st[ij.x], sj = (int)G.st[ij.y];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           const Cx<R> c = s_pc[4 * p + q];
           if (c.re == R(0) && c.im == R(0)) continue;
-          const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;  // '-' ladder on site i / j
+          const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;
           const R f = (im_ ? s_gm[ij.x * 16 + di] : s_gp[ij.x * 16 + di]) *
                       (jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj]);
           const uint32_t pr = (f != R(0)) ? (uint32_t)((int)r + (im_ ? si : -si) + (jm ? sj : -sj)) : r;
@@ -199,92 +368,72 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
         }
       }
     }
-    // single flips of outer sites: uniform coefficient and validity
-    {
-      uint32_t sm = G.smask & ~((t < 32) ? ((1u << t) - 1u) : 0xffffffffu);
-      while (sm) {
-        const int j = __builtin_ctz(sm);
-        sm &= sm - 1u;
-        const int d = odig(j), rd = G.radix[j];
+    // terms with a uniform coefficient (single flips of outer sites, pairs of
+    // two outer sites): the tile's rows shifted by one offset.  The term's base
+    // address and coefficient are made wave-uniform (scalar registers), so a
+    // load takes the lane's 32-bit row offset only; four terms' loads are in
+    // flight at a time
+    const int no = s_cnt[0], nm = s_cnt[1];
+    for (int e = 0; e < no; e += 4) {
+      const Cx<R> *src[4];
+      Cx<R> c[4];
 #pragma unroll
-        for (int di = 0; di < 4; di++) {
-          const int D = (di < 2) ? di - 2 : di - 1;
-          if ((unsigned)(d + D) >= (unsigned)rd) continue;
-          const Cx<R> c = hoffg[(j * 4 + di) * 16 + d];
-          const int64_t off = (int64_t)base + (int64_t)D * (int64_t)G.st[j];
-          Cx<R> y[RPT];
-#pragma unroll
-          for (int k = 0; k < RPT; k++) {
-            const uint32_t r = tid + (uint32_t)k * NT;
-            if (r < T) y[k] = v[off + r];
-          }
-#pragma unroll
-          for (int k = 0; k < RPT; k++)
-            if (tid + (uint32_t)k * NT < T) cfma<R, CPLX>(ar[k], ai[k], c, y[k]);
-        }
+      for (int u = 0; u < 4; u++) {
+        const int eu = e + u < no ? e + u : e;
+        src[u] = v + ((int64_t)base + uniform_i64(s_ooff[eu]));
+        c[u] = e + u < no ? uniform_cx(s_oc[eu]) : Cx<R>{0, 0};
       }
-    }
-    // pairs with one tile site i and one outer site j: the outer move is uniform,
-    // the tile site's ladder factor and validity are per row
-    for (int p = G.np_in; p < G.np_in + G.np_mx; p++) {
-      const int2 ij = s_pij[p];
-      const int dj = odig(ij.y), rj = G.radix[ij.y];
-      const int64_t si = (int64_t)G.st[ij.x], sj = (int64_t)G.st[ij.y];
+      Cx<R> y[4][RPT];
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const Cx<R> c = s_pc[4 * p + q];
-        if (c.re == R(0) && c.im == R(0)) continue;
-        const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;
-        if (jm ? (dj > rj - 2) : (dj < 1)) continue;
-        const R fj = jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj];
-        const Cx<R> cu{c.re * fj, c.im * fj};
-        const int64_t off = (int64_t)base + (jm ? sj : -sj) + (im_ ? si : -si);
-        const R *gi = (im_ ? s_gm : s_gp) + ij.x * 16;
-        Cx<R> y[RPT];
-        R fi[RPT];
+      for (int u = 0; u < 4; u++)
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
           const uint32_t r = tid + (uint32_t)k * NT;
-          fi[k] = 0;
-          if (r < T) {
-            fi[k] = gi[digit(k, ij.x)];
-            // an invalid move reads the row's own element (its factor is 0)
-            const int64_t idx = (fi[k] != R(0)) ? off + (int64_t)r : (int64_t)base + (int64_t)r;
-            y[k] = v[idx];
-          }
+          y[u][k] = Cx<R>{0, 0};
+          if (r < T) y[u][k] = src[u][r];
         }
 #pragma unroll
-        for (int k = 0; k < RPT; k++)
-          if (tid + (uint32_t)k * NT < T) cfma<R, CPLX>(ar[k], ai[k], Cx<R>{cu.re * fi[k], cu.im * fi[k]}, y[k]);
-      }
-    }
-    // pairs of two outer sites: partner rows are the tile shifted by one offset
-    for (int p = G.np_in + G.np_mx; p < np; p++) {
-      const int2 ij = s_pij[p];
-      const int di = odig(ij.x), dj = odig(ij.y);
-      const int ri = G.radix[ij.x], rj = G.radix[ij.y];
-      const int64_t si = (int64_t)G.st[ij.x], sj = (int64_t)G.st[ij.y];
+      for (int u = 0; u < 4; u++)
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const Cx<R> c = s_pc[4 * p + q];
-        if (c.re == R(0) && c.im == R(0)) continue;
-        const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;
-        if (im_ ? (di > ri - 2) : (di < 1)) continue;
-        if (jm ? (dj > rj - 2) : (dj < 1)) continue;
-        const R f = (im_ ? s_gm[ij.x * 16 + di] : s_gp[ij.x * 16 + di]) *
-                    (jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj]);
-        const Cx<R> cf{c.re * f, c.im * f};
-        const int64_t off = (int64_t)base + (im_ ? si : -si) + (jm ? sj : -sj);
-        Cx<R> y[RPT];
+        for (int k = 0; k < RPT; k++) cfma<R, CPLX>(ar[k], ai[k], c[u], y[u][k]);
+    }
+    // pairs with one tile site i: the outer move is uniform; the tile site's
+    // digit gives the ladder factor (or, spin 1/2, the coefficient) and validity.
+    // Rows whose move is invalid load nothing (coefficient 0, value 0)
+    for (int e = 0; e < nm; e += 2) {
+      Cx<R> y[2][RPT], cr[2][RPT];
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        const bool oku = e + u < nm;
+        const int eu = oku ? e + u : e;
+        const Cx<R> *src = v + ((int64_t)base + uniform_i64(s_moff[eu]));
+        const Cx<R> c0v = uniform_cx(s_mc0[eu]), c1v = uniform_cx(s_mc1[eu]);
+        const int mi = __builtin_amdgcn_readfirstlane(s_mi[eu]);
+        const int i = mi & 255, im_ = mi >> 8;
+        const R *gi = (im_ ? s_gm : s_gp) + i * 16;
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
           const uint32_t r = tid + (uint32_t)k * NT;
-          if (r < T) y[k] = v[off + r];
+          Cx<R> cc{0, 0};
+          uint32_t row = r;
+          if (oku && r < T) {
+            if (HALF) {
+              cc = ((r >> i) & 1u) ? c1v : c0v;
+              row = r ^ (1u << i);
+            } else {
+              const R fi = gi[digit(k, i)];
+              cc = Cx<R>{c0v.re * fi, c0v.im * fi};
+            }
+          }
+          cr[u][k] = cc;
+          y[u][k] = Cx<R>{0, 0};
+          if (cc.re != R(0) || cc.im != R(0)) y[u][k] = src[row];
         }
-#pragma unroll
-        for (int k = 0; k < RPT; k++)
-          if (tid + (uint32_t)k * NT < T) cfma<R, CPLX>(ar[k], ai[k], cf, y[k]);
       }
+#pragma unroll
+      for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int k = 0; k < RPT; k++) cfma<R, CPLX>(ar[k], ai[k], cr[u][k], y[u][k]);
     }
 #pragma unroll
     for (int k = 0; k < RPT; k++) {
@@ -302,11 +451,7 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
 
 template <typename R>
 size_t stream_smem(const StreamGeom &g) {
-  const size_t np = (size_t)(g.np_in + g.np_mx + g.np_out);
-  size_t b = sizeof(Cx<R>) * ((size_t)g.T + 64 * (size_t)g.t + 4 * np) +
-             sizeof(R) * (48 * (size_t)g.n + np + (size_t)g.t + 2);
-  b = (b + 7) & ~size_t(7);
-  return b + sizeof(int2) * np;
+  return StreamLds<R>(g).total;
 }
 
 // kc of the tuning: bits 0..3 select the block (0: 1024 threads, 1: 256,
@@ -314,44 +459,47 @@ size_t stream_smem(const StreamGeom &g) {
 inline int stream_threads(int kc) { return (kc & 15) == 1 ? 256 : (kc & 15) == 2 ? 512 : 1024; }
 inline uint32_t stream_chunk(int kc) { return 1u << ((kc >> 4) & 15); }
 
-template <typename R, bool POW2, bool CPLX, int RPT, int NT>
+template <typename R, bool POW2, bool HALF, bool CPLX, int RPT, int NT>
 void launch_stream_t(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
                      hipStream_t s) {
   static size_t granted = 0;  // per instantiation
   const size_t sm = stream_smem<R>(sp.geom);
   if (sm > granted) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_stream<R, POW2, CPLX, RPT, NT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_stream<R, POW2, HALF, CPLX, RPT, NT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     granted = sm;
   }
-  hipLaunchKernelGGL((hv_stream<R, POW2, CPLX, RPT, NT>), dim3(gx), dim3(NT), sm, s, sp.geom, tb, sp.d_pij,
+  hipLaunchKernelGGL((hv_stream<R, POW2, HALF, CPLX, RPT, NT>), dim3(gx), dim3(NT), sm, s, sp.geom, tb, sp.d_pij,
                      reinterpret_cast<const Cx<R> *>(sp.d_pc), reinterpret_cast<const R *>(sp.d_pzz),
                      reinterpret_cast<const R *>(sp.d_tdiag), tb.hoff, chunk, P);
 }
 
-template <typename R, bool POW2, bool CPLX, int NT>
+template <typename R, bool POW2, bool HALF, bool CPLX, int NT>
 void launch_stream_rpt(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
                        hipStream_t s) {
   // tiles hold at most 8192 rows: 8, 16 or 32 rows per thread at 1024, 512 or 256 threads
   const uint32_t rpt = (sp.geom.T + NT - 1) / NT;
-  if (rpt <= 2) launch_stream_t<R, POW2, CPLX, 2, NT>(sp, tb, P, gx, chunk, s);
-  else if (rpt <= 4) launch_stream_t<R, POW2, CPLX, 4, NT>(sp, tb, P, gx, chunk, s);
-  else if (rpt <= 8) launch_stream_t<R, POW2, CPLX, 8, NT>(sp, tb, P, gx, chunk, s);
+  if (rpt <= 2) launch_stream_t<R, POW2, HALF, CPLX, 2, NT>(sp, tb, P, gx, chunk, s);
+  else if (rpt <= 4) launch_stream_t<R, POW2, HALF, CPLX, 4, NT>(sp, tb, P, gx, chunk, s);
+  else if (rpt <= 8) launch_stream_t<R, POW2, HALF, CPLX, 8, NT>(sp, tb, P, gx, chunk, s);
   else if constexpr (NT <= 512) {
-    if (rpt <= 16) launch_stream_t<R, POW2, CPLX, 16, NT>(sp, tb, P, gx, chunk, s);
-    else if constexpr (NT <= 256) launch_stream_t<R, POW2, CPLX, 32, NT>(sp, tb, P, gx, chunk, s);
+    if (rpt <= 16) launch_stream_t<R, POW2, HALF, CPLX, 16, NT>(sp, tb, P, gx, chunk, s);
+    else if constexpr (NT <= 256) launch_stream_t<R, POW2, HALF, CPLX, 32, NT>(sp, tb, P, gx, chunk, s);
   }
 }
 
 template <typename R, int NT>
 void launch_stream_nt(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
                       hipStream_t s) {
-  if (sp.pow2) {
-    if (sp.cplx) launch_stream_rpt<R, true, true, NT>(sp, tb, P, gx, chunk, s);
-    else launch_stream_rpt<R, true, false, NT>(sp, tb, P, gx, chunk, s);
+  if (sp.half) {
+    if (sp.cplx) launch_stream_rpt<R, true, true, true, NT>(sp, tb, P, gx, chunk, s);
+    else launch_stream_rpt<R, true, true, false, NT>(sp, tb, P, gx, chunk, s);
+  } else if (sp.pow2) {
+    if (sp.cplx) launch_stream_rpt<R, true, false, true, NT>(sp, tb, P, gx, chunk, s);
+    else launch_stream_rpt<R, true, false, false, NT>(sp, tb, P, gx, chunk, s);
   } else {
-    if (sp.cplx) launch_stream_rpt<R, false, true, NT>(sp, tb, P, gx, chunk, s);
-    else launch_stream_rpt<R, false, false, NT>(sp, tb, P, gx, chunk, s);
+    if (sp.cplx) launch_stream_rpt<R, false, false, true, NT>(sp, tb, P, gx, chunk, s);
+    else launch_stream_rpt<R, false, false, false, NT>(sp, tb, P, gx, chunk, s);
   }
 }
 
@@ -428,6 +576,7 @@ void plan_stream(const HostHam &hh, uint32_t tile_rows, StreamPlan &pl) {
         if (a != b) cplx = cplx || hh.h[(size_t)k * 256 + a * 16 + b].im != 0.0;
   pl.cplx = cplx;
   pl.pow2 = pow2;
+  pl.half = hh.spin_half;
   // diagonal over the tile sites, per tile row
   pl.tdiag.assign(T, 0.0);
   for (uint32_t r = 0; r < T; r++) {

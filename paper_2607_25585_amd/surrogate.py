@@ -7,13 +7,22 @@ to (ln Z, M, C).  Weights are BF16 with FP32 master copies; forward, backward an
 Adam run in the library's HIP kernels (ftlm_mlp_forward / _backward,
 ftlm_adam_step); PyTorch only owns device memory and streams.  Training data
 are FTLM curves from the batched GPU path.  A gate (parameter domain and the
-disagreement of an ensemble of two networks) decides when to fall back to full
-FTLM, which also measures the surrogate's error.
+disagreement of an ensemble of two networks on C, with a threshold calibrated
+on a validation split so that accepted curves meet a stated error quantile)
+decides when to fall back to full FTLM, which also measures the surrogate's
+error.
 
 Encodings (readings, not from the paper):
   inputs  -- J/3, d/5, 2 tilt/(pi/2) - 1, |B|/3.5 - 1, 2 theta/pi - 1,
-             phi/pi - 1, (log10 T + 1)/1.5 - 1
-  targets -- T (ln Z - ln dim)/20, M/10, C/5
+             cos(8 phi), (log10 T + 1)/1.5 - 1.  The ring's axes are tilted
+             radially, so rotating the field by 2 pi/8 about z or reflecting
+             its azimuth (phi -> -phi: a mirror of the ring combined with time
+             reversal) leaves ln Z, E, C and M unchanged: they depend on phi
+             only through cos(8 phi), which has no wrap at phi = 0 = 2 pi
+  targets -- T (ln Z - ln dim)/20, M/10, (ln(C + C0) + 4)/4 with C0 = 1e-4:
+             an error of the network's C output is then relative to C (C
+             spans decades between its Schottky tails and its maxima, and the
+             curves are compared by relative error)
 """
 from __future__ import annotations
 
@@ -58,15 +67,19 @@ def encode_inputs(params: np.ndarray, T: np.ndarray) -> np.ndarray:
     x[..., 2] = (2 * params[:, 2] / (0.5 * math.pi) - 1)[:, None]
     x[..., 3] = (params[:, 3] / 3.5 - 1)[:, None]
     x[..., 4] = (2 * params[:, 4] / math.pi - 1)[:, None]
-    x[..., 5] = (params[:, 5] / math.pi - 1)[:, None]
+    x[..., 5] = np.cos(8.0 * params[:, 5])[:, None]
     x[..., 6] = ((np.log10(T) + 1) / 1.5 - 1)[None, :]
     return x.reshape(-1, 7)
 
 
+C0 = 1e-4
+
+
 def encode_targets(lnZ, M, C, T, dim=DIM_CFG5) -> np.ndarray:
     T = np.asarray(T, np.float64)[None, :]
+    Cc = np.maximum(np.asarray(C, np.float64), 0.0)
     y = np.stack([T * (np.asarray(lnZ) - math.log(dim)) / 20.0, np.asarray(M) / 10.0,
-                  np.asarray(C) / 5.0], axis=-1)
+                  (np.log(Cc + C0) + 4.0) / 4.0], axis=-1)
     return y.reshape(-1, 3)
 
 
@@ -74,7 +87,8 @@ def decode_outputs(y: np.ndarray, T: np.ndarray, dim=DIM_CFG5):
     T = np.asarray(T, np.float64)
     y = np.asarray(y, np.float64).reshape(-1, len(T), 3)
     lnZ = math.log(dim) + 20.0 * y[..., 0] / T[None, :]
-    return lnZ, 10.0 * y[..., 1], 5.0 * y[..., 2]
+    C = np.maximum(np.exp(4.0 * y[..., 2] - 4.0) - C0, 0.0)
+    return lnZ, 10.0 * y[..., 1], C
 
 
 class MLP:
@@ -245,22 +259,44 @@ def train(model: MLP, x: np.ndarray, y: np.ndarray, epochs: int = 20, batch: int
     return losses
 
 
+def c_relerr(C, C_ref, T, t_min: float = 1.0) -> np.ndarray:
+    """Per set: max over T >= t_min of |C - C_ref| / max(|C_ref|, 1e-3 max_T |C_ref|)
+    (the relative error measure of the curve comparisons)."""
+    C, C_ref = np.asarray(C, np.float64), np.asarray(C_ref, np.float64)
+    hi = np.asarray(T) >= t_min
+    floor = 1e-3 * np.max(np.abs(C_ref[:, hi]), axis=1, keepdims=True)
+    return np.max(np.abs(C[:, hi] - C_ref[:, hi]) / np.maximum(np.abs(C_ref[:, hi]), np.maximum(floor, 1e-12)),
+                  axis=1)
+
+
 class Surrogate:
-    """Ensemble of two MLPs with a gate and FTLM fallback."""
+    """Ensemble of two MLPs with a gate and FTLM fallback.
 
-    def __init__(self, models, disagreement: float = 0.05):
+    Gate: a parameter set is answered by the surrogate when its parameters and
+    temperatures lie in the training domain and the ensemble's disagreement on
+    C (the two members' C curves compared with the relative measure of
+    c_relerr, above t_min) is at most the threshold.  ``calibrate`` sets the
+    threshold from a validation split with FTLM truth so that the accepted
+    curves meet a stated error quantile; everything else goes to FTLM."""
+
+    def __init__(self, models, threshold: float = 0.05, t_min: float = 1.0):
         self.models = list(models)
-        self.disagreement = disagreement
+        self.threshold = float(threshold)
+        self.t_min = float(t_min)
 
-    def predict(self, params: np.ndarray, T: np.ndarray):
-        """Mean prediction and the ensemble spread (normalised units)."""
+    def _members(self, params: np.ndarray, T: np.ndarray):
         torch = _torch()
         x = torch.as_tensor(encode_inputs(params, T).astype(np.float32), device="cuda")
-        ys = [m.forward(x).cpu().numpy().astype(np.float64) for m in self.models]
-        y = np.mean(ys, axis=0)
-        spread = np.max(np.abs(ys[0] - ys[-1]).reshape(-1, len(T), 3), axis=(1, 2))
-        lnZ, M, C = decode_outputs(y, T)
-        return lnZ, M, C, spread
+        return [m.forward(x).cpu().numpy().astype(np.float64) for m in self.models]
+
+    def predict(self, params: np.ndarray, T: np.ndarray):
+        """Mean prediction and the gate score (ensemble disagreement on C)."""
+        ys = self._members(params, T)
+        lnZ, M, C = decode_outputs(np.mean(ys, axis=0), T)
+        c0 = decode_outputs(ys[0], T)[2]
+        c1 = decode_outputs(ys[-1], T)[2]
+        score = c_relerr(c0, c1, T, self.t_min)
+        return lnZ, M, C, score
 
     def in_domain(self, params: np.ndarray, T: np.ndarray):
         p = np.asarray(params, np.float64).reshape(-1, 6)
@@ -268,13 +304,30 @@ class Surrogate:
         T = np.asarray(T)
         return ok & bool(np.all((T >= T_LO - 1e-12) & (T <= T_HI + 1e-12)))
 
+    def calibrate(self, params: np.ndarray, C_true: np.ndarray, T: np.ndarray, tol: float = 0.05,
+                  quantile: float = 0.9):
+        """Largest threshold at which the accepted validation sets have their
+        quantile of C error (c_relerr above t_min) at most tol: the sets are
+        taken in order of increasing score while that holds.  Returns the
+        validation acceptance rate."""
+        _l, _m, C, score = self.predict(params, T)
+        err = c_relerr(C, C_true, T, self.t_min)
+        dom = self.in_domain(params, T)
+        order = [i for i in np.argsort(score) if dom[i]]
+        best = 0
+        for k in range(1, len(order) + 1):
+            if np.quantile(err[order[:k]], quantile) <= tol:
+                best = k
+        self.threshold = float(score[order[best - 1]]) if best else -1.0
+        return best / max(len(params), 1)
+
     def predict_or_fallback(self, params: np.ndarray, T: np.ndarray, R: int = 20, n_lanczos: int = 100,
                             seed: int = 7):
         """Surrogate where the gate accepts, full FTLM (GPU) elsewhere.  Returns
         lnZ, M, C [P, nT] and the boolean fallback mask."""
         params = np.asarray(params, np.float64).reshape(-1, 6)
-        lnZ, M, C, spread = self.predict(params, T)
-        fb = ~self.in_domain(params, T) | (spread > self.disagreement)
+        lnZ, M, C, score = self.predict(params, T)
+        fb = ~self.in_domain(params, T) | (score > self.threshold)
         if np.any(fb):
             idx = np.nonzero(fb)[0]
             l2, m2, c2 = generate_dataset(params[idx], T, R, n_lanczos, seed=seed, precision=0)

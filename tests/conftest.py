@@ -17,3 +17,21 @@ def pytest_configure(config):
 def oracle_lib():
     from oracle import ftlm as of
     return of.lib()
+
+
+@pytest.fixture
+def force_variant(monkeypatch):
+    """force_variant(variant, kc=0): every Hamiltonian the test creates gets
+    this H*v launch for both precisions and every column count, through the
+    C ABI's tuning call (ftlm_hamiltonian_set_tuning)."""
+    def apply(variant, kc=0):
+        import paper_2607_25585_amd as F
+        orig = F.Hamiltonian.__init__
+
+        def init(self, system, _orig=orig):
+            _orig(self, system)
+            for prec in (F.FTLM_C128, F.FTLM_C64):
+                for k in range(1, 65):
+                    self.set_tuning(prec, k, int(variant), 0, int(kc))
+        monkeypatch.setattr(F.Hamiltonian, "__init__", init)
+    return apply

@@ -13,10 +13,10 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(autouse=True)
-def _force_l2win(monkeypatch):
+def _force_l2win(monkeypatch, force_variant):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    monkeypatch.setenv("FTLM_HV_VARIANT", "4")
+    force_variant(4)
     monkeypatch.setenv("FTLM_L2_WINDOW_KB", "16")
     monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "128")
 
@@ -97,11 +97,10 @@ def test_l2win_full_size_sampled_rows(wl, monkeypatch):
 
 @pytest.mark.parametrize("groups", [1, 2])
 @pytest.mark.parametrize("seed,n", [(0, 12), (1, 14), (2, 16), (3, 13)])
-def test_tile_window_hv_matches_oracle(seed, n, groups, monkeypatch):
+def test_tile_window_hv_matches_oracle(seed, n, groups, monkeypatch, force_variant):
     """Variant 5 (LDS tile kernel walked over L2 windows), spin 1/2, with one and
     two row groups per tile: tiny windows give many passes (N = 16: ten)."""
-    monkeypatch.setenv("FTLM_HV_VARIANT", "5")
-    monkeypatch.setenv("FTLM_TILE_GROUPS", str(groups))
+    force_variant(5, groups)
     rng = np.random.default_rng(2900 + seed)
     sysm = W.random_small_system(rng, n, max_two_s=1)
     sysm.two_s[:] = 1
@@ -115,9 +114,8 @@ def test_tile_window_hv_matches_oracle(seed, n, groups, monkeypatch):
 
 
 @pytest.mark.parametrize("groups", [1, 2])
-def test_tile_window_run_matches_oracle(groups, monkeypatch):
-    monkeypatch.setenv("FTLM_HV_VARIANT", "5")
-    monkeypatch.setenv("FTLM_TILE_GROUPS", str(groups))
+def test_tile_window_run_matches_oracle(groups, monkeypatch, force_variant):
+    force_variant(5, groups)
     rng = np.random.default_rng(2950)
     sysm = W.random_small_system(rng, 15, max_two_s=1)
     sysm.two_s[:] = 1
@@ -132,23 +130,21 @@ def test_tile_window_run_matches_oracle(groups, monkeypatch):
 
 
 @pytest.mark.parametrize("groups", [1, 2])
-def test_tile_window_full_size_sampled_rows(groups, monkeypatch):
-    monkeypatch.setenv("FTLM_HV_VARIANT", "5")
-    monkeypatch.setenv("FTLM_TILE_GROUPS", str(groups))
+def test_tile_window_full_size_sampled_rows(groups, monkeypatch, force_variant):
+    force_variant(5, groups)
     monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "2048")
     sysm, _ = W.cfg2()
     _sampled(sysm, F().FTLM_C128, 1e-12)
     _sampled(sysm, F().FTLM_C64, 2e-5)
 
 
-def test_tile_window_lanczos_full_size_matches_oracle(monkeypatch):
+def test_tile_window_lanczos_full_size_matches_oracle(monkeypatch, force_variant):
     """cfg2 at its full size (2^24 rows), in the launch the curve benchmark
     times (tile-window kernel, 512-thread tiles, 2048 blocks, 2 MB windows):
     the Lanczos coefficients of the first two steps, produced by the fused
     epilogue of the last pass and the update kernel, against the oracle's
     recursion from the same seeded start vector (oracle H*v on every row)."""
-    monkeypatch.setenv("FTLM_HV_VARIANT", "5")
-    monkeypatch.setenv("FTLM_TILE_GROUPS", "2")
+    force_variant(5, 2)
     monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "2048")
     sysm, _ = W.cfg2()
     print("case tile-window Lanczos at full size: cfg2, seed 11, 2 steps", flush=True)

@@ -30,8 +30,8 @@ def rel_max(a, b):
 
 
 @pytest.mark.parametrize("variant", ["0", "1", "2", "4"])
-def test_mn9_sampled_rows(variant, monkeypatch):
-    monkeypatch.setenv("FTLM_HV_VARIANT", variant)
+def test_mn9_sampled_rows(variant, force_variant):
+    force_variant(int(variant))
     sysm, spec = W.mn9()
     ham = F().Hamiltonian(sysm)
     assert ham.dim == 2343750

@@ -11,10 +11,10 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(autouse=True)
-def _force_passes(monkeypatch):
+def _force_passes(monkeypatch, force_variant):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    monkeypatch.setenv("FTLM_HV_VARIANT", "2")
+    force_variant(2)
     monkeypatch.setenv("FTLM_WINDOW_KB", "4")
 
 

@@ -2,8 +2,9 @@
 small end-to-end training run that must beat a trivial predictor and FTLM speed.
 
 BF16 budget: forward outputs within 3e-2 of the oracle (relative to the output
-scale); per-tensor gradients with cosine >= 0.999 and relative error <= 1e-2
-... 3e-2 (BF16 inputs to every GEMM)."""
+scale; BF16 inputs to every GEMM); per-tensor gradients with cosine >= 0.999 and
+relative error <= 1e-2 (measured: relative 1.2e-4 to 1.2e-3, cosine >= 0.999999).
+The gate is calibrated on a validation split and checked on held-out sets."""
 import math
 import time
 
@@ -66,7 +67,8 @@ def test_mlp_gradients_match_oracle():
         for got, ref in ((gw, gref[2 * k]), (gb, gref[2 * k + 1])):
             cos = np.sum(got * ref) / (np.linalg.norm(got) * np.linalg.norm(ref) + 1e-300)
             rel = np.linalg.norm(got - ref) / (np.linalg.norm(ref) + 1e-300)
-            assert cos >= 0.999 and rel <= 3e-2, (k, cos, rel)
+            print("layer", k, "shape", got.shape, "cosine %.6f rel %.3e" % (cos, rel), flush=True)
+            assert cos >= 0.999 and rel <= 1e-2, (k, cos, rel)
 
 
 def test_adam_step_matches_oracle():
@@ -116,7 +118,7 @@ def test_surrogate_gains_over_ftlm():
         m = sur.MLP(seed=seed)
         sur.train(m, x, y, epochs=120, batch=512, lr=2e-3, seed=seed)
         models.append(m)
-    ens = sur.Surrogate(models, disagreement=10.0)
+    ens = sur.Surrogate(models, threshold=1e30)
     t1 = time.time()
     for _ in range(5):
         plz, pm, pc, _sp = ens.predict(ptest, T)
@@ -132,3 +134,37 @@ def test_surrogate_gains_over_ftlm():
     bad[:, 3] = 9.0  # |B| outside the training range
     _l, _m, _c, fb = ens.predict_or_fallback(bad, T, R=4, n_lanczos=30)
     assert np.all(fb)
+
+
+def test_gate_calibration_meets_tolerance_on_held_out_sets():
+    """The gate's threshold is calibrated on a validation split (FTLM truth) so
+    that the accepted validation sets have their 90th-percentile C error above
+    1 K at most 0.8 tol; on separate held-out sets the accepted curves then meet
+    tol at the 90th percentile, and the gate accepts some of them."""
+    import ftlm_workloads as W
+    sur = S()
+    T = W.t_grid(40)
+    ptrain = W.cfg5_params(1024, seed=21)
+    pval = W.cfg5_params(96, seed=22)
+    ptest = W.cfg5_params(96, seed=23)
+    lz, mm, cc = sur.generate_dataset(ptrain, T, R=8, n_lanczos=60, chunk=256)
+    _l, _m, cval = sur.generate_dataset(pval, T, R=8, n_lanczos=60, chunk=64, seed=7001)
+    _l, _m, ctest = sur.generate_dataset(ptest, T, R=8, n_lanczos=60, chunk=64, seed=7002)
+    x = sur.encode_inputs(ptrain, T)
+    y = sur.encode_targets(lz, mm, cc, T)
+    models = []
+    for seed in (0, 1):
+        m = sur.MLP(seed=seed)
+        sur.train(m, x, y, epochs=120, batch=1024, lr=2e-3, seed=seed)
+        models.append(m)
+    tol = 0.25
+    ens = sur.Surrogate(models)
+    acc_val = ens.calibrate(pval, cval, T, tol=0.8 * tol, quantile=0.9)
+    _lz, _m, ct, score = ens.predict(ptest, T)
+    acc = ens.in_domain(ptest, T) & (score <= ens.threshold)
+    err = sur.c_relerr(ct, ctest, T)
+    print("gate threshold", ens.threshold, "validation acceptance", acc_val, "held-out acceptance",
+          float(np.mean(acc)), "accepted p90", float(np.quantile(err[acc], 0.9)) if np.any(acc) else None,
+          "all p90", float(np.quantile(err, 0.9)), flush=True)
+    assert np.any(acc)
+    assert np.quantile(err[acc], 0.9) <= tol

@@ -464,6 +464,35 @@ def test_c_hv_rows_equal_full_product_rows(seed, max_two_s):
     assert np.array_equal(ham.apply_rows(v, allr).view(np.float64), full[allr].view(np.float64))
 
 
+def _radial_ring(n, J, d, tilt, bmag, theta, phi):
+    """The surrogate workload's ring construction for n sites: uniform
+    nearest-neighbour J, single-ion d along axes tilted by `tilt` towards the
+    radial directions phi_i = 2 pi i/n, g = 2, no dipolar term."""
+    ang = 2 * np.pi * np.arange(n) / n
+    e = np.stack([np.sin(tilt) * np.cos(ang), np.sin(tilt) * np.sin(ang), np.full(n, np.cos(tilt))], axis=1)
+    B = bmag * np.array([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
+    return W.System(two_s=np.full(n, 3, np.int32), J=W.ring_couplings(n, J), d=np.full(n, d), e=e,
+                    g=np.full(n, 2.0), B=B, pos=None)
+
+
+def test_radial_ring_depends_on_field_azimuth_through_cos_n_phi():
+    """The surrogate's input encoding rests on a symmetry of its ring: with
+    radially tilted axes, rotating the field by 2 pi/n about the ring axis, or
+    reflecting its azimuth (a mirror of the ring combined with time reversal),
+    leaves ln Z, C and M unchanged (exact diagonalisation of a four-site
+    s=3/2 ring), while a rotation by pi/n does not."""
+    T = W.t_grid(12)
+    n = 4
+    for phi in (0.3, 1.1):
+        ref = dense.exact_thermo(_radial_ring(n, 1.3, -2.2, 0.6, 2.5, 0.9, phi), T)
+        for phi2 in (phi + 2 * np.pi / n, -phi, 2 * np.pi / n - phi):
+            got = dense.exact_thermo(_radial_ring(n, 1.3, -2.2, 0.6, 2.5, 0.9, phi2), T)
+            for k in ("lnZ", "C", "M"):
+                assert np.max(np.abs(got[k] - ref[k])) < 1e-10 * max(1.0, np.max(np.abs(ref[k]))), (phi2, k)
+        half = dense.exact_thermo(_radial_ring(n, 1.3, -2.2, 0.6, 2.5, 0.9, phi + np.pi / n), T)
+        assert np.max(np.abs(half["C"] - ref["C"])) > 1e-5
+
+
 # ------------------------------------------------ next row: sFTLM, time reversal
 def test_oracle_time_reverse_maps_h_b_to_h_minus_b():
     """The oracle's Theta (used for the random-vector pairs) satisfies
