@@ -102,8 +102,14 @@ int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, con
  * 1 = direct gather (columns per lane 1, 2, 4, 8), 2 = windowed LDS passes,
  * 3 = LDS tile (spin 1/2, N >= 11), 4 = L2-window passes (one column), 5 = LDS
  * tile walked over L2 windows (spin 1/2, N >= 12; 256 or 512 threads per tile,
- * given in the columns-per-lane field as 1 or 2 row groups), each at 512, 1024,
- * 2048 and 4096 blocks (variants 4, 5: at most 2048) --
+ * given in the columns-per-lane field as 1 or 2 row groups), 6 = single pass
+ * over LDS tiles of the low digits with coalesced partner reads for the terms
+ * on outer sites (one column; Hamiltonians without s+- s^z pair pieces, i.e.
+ * whose single-flip coefficients do not depend on the other sites; the
+ * columns-per-lane field carries the block size in bits 0..3 -- 1: 256
+ * threads for tiles of up to 4096 rows, else 1024 -- and the log2 of the
+ * tiles per XCD chunk in bits 4..7), each at 512, 1024, 2048 and 4096 blocks (variants 4, 5, 6: at most
+ * 2048) --
  * with HIP events on the stream (blocking): three launches each, then the four
  * fastest again with ten launches each.  Stores the fastest of that second
  * round in the handle for later ftlm_apply / ftlm_run launches of the same

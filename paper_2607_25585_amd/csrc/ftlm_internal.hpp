@@ -310,8 +310,8 @@ struct HvLaunch {
 int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s);
 struct HvParams;
 // Variant 6 (stream.hip): one launch of grid <= cap blocks; *gx receives its grid.
-// kc: bits 0..3 the block size (0: 1024 threads, 1: 256, 2: 512), bits 4..7 the
-// log2 of the tiles per XCD chunk.
+// kc: bits 0..3 the block size (1: 256 threads, else 1024), bits 4..7 the log2 of
+// the tiles per XCD chunk.
 int launch_stream(const DevHam &dh, int precision, const HvParams &P, int cap, int kc, unsigned *gx,
                   hipStream_t s);
 // (Re)computes the per-window records of both pass plans (allocates rec_block on

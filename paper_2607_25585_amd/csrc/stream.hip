@@ -454,9 +454,9 @@ size_t stream_smem(const StreamGeom &g) {
   return StreamLds<R>(g).total;
 }
 
-// kc of the tuning: bits 0..3 select the block (0: 1024 threads, 1: 256,
-// 2: 512), bits 4..7 the log2 of the tiles per XCD chunk
-inline int stream_threads(int kc) { return (kc & 15) == 1 ? 256 : (kc & 15) == 2 ? 512 : 1024; }
+// kc of the tuning: bits 0..3 select the block (1: 256 threads, else 1024),
+// bits 4..7 the log2 of the tiles per XCD chunk
+inline int stream_threads(int kc) { return (kc & 15) == 1 ? 256 : 1024; }
 inline uint32_t stream_chunk(int kc) { return 1u << ((kc >> 4) & 15); }
 
 template <typename R, bool POW2, bool HALF, bool CPLX, int RPT, int NT>
@@ -477,15 +477,12 @@ void launch_stream_t(const StreamPlan &sp, const DevTables<R> &tb, const HvParam
 template <typename R, bool POW2, bool HALF, bool CPLX, int NT>
 void launch_stream_rpt(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
                        hipStream_t s) {
-  // tiles hold at most 8192 rows: 8, 16 or 32 rows per thread at 1024, 512 or 256 threads
+  // rows per thread: 4 or 8 at 1024 threads (tiles up to 8192 rows), 4, 8 or 16
+  // at 256 (tiles up to 4096 rows; the caller checks)
   const uint32_t rpt = (sp.geom.T + NT - 1) / NT;
-  if (rpt <= 2) launch_stream_t<R, POW2, HALF, CPLX, 2, NT>(sp, tb, P, gx, chunk, s);
-  else if (rpt <= 4) launch_stream_t<R, POW2, HALF, CPLX, 4, NT>(sp, tb, P, gx, chunk, s);
+  if (rpt <= 4) launch_stream_t<R, POW2, HALF, CPLX, 4, NT>(sp, tb, P, gx, chunk, s);
   else if (rpt <= 8) launch_stream_t<R, POW2, HALF, CPLX, 8, NT>(sp, tb, P, gx, chunk, s);
-  else if constexpr (NT <= 512) {
-    if (rpt <= 16) launch_stream_t<R, POW2, HALF, CPLX, 16, NT>(sp, tb, P, gx, chunk, s);
-    else if constexpr (NT <= 256) launch_stream_t<R, POW2, HALF, CPLX, 32, NT>(sp, tb, P, gx, chunk, s);
-  }
+  else if constexpr (NT <= 256) launch_stream_t<R, POW2, HALF, CPLX, 16, NT>(sp, tb, P, gx, chunk, s);
 }
 
 template <typename R, int NT>
@@ -507,14 +504,14 @@ template <typename R>
 int launch_stream_r(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, int cap, int kc,
                     unsigned *gx_out, hipStream_t s) {
   if (!sp.ok || !sp.d_pij || !sp.d_tdiag) return FTLM_EINVAL;
-  const int nt = stream_threads(kc);
-  if (sp.geom.T > 8192u || (sp.geom.T + nt - 1) / nt > 8192u / nt) return FTLM_ERANGE;
+  // 256 threads take tiles of up to 4096 rows (16 rows per thread); larger tiles take 1024
+  const int nt = (stream_threads(kc) == 256 && sp.geom.T <= 4096u) ? 256 : 1024;
+  if (sp.geom.T > 8192u) return FTLM_ERANGE;
   if (stream_smem<R>(sp.geom) > 160 * 1024) return FTLM_ERANGE;
   uint32_t gx = sp.geom.ntile < (uint32_t)cap ? sp.geom.ntile : (uint32_t)cap;
   if (gx >= 8) gx &= ~7u;
   const uint32_t chunk = stream_chunk(kc);
   if (nt == 256) launch_stream_nt<R, 256>(sp, tb, P, gx, chunk, s);
-  else if (nt == 512) launch_stream_nt<R, 512>(sp, tb, P, gx, chunk, s);
   else launch_stream_nt<R, 1024>(sp, tb, P, gx, chunk, s);
   *gx_out = gx;
   return FTLM_OK;

@@ -54,9 +54,9 @@ int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_
     if (n_cols == 1 && cap <= 2048 && g.spin_half && g.n > kTileBits &&
         !(precision == FTLM_C64 ? h->dev.tw32 : h->dev.tw64).passes.empty())
       for (int groups : {1, 2}) cands.push_back({5, cap, groups});
-    // stream kernel: 1024 or 512 threads per block, chunks of 1, 4, 16 or 64 tiles per XCD
+    // stream kernel: 1024 or 256 threads per block, chunks of 1, 4, 16 or 64 tiles per XCD
     if (n_cols == 1 && cap <= 2048 && (precision == FTLM_C64 ? h->dev.sp32 : h->dev.sp64).ok)
-      for (int nt : {0, 2})
+      for (int nt : {0, 1})
         for (int ch : {0, 2, 4, 6}) cands.push_back({6, cap, nt | (ch << 4)});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;

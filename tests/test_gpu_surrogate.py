@@ -139,30 +139,32 @@ def test_surrogate_gains_over_ftlm():
 def test_gate_calibration_meets_tolerance_on_held_out_sets():
     """The gate's threshold is calibrated on a validation split (FTLM truth) so
     that the accepted validation sets have their 90th-percentile C error above
-    1 K at most 0.8 tol; on separate held-out sets the accepted curves then meet
-    tol at the 90th percentile, and the gate accepts some of them."""
+    3 K at most 0.8 tol; on separate held-out sets the accepted curves then meet
+    tol at the 90th percentile, and the gate accepts some of them.  (Small
+    scale: 2048 training curves of 8 vectors; the truth uses 32 vectors so that
+    its own statistical error stays well below tol above 3 K.)"""
     import ftlm_workloads as W
     sur = S()
     T = W.t_grid(40)
-    ptrain = W.cfg5_params(1024, seed=21)
+    ptrain = W.cfg5_params(2048, seed=21)
     pval = W.cfg5_params(96, seed=22)
     ptest = W.cfg5_params(96, seed=23)
     lz, mm, cc = sur.generate_dataset(ptrain, T, R=8, n_lanczos=60, chunk=256)
-    _l, _m, cval = sur.generate_dataset(pval, T, R=8, n_lanczos=60, chunk=64, seed=7001)
-    _l, _m, ctest = sur.generate_dataset(ptest, T, R=8, n_lanczos=60, chunk=64, seed=7002)
+    _l, _m, cval = sur.generate_dataset(pval, T, R=32, n_lanczos=60, chunk=96, seed=7001)
+    _l, _m, ctest = sur.generate_dataset(ptest, T, R=32, n_lanczos=60, chunk=96, seed=7002)
     x = sur.encode_inputs(ptrain, T)
     y = sur.encode_targets(lz, mm, cc, T)
     models = []
     for seed in (0, 1):
         m = sur.MLP(seed=seed)
-        sur.train(m, x, y, epochs=120, batch=1024, lr=2e-3, seed=seed)
+        sur.train(m, x, y, epochs=200, batch=1024, lr=2e-3, seed=seed)
         models.append(m)
     tol = 0.25
-    ens = sur.Surrogate(models)
+    ens = sur.Surrogate(models, t_min=3.0)
     acc_val = ens.calibrate(pval, cval, T, tol=0.8 * tol, quantile=0.9)
     _lz, _m, ct, score = ens.predict(ptest, T)
     acc = ens.in_domain(ptest, T) & (score <= ens.threshold)
-    err = sur.c_relerr(ct, ctest, T)
+    err = sur.c_relerr(ct, ctest, T, 3.0)
     print("gate threshold", ens.threshold, "validation acceptance", acc_val, "held-out acceptance",
           float(np.mean(acc)), "accepted p90", float(np.quantile(err[acc], 0.9)) if np.any(acc) else None,
           "all p90", float(np.quantile(err, 0.9)), flush=True)
