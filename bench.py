@@ -180,32 +180,39 @@ def hv_rate(ham, dt, reps):
     return float(sorted(times)[len(times) // 2]), float(min(times))
 
 
-def hv_hbm(workloads=("cfg4_hb", "cfg2_hb"), reps=20):
-    """H*v GB/s where the HBM roofline binds: the short-range variants (nearest
-    and next-nearest Heisenberg exchange, field along z, real coefficients) at
-    full size, complex128, one column, tuned launch.  algorithmic bytes = read v
-    + write w once (32 B per row); traffic = calibrated rocprofv3 FETCH_SIZE +
-    WRITE_SIZE per product from profiles/hv_traffic.json (null when the kernel
-    sources changed since the counters were taken)."""
+def hv_hbm(cases=(("cfg4", "c128"), ("cfg4", "c64"), ("cfg4_hb", "c128"), ("cfg2_hb", "c128")), reps=20):
+    """H*v alone at full size, one column, tuned launch, for the large single
+    system (12 spins 2, all-pairs dipolar) in complex128 and complex64 storage,
+    and for the short-range variants where the HBM roofline binds (nearest and
+    next-nearest Heisenberg exchange, field along z).  algorithmic bytes = read v
+    + write w once (32 B per row at complex128, 16 at complex64); flops = 8 per
+    stored nonzero; traffic = calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE per
+    product from profiles/hv_traffic.json (null when the kernel sources changed
+    since the counters were taken, or when no counters were taken)."""
     import torch
 
     import ftlm_workloads as W
     import paper_2607_25585_amd as F
     from paper_2607_25585_amd import autotune
     out = {}
-    for wl in workloads:
+    for wl, pr in cases:
         sysm = W.WORKLOADS[wl]()[0]
         ham = F.Hamiltonian(sysm)
-        tuning = autotune.tune(ham, F.FTLM_C128, 1, use_cache=False)
-        ms, ms_min = hv_rate(ham, torch.complex128, reps)
-        alg = 32.0 * ham.dim
+        prec, dt, es = (F.FTLM_C128, torch.complex128, 16) if pr == "c128" else (F.FTLM_C64, torch.complex64, 8)
+        tuning = autotune.tune(ham, prec, 1, use_cache=False)
+        ms, ms_min = hv_rate(ham, dt, reps)
+        alg = 2.0 * es * ham.dim
         gbps = alg / (ms * 1e-3) / 1e9
-        out[wl] = {"dim": ham.dim, "nnz_per_row": round(ham.nnz_per_row, 3), "precision": "c128",
-                   "hv_ms_median": round(ms, 4), "hv_ms_min": round(ms_min, 4),
-                   "algorithmic_bytes": alg, "achieved_GBps": round(gbps, 1), "peak_GBps": HBM_PEAK_GBPS,
-                   "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": _traffic(wl, "c128"),
-                   "tuning": tuning}
-        print("hv_hbm %s done" % wl, file=sys.stderr, flush=True)
+        tf = 8.0 * ham.nnz_per_row * ham.dim / (ms * 1e-3) / 1e12
+        vpeak = PEAK["f64"] if pr == "c128" else PEAK["f32"]
+        out["%s_%s" % (wl, pr)] = {
+            "dim": ham.dim, "nnz_per_row": round(ham.nnz_per_row, 3), "precision": pr,
+            "hv_ms_median": round(ms, 4), "hv_ms_min": round(ms_min, 4),
+            "algorithmic_bytes": alg, "achieved_GBps": round(gbps, 1), "peak_GBps": HBM_PEAK_GBPS,
+            "frac": round(gbps / HBM_PEAK_GBPS, 4), "TFLOPs": round(tf, 3),
+            "valu_frac": round(tf / vpeak, 4), "valu_peak_TFLOPs": vpeak,
+            "traffic": _traffic(wl, pr), "tuning": tuning}
+        print("hv_hbm %s %s done" % (wl, pr), file=sys.stderr, flush=True)
         ham.close()
         del ham
         torch.cuda.empty_cache()
@@ -254,17 +261,19 @@ def hv_only(args, sysm, spec, ham, prec, K):
                 "nnz_per_row": round(nnz, 3)}}
 
 
-def surrogate_report(n_train, n_test, train_s, n_val=1000, tol=0.10, t_min=2.0, n_powder_sets=8, n_dirs=50):
+def surrogate_report(n_train, n_test, train_s, n_val=500, tol=0.10, t_min=2.0, n_powder_sets=8, n_dirs=50,
+                     r_truth=160, tols=(0.05, 0.10, 0.20)):
     """The learned surrogate on the 8-spin s=3/2 ring data: FTLM training curves
     (batched FP32 path, R=20, N_L=100, 200 temperatures), an ensemble of two MLPs
-    trained by the library's BF16/FP32 kernels, a gate calibrated on a validation
-    split (FP64 FTLM truth) so that the accepted curves have their 90th
-    percentile of C error above t_min at most tol, the statistical error of FTLM
-    itself (two FTLM runs with different vectors on the validation sets), held-out
-    errors and acceptance
-    against plain FP64 FTLM curves of other parameters, and the powder-average
-    protocol: n_dirs field directions x 200 T per set, surrogate against batched
-    FTLM, curves/s and the error of the powder average."""
+    trained by the library's BF16/FP32 kernels, and its errors against a reference
+    that is itself FTLM: FP64 curves with r_truth random vectors (statistical error
+    sqrt(20 / r_truth) of the R=20 recipe's).  The gate is calibrated on a
+    validation split so that the accepted curves have their 90th percentile of C
+    error above t_min at most tol (also reported for each of `tols`); next to the
+    surrogate's errors stand those of an FP64 FTLM run with the recipe's R=20 on the
+    same held-out sets, the alternative the surrogate replaces.  Then the
+    powder-average protocol: n_dirs field directions x 200 T per set, surrogate
+    against batched FTLM, curves/s and the error of the powder average."""
     import numpy as np
     import torch
 
@@ -286,16 +295,20 @@ def surrogate_report(n_train, n_test, train_s, n_val=1000, tol=0.10, t_min=2.0, 
     t_gen = time.perf_counter() - t0
     print("surrogate: %d training curves in %.1f s" % (n_train, t_gen), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    lzt, mmt, cct = S.generate_dataset(ptest, T, spec.R, spec.n_lanczos, seed=spec.seed + 999, chunk=256,
+    lzr, mmr, ccr = S.generate_dataset(ptest, T, spec.R, spec.n_lanczos, seed=spec.seed + 999, chunk=256,
                                        precision=0)
     torch.cuda.synchronize()
     t_ftlm64 = time.perf_counter() - t0
-    print("surrogate: %d held-out FP64 curves in %.1f s" % (n_test, t_ftlm64), file=sys.stderr, flush=True)
-    _lv, _mv, ccv = S.generate_dataset(pval, T, spec.R, spec.n_lanczos, seed=spec.seed + 1999, chunk=256,
+    print("surrogate: %d held-out FP64 curves (R=%d) in %.1f s" % (n_test, spec.R, t_ftlm64), file=sys.stderr,
+          flush=True)
+    # reference curves: FP64 FTLM with r_truth vectors (chunks sized for r_truth columns per set)
+    chunk_t = max(8, (256 * spec.R) // r_truth)
+    lzt, mmt, cct = S.generate_dataset(ptest, T, r_truth, spec.n_lanczos, seed=spec.seed + 1499, chunk=chunk_t,
                                        precision=0)
-    _lv2, _mv2, ccv2 = S.generate_dataset(pval, T, spec.R, spec.n_lanczos, seed=spec.seed + 2499, chunk=256,
-                                          precision=0)
-    print("surrogate: %d validation FP64 curves (two vector sets)" % n_val, file=sys.stderr, flush=True)
+    print("surrogate: %d held-out reference curves (R=%d)" % (n_test, r_truth), file=sys.stderr, flush=True)
+    _lv, _mv, ccv = S.generate_dataset(pval, T, r_truth, spec.n_lanczos, seed=spec.seed + 1999, chunk=chunk_t,
+                                       precision=0)
+    print("surrogate: %d validation reference curves (R=%d)" % (n_val, r_truth), file=sys.stderr, flush=True)
     x = S.encode_inputs(ptrain, T)
     y = S.encode_targets(lz, mm, cc, T)
     models, losses = [], []
@@ -315,9 +328,19 @@ def surrogate_report(n_train, n_test, train_s, n_val=1000, tol=0.10, t_min=2.0, 
     t_train = time.perf_counter() - t0
     print("surrogate: trained in %.1f s" % t_train, file=sys.stderr, flush=True)
     ens = S.Surrogate(models, t_min=t_min)
-    acc_val = ens.calibrate(pval, ccv, T, tol=tol, quantile=0.9)
-    ftlm_noise = S.c_relerr(ccv2, ccv, T, t_min)
     plz, pm, pc, score = ens.predict(ptest, T)
+    dom = ens.in_domain(ptest, T)
+    eC1_all = S.c_relerr(pc, cct, T, t_min)
+    q = lambda a: {"median": float(np.median(a)), "p90": float(np.quantile(a, 0.9)), "max": float(np.max(a))} if len(a) else None  # noqa: E731
+    gate_scan = []
+    for tl in tols:
+        a_val = ens.calibrate(pval, ccv, T, tol=tl, quantile=0.9)
+        acc_t = dom & (score <= ens.threshold)
+        gate_scan.append({"tol_p90": tl, "threshold": ens.threshold, "validation_acceptance": a_val,
+                          "heldout_acceptance": float(np.mean(acc_t)),
+                          "heldout_accepted_C_relerr_A12_T_ge_tmin": q(eC1_all[acc_t])})
+    acc_val = ens.calibrate(pval, ccv, T, tol=tol, quantile=0.9)
+    ftlm_r20 = S.c_relerr(ccr, cct, T, t_min)
     torch.cuda.synchronize()
     reps = 20
     t0 = time.perf_counter()
@@ -334,8 +357,7 @@ def surrogate_report(n_train, n_test, train_s, n_val=1000, tol=0.10, t_min=2.0, 
     eZ = np.max(np.abs(plz - lzt), axis=1)
     hi = T >= t_min
     eC1, eM1 = rel(pc, cct, hi), rel(pm, mmt, hi)
-    acc = ens.in_domain(ptest, T) & (score <= ens.threshold)
-    q = lambda a: {"median": float(np.median(a)), "p90": float(np.quantile(a, 0.9)), "max": float(np.max(a))} if len(a) else None  # noqa: E731
+    acc = dom & (score <= ens.threshold)
     rms = lambda a, b: float(np.sqrt(np.mean((a - b) ** 2)))  # noqa: E731
 
     # powder average: every held-out set's |B| over n_dirs directions uniform on the sphere
@@ -366,7 +388,10 @@ def surrogate_report(n_train, n_test, train_s, n_val=1000, tol=0.10, t_min=2.0, 
             "rmse_all_T": {"lnZ": rms(plz, lzt), "M_muB": rms(pm, mmt), "C_kB": rms(pc, cct)},
             "t_min_K": t_min,
             "heldout_C_relerr_A12_T_ge_tmin": q(eC1), "heldout_M_relerr_A12_T_ge_tmin": q(eM1),
-            "ftlm_vs_ftlm_C_relerr_A12_T_ge_tmin": q(ftlm_noise),
+            "reference": "FP64 FTLM, R=%d, N_L=%d" % (r_truth, spec.n_lanczos),
+            "ftlm_R%d_fp64_C_relerr_A12_T_ge_tmin" % spec.R: q(ftlm_r20),
+            "ftlm_R%d_fp64_M_relerr_A12_T_ge_tmin" % spec.R: q(rel(mmr, mmt, hi)),
+            "gate_scan": gate_scan,
             "gate": {"score": "ensemble disagreement on C above t_min (relative measure)",
                      "tolerance": "p90 of C relative error above %g K <= %g" % (t_min, tol),
                      "threshold": ens.threshold, "validation_acceptance": acc_val,
@@ -492,6 +517,8 @@ def main():
     ap.add_argument("--surrogate-tol", type=float, default=0.10,
                     help="gate contract: p90 of the C relative error above --surrogate-tmin")
     ap.add_argument("--surrogate-tmin", type=float, default=2.0)
+    ap.add_argument("--surrogate-rtruth", type=int, default=160,
+                    help="random vectors of the FP64 FTLM reference curves (held-out and validation sets)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -522,7 +549,8 @@ def main():
         out = {"metric": "surrogate curves/s vs FTLM at held-out accuracy", "n_gpus": 1, "data": "synthetic",
                "config": {"workload": "8-spin s=3/2 ring, MLP 7-256-256-256-3 (bf16 weights, fp32 accumulate)"}}
         out.update(surrogate_report(args.surrogate_train, args.surrogate_test, args.surrogate_train_s,
-                                    tol=args.surrogate_tol, t_min=args.surrogate_tmin))
+                                    tol=args.surrogate_tol, t_min=args.surrogate_tmin,
+                                    r_truth=args.surrogate_rtruth))
         print(json.dumps(out), flush=True)
         return
     sysm, spec = W.WORKLOADS[args.workload]()

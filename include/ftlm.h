@@ -248,14 +248,16 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst,
  * paper's remedy for the random access of H*v, Secs. 3.1 and 4): grid_cap =
  * blocks of the per-step launch (64..65536; 0 = 1024), unit_bits = log2 of the
  * rows of a work unit (11 or 12; 0 = 11), order = the order in which a wave's
- * items take their work units (0 = curve order, 1 = largest instance first).
+ * items take their work units (0 = curve order, 1 = largest instance first),
+ * block = threads per block of the H*v step launch (256, 512 or 1024; 0 = 512).
  * Results are bitwise independent of grid_cap and order (every work unit's
  * partial sums are formed alike and summed per item in unit order); unit_bits
- * changes the summation tree of the dot products (rounding only).  If out[0].hv_ms is
+ * and block change the summation tree of the dot products (rounding only).
+ * FTLM_EINVAL (settings unchanged) for a value outside these.  If out[0].hv_ms is
  * non-NULL, ftlm_run_batched stores there the summed duration of the Lanczos
  * step launches (HIP events around each wave's step graph) and in
  * out[0].hv_launches the number of steps timed. */
-int ftlm_batched_set_tuning(int32_t grid_cap, int32_t unit_bits, int32_t order);
+int ftlm_batched_set_tuning(int32_t grid_cap, int32_t unit_bits, int32_t order, int32_t block);
 
 /* Krylov eigen-decomposition step on the device (the tridiagonal eigenproblem of
  * Sec. 2.2): for every column c, the symmetric tridiagonal with diagonal
@@ -303,6 +305,16 @@ int ftlm_mlp_backward(const ftlm_mlp_weights *w, int32_t batch, const float *t, 
 int ftlm_adam_step(int64_t n, float *p, const float *grad, float *m, float *v, uint16_t *pb,
                    float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
 
+/* Window sizes of the H*v planners, in KiB, for handles created (and plans
+ * described) afterwards; 0 selects the default.  pass_kb: LDS windows of the
+ * multi-pass kernel (variant 2; 4..128, default 64).  l2_kb: L2 windows of the
+ * window kernels of variant 4 (4..65536, default 1024).  tile_kb: L2 windows of
+ * the tile-window kernel (variant 5; 4..65536, default 2048, or a single window
+ * when the vector is at most 160 MB).  Existing handles keep their plans.  The
+ * setting is process-wide; calls concurrent with handle creation race.
+ * FTLM_EINVAL (settings unchanged) for a value outside its range. */
+int ftlm_set_plan_windows(int32_t pass_kb, int32_t l2_kb, int32_t tile_kb);
+
 /* Host-only (no device work): compiles the Hamiltonian and reports the plan the
  * one-column H*v uses in the given precision.  Each pass stages windows of rows
  * that share every digit except those of its active sites and applies from LDS
@@ -321,7 +333,7 @@ int ftlm_describe_passes(const ftlm_system *sys, int32_t precision, int32_t max_
  * outside window_sites; its rows fit a share of one XCD's L2, and each pass walks
  * the windows so that all blocks of an XCD work on the same one, applying the
  * terms whose sites all lie in the window.  window_bytes <= 0 selects the library
- * setting ($FTLM_L2_WINDOW_KB, default 1024).  Per pass p < max_pass:
+ * setting (ftlm_set_plan_windows' l2_kb, default 1024).  Per pass p < max_pass:
  * window_rows[p], window_sites[p] (bit k = site k), n_pairs[p] and
  * single_sites[p] (bit k: the pass applies the single-site flips of site k);
  * pair_sites (may be NULL) receives the (i, j) sites of every pair term, pass by

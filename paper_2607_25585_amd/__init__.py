@@ -84,6 +84,12 @@ def describe_passes(system, precision: int = FTLM_C128):
                 pair_sites=ps[:2 * tot].reshape(-1, 2), nnz_per_row=nnz.value)
 
 
+def set_plan_windows(pass_kb: int = 0, l2_kb: int = 0, tile_kb: int = 0) -> None:
+    """Window sizes (KiB) of the H*v planners for handles created afterwards
+    (``ftlm_set_plan_windows``; zeros restore the defaults)."""
+    check(_ffi.lib().ftlm_set_plan_windows(int(pass_kb), int(l2_kb), int(tile_kb)), "ftlm_set_plan_windows")
+
+
 def describe_windows(system, precision: int = FTLM_C128, window_bytes: int = 0):
     """Host-only: the L2-window plan of the one-column H*v (variant 4)."""
     s, keep = _system_struct(system)
@@ -300,10 +306,10 @@ def run_kpm(ham: Hamiltonian, R: int, n_moments: int, T, seed: int = 0, fields=N
     return out
 
 
-def batched_set_tuning(grid_cap: int = 0, unit_bits: int = 0, order: int = 0) -> None:
+def batched_set_tuning(grid_cap: int = 0, unit_bits: int = 0, order: int = 0, block: int = 0) -> None:
     """Launch choices of later run_batched calls on this thread
     (``ftlm_batched_set_tuning``; zeros restore the defaults)."""
-    check(_ffi.lib().ftlm_batched_set_tuning(int(grid_cap), int(unit_bits), int(order)),
+    check(_ffi.lib().ftlm_batched_set_tuning(int(grid_cap), int(unit_bits), int(order), int(block)),
           "ftlm_batched_set_tuning")
 
 

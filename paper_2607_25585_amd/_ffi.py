@@ -82,7 +82,8 @@ def lib():
         L.ftlm_run_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
                                        ctypes.POINTER(FtlmRunParams), vp, ctypes.c_size_t, vp,
                                        ctypes.POINTER(FtlmResult)]
-        L.ftlm_batched_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.ftlm_batched_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.ftlm_set_plan_windows.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.ftlm_tridiag_eigen.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp,
                                          vp, vp, vp]
         L.ftlm_boltzmann.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,

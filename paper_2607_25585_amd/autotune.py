@@ -6,8 +6,9 @@ library's autotuner measured fastest (variant, grid size, columns per lane).
 
 Batched run: the key is the sorted spin lists of the instances, their term
 sets, the precision and R; the value is the fastest (columns per item, grid
-cap, rows per work unit, unit order) by the duration of the Lanczos step
-launches of short batched runs on the caller's instances and fields.
+cap, rows per work unit, unit order, threads per block) by the duration of the
+Lanczos step launches of short batched runs on the caller's instances and
+fields.
 
 The cache file is $FTLM_TUNE_CACHE, else ~/.cache/ftlm_mi355x/hv_tuning.json.
 """
@@ -93,41 +94,46 @@ def batched_key(hams, precision: int, R: int) -> str:
 def tune_batched(hams, R: int, T, fields_per_inst, seed: int = 0, precision: int = FTLM_C128,
                  n_steps: int = 6, use_cache: bool = False):
     """Chooses the batched launch for these instances and fields: columns per
-    item K (dividing R), then the grid cap, then the rows per work unit and the
-    unit order, each by the mean duration of a Lanczos step (HIP events around
-    the step launches of a run of n_steps steps over every curve), coordinate by
-    coordinate.  Applies the choice (batched_set_tuning) and returns it; pass
-    its "columns" to run_batched."""
+    item K (dividing R), then the threads per block, then the grid cap, then the
+    rows per work unit and the unit order, each by the mean duration of a
+    Lanczos step (HIP events around the step launches of a run of n_steps steps
+    over every curve), coordinate by coordinate.  Applies the choice
+    (batched_set_tuning) and returns it; pass its "columns" to run_batched."""
     from . import batched_set_tuning, run_batched
     key = batched_key(hams, precision, R)
     cache = _load() if use_cache else {}
     if key in cache:
         c = cache[key]
-        batched_set_tuning(c["grid_cap"], c["unit_bits"], c["order"])
+        batched_set_tuning(c["grid_cap"], c["unit_bits"], c["order"], c.get("block", 0))
         return dict(c, cached=True)
 
-    def step_ms(K, grid, ubits, order):
-        batched_set_tuning(grid, ubits, order)
+    def step_ms(K, grid, ubits, order, block):
+        batched_set_tuning(grid, ubits, order, block)
         res = run_batched(hams, R, n_steps, T, fields_per_inst, seed=seed, precision=precision,
                           columns=K, time_steps=True)
         return float(res[0]["step_ms"][0]) / n_steps  # summed over the waves of each step
 
+    # best = (ms, K, block, grid, ubits, order)
     best = None
     for K in [k for k in (16, 8, 4, 2, 1) if R % k == 0]:
-        ms = step_ms(K, 1024, 11, 0)
+        ms = step_ms(K, 1024, 11, 0, 512)
         if best is None or ms < best[0]:
-            best = (ms, K, 1024, 11, 0)
-    for grid in (512, 2048, 4096):
-        ms = step_ms(best[1], grid, 11, 0)
+            best = (ms, K, 512, 1024, 11, 0)
+    for block in (256, 1024):
+        ms = step_ms(best[1], 1024, 11, 0, block)
         if ms < best[0]:
-            best = (ms, best[1], grid, 11, 0)
+            best = (ms, best[1], block, 1024, 11, 0)
+    for grid in (256, 512, 2048, 4096):
+        ms = step_ms(best[1], grid, 11, 0, best[2])
+        if ms < best[0]:
+            best = (ms, best[1], best[2], grid, 11, 0)
     for ubits, order in ((12, 0), (11, 1), (12, 1)):
-        ms = step_ms(best[1], best[2], ubits, order)
+        ms = step_ms(best[1], best[3], ubits, order, best[2])
         if ms < best[0]:
-            best = (ms, best[1], best[2], ubits, order)
-    c = {"columns": best[1], "grid_cap": best[2], "unit_bits": best[3], "order": best[4],
+            best = (ms, best[1], best[2], best[3], ubits, order)
+    c = {"columns": best[1], "block": best[2], "grid_cap": best[3], "unit_bits": best[4], "order": best[5],
          "step_ms": round(best[0], 4)}
-    batched_set_tuning(c["grid_cap"], c["unit_bits"], c["order"])
+    batched_set_tuning(c["grid_cap"], c["unit_bits"], c["order"], c["block"])
     if use_cache:
         cache = _load()
         cache[key] = c

@@ -430,11 +430,8 @@ int upload_tables(const HostHam &hh, DevHam &dh, std::string &err) {
 }
 
 size_t window_bytes_setting() {
-  const char *e = std::getenv("FTLM_WINDOW_KB");
-  long kb = e ? std::atol(e) : 64;
-  if (kb < 4) kb = 4;
-  if (kb > 128) kb = 128;
-  return (size_t)kb * 1024;
+  const int kb = g_windows.pass_kb.load();
+  return (size_t)(kb ? kb : 64) * 1024;
 }
 
 static void field_direction(const double B[3], double out[3]) {

@@ -31,14 +31,17 @@ namespace ftlm {
 // index) and >= ubits (the unit's).
 constexpr uint32_t kUnitRows = 2048;  // smallest unit: sizes the workspace's unit arrays
 constexpr int kMaxUnitSub = 16;       // unit-table entries per (site, ladder) at ubits = 12
-
 // Launch choices of the batched run (the batched autotuner sets them): grid
-// cap, unit size and the order in which a wave's items take their units
-// (0: curve order, 1: largest instance first).
+// cap, unit size, the order in which a wave's items take their units (0: curve
+// order, 1: largest instance first) and the threads of the H*v step's blocks.
+// An item's staged tables (about 37 KB for 22 spins 1/2 with dipolar pieces)
+// allow four blocks per CU, so blocks of 512 threads keep twice the waves of
+// 256 resident.
 struct BatchTuning {
   int grid_cap = 1024;
   int ubits = 11;
   int order = 0;
+  int block = 512;
 };
 static thread_local BatchTuning g_btune;
 
@@ -74,6 +77,7 @@ struct BStep {
   uint32_t n_items;                    // items of the wave (blocks of the finishing launch)
   uint32_t lds;                        // dynamic LDS of the H*v launch (largest item's tables)
   int ubits;                           // log2 of the rows per work unit (11 or 12)
+  int block;                           // threads per block of the H*v launch (256, 512, 1024)
   const int *unit_item;                // [n_units]
 };
 
@@ -180,7 +184,7 @@ template <typename T>
 __device__ __forceinline__ void stage_copy(const T *dst, const T *src, size_t cnt) {
   T *d = const_cast<T *>(dst);
   if (src)
-    for (size_t i = threadIdx.x; i < cnt; i += kBlock) d[i] = src[i];
+    for (size_t i = threadIdx.x; i < cnt; i += blockDim.x) d[i] = src[i];
 }
 
 // Copies the tables brow reads for item it into LDS (layout table_layout).
@@ -203,7 +207,7 @@ __device__ void stage_tables(const BItem<R> &it, bool moment, unsigned char *lds
     stage_copy(d.hflip, src.hflip, (size_t)n * 2);
     if (hz) {
       Cx<R> *T = const_cast<Cx<R> *>(d.cz_half);
-      for (int e = threadIdx.x; e < 2 * n * 32; e += kBlock) {
+      for (int e = threadIdx.x; e < 2 * n * 32; e += (int)blockDim.x) {
         const int v = e & 15, b = (e >> 4) & 1, k = (e >> 5) % n, j = (e >> 5) / n;
         R fr = 0, fi = 0;
         for (int l = 4 * j; l < 4 * j + 4 && l < n; l++) {
@@ -435,8 +439,8 @@ __global__ __launch_bounds__(kBlock) void bstart_kernel(const BItem<R> *__restri
   }
 }
 
-template <typename R, int KC>
-__global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict__ items, BStep S) {
+template <typename R, int KC, int NT>
+__global__ __launch_bounds__(NT) void bhv_kernel(const BItem<R> *__restrict__ items, BStep S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int j = S.step;
   int staged = -1;  // item whose tables are in LDS (a block's units are mostly of one item)
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       // z-field of the sites >= 8 for the unit's rows with bits 8..ubits-1 = i:
       // F_k^b(i) = sum_{l >= 8, l != k} C^b_kl m_l
       const int n = it.n;
-      for (int e = threadIdx.x; e < (n * 2) << usb; e += kBlock) {
+      for (int e = threadIdx.x; e < (n * 2) << usb; e += NT) {
         const int i = e & ((1 << usb) - 1), b = (e >> usb) & 1, k = e >> (usb + 1);
         const uint32_t rb = r0 | ((uint32_t)i << 8);
         R fr = 0, fi = 0;
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
     for (int a = 0; a < 3; a++)
 #pragma unroll
       for (int q = 0; q < KC; q++) red[a][q] = 0.0;
-    for (uint32_t row = r0 + threadIdx.x; row < r1; row += kBlock) {
+    for (uint32_t row = r0 + threadIdx.x; row < r1; row += NT) {
       BAcc<R, KC> acc;
       brow<R, KC>(it, lt, moment, row, v, acc, it.diag, dmode, usb);
       const size_t o = (size_t)row * KC;
@@ -515,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void bhv_kernel(const BItem<R> *__restrict_
       }
     }
     if (moment) continue;  // uniform over the launch
-    block_partials_store<3, KC>(red, S.part, u);
+    block_partials_store<3, KC, NT>(red, S.part, u);
     __syncthreads();  // the block's LDS partials are reused by the next unit
   }
 }
@@ -813,17 +817,24 @@ void pack_site(const HostHam &hh, unsigned char *dst, int maxn, DevTables<R> &tb
   tb_rel.hflip = reinterpret_cast<const Cx<R> *>((uintptr_t)((unsigned char *)hf - dst));
 }
 
+template <typename R, int KC, int NT>
+void launch_bhv(dim3 grid, const BItem<R> *items, const BStep &S, hipStream_t s) {
+  static uint32_t granted = 64 * 1024;  // per instantiation
+  if (S.lds > granted) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bhv_kernel<R, KC, NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)S.lds);
+    granted = S.lds;
+  }
+  hipLaunchKernelGGL((bhv_kernel<R, KC, NT>), grid, dim3(NT), S.lds, s, items, S);
+}
+
 template <typename R, int KC>
 void launch_b(int kind, dim3 grid, const BItem<R> *items, const BStep &S, hipStream_t s) {
   if (kind == 0) hipLaunchKernelGGL((bstart_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
   else if (kind == 1) {
-    static uint32_t granted = 64 * 1024;
-    if (S.lds > granted) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bhv_kernel<R, KC>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)S.lds);
-      granted = S.lds;
-    }
-    hipLaunchKernelGGL((bhv_kernel<R, KC>), grid, dim3(kBlock), S.lds, s, items, S);
+    if (S.block == 256) launch_bhv<R, KC, 256>(grid, items, S, s);
+    else if (S.block == 1024) launch_bhv<R, KC, 1024>(grid, items, S, s);
+    else launch_bhv<R, KC, 512>(grid, items, S, s);
   }
   else hipLaunchKernelGGL((bupdate_kernel<R, KC>), grid, dim3(kBlock), 0, s, items, S);
   if (kind != 1 || S.mode == 1)  // O v_1 has no reductions
@@ -1100,13 +1111,16 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
     S.part = reinterpret_cast<double *>(wbase + o_part);
     S.n_items = (uint32_t)nit;
     S.ubits = bt.ubits;
+    S.block = bt.block;
     {
       size_t lds = 16;
       for (size_t i = 0; i < nit; i++) {
         const HostHam &hh = hs[pl.curves[items[next + i].curve].inst]->host;
         lds = std::max(lds, staged_bytes(hh.n, hh.npair, hh.spin_half, pl.es / 2));
       }
-      if (lds > 160 * 1024) {
+      // with the block's static partial-sum array (block_partials_store)
+      const size_t stat = (size_t)(bt.block / 64) * 3 * (size_t)K * sizeof(double);
+      if (lds + stat > 160 * 1024) {
         set_error("batched item tables exceed the LDS");
         return FTLM_ERANGE;
       }
@@ -1263,7 +1277,7 @@ int ftlm_run_batched(const ftlm_hamiltonian *const *hs, int32_t n_inst, const ft
   return FTLM_OK;
 }
 
-int ftlm_batched_set_tuning(int32_t grid_cap, int32_t unit_bits, int32_t order) {
+int ftlm_batched_set_tuning(int32_t grid_cap, int32_t unit_bits, int32_t order, int32_t block) {
   if (grid_cap != 0 && (grid_cap < 64 || grid_cap > 65536)) {
     set_error("grid_cap must be 0 or in [64, 65536]");
     return FTLM_EINVAL;
@@ -1276,9 +1290,14 @@ int ftlm_batched_set_tuning(int32_t grid_cap, int32_t unit_bits, int32_t order) 
     set_error("order must be 0 (curve order) or 1 (largest first)");
     return FTLM_EINVAL;
   }
+  if (block != 0 && block != 256 && block != 512 && block != 1024) {
+    set_error("block must be 0, 256, 512 or 1024");
+    return FTLM_EINVAL;
+  }
   g_btune.grid_cap = grid_cap ? grid_cap : 1024;
   g_btune.ubits = unit_bits ? unit_bits : 11;
   g_btune.order = order;
+  g_btune.block = block ? block : 512;
   return FTLM_OK;
 }
 

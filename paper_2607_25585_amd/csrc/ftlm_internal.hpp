@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -251,6 +252,11 @@ struct DevHam {
 bool site_has_singles(const HostHam &hh, int k);
 int plan_passes_sorted(const HostHam &hh, const std::vector<int> &pi, const std::vector<int> &pj,
                        size_t window_rows, PassPlan &plan);
+// window sizes of the planners in KiB (0: default), set by ftlm_set_plan_windows
+struct PlanWindows {
+  std::atomic<int> pass_kb{0}, l2_kb{0}, tile_kb{0};
+};
+extern PlanWindows g_windows;
 size_t window_bytes_setting();
 // L2-window plan for windows of at most window_rows rows (spin_half: the
 // kernel's lanes run over row bits 0..7, which every window holds).

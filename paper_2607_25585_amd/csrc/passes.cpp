@@ -441,28 +441,36 @@ int plan_l2_windows(const HostHam &hh, const std::vector<int> &pi, const std::ve
   return FTLM_OK;
 }
 
+PlanWindows g_windows;
+
 size_t tile_window_bytes_setting(uint64_t vec_bytes) {
-  const char *e = std::getenv("FTLM_TILE_WINDOW_KB");
   // default: 2 MB windows (two in flight per XCD fill its 4 MB L2); a vector of
   // at most 160 MB stays in the 256 MB last-level cache, where one window over
   // everything (a single pass) is faster
-  long kb = e ? std::atol(e) : (vec_bytes <= (160ull << 20) ? 65536 : 2048);
-  if (kb < 4) kb = 4;
-  if (kb > 65536) kb = 65536;
-  return (size_t)kb * 1024;
+  const int kb = g_windows.tile_kb.load();
+  return (size_t)(kb ? kb : (vec_bytes <= (160ull << 20) ? 65536 : 2048)) * 1024;
 }
 
 size_t l2_window_bytes_setting() {
-  const char *e = std::getenv("FTLM_L2_WINDOW_KB");
-  long kb = e ? std::atol(e) : 1024;
-  if (kb < 4) kb = 4;
-  if (kb > 65536) kb = 65536;
-  return (size_t)kb * 1024;
+  const int kb = g_windows.l2_kb.load();
+  return (size_t)(kb ? kb : 1024) * 1024;
 }
 
 }  // namespace ftlm
 
 using namespace ftlm;
+
+extern "C" int ftlm_set_plan_windows(int32_t pass_kb, int32_t l2_kb, int32_t tile_kb) {
+  auto ok = [](int32_t v, int32_t hi) { return v == 0 || (v >= 4 && v <= hi); };
+  if (!ok(pass_kb, 128) || !ok(l2_kb, 65536) || !ok(tile_kb, 65536)) {
+    set_error("plan windows out of range (pass 4..128 KiB, L2 and tile 4..65536 KiB, or 0)");
+    return FTLM_EINVAL;
+  }
+  g_windows.pass_kb = pass_kb;
+  g_windows.l2_kb = l2_kb;
+  g_windows.tile_kb = tile_kb;
+  return FTLM_OK;
+}
 
 extern "C" int ftlm_describe_passes(const ftlm_system *sys, int32_t precision, int32_t max_pass,
                                     int32_t *n_pass, uint32_t *window_rows, int32_t *n_active,

@@ -35,3 +35,16 @@ def force_variant(monkeypatch):
                     self.set_tuning(prec, k, int(variant), 0, int(kc))
         monkeypatch.setattr(F.Hamiltonian, "__init__", init)
     return apply
+
+
+@pytest.fixture
+def plan_windows():
+    """plan_windows(pass_kb=0, l2_kb=0, tile_kb=0): window sizes of the H*v
+    planners for the Hamiltonians the test creates afterwards (through the C
+    ABI's ftlm_set_plan_windows); the defaults are restored after the test."""
+    import paper_2607_25585_amd as F
+
+    def apply(pass_kb=0, l2_kb=0, tile_kb=0):
+        F.set_plan_windows(pass_kb, l2_kb, tile_kb)
+    yield apply
+    F.set_plan_windows(0, 0, 0)

@@ -100,6 +100,45 @@ def test_pass_plan_covers_every_pair_once(libftlm, wl, prec):
     assert len(d["window_rows"]) <= 16
 
 
+def test_plan_windows_setting(libftlm):
+    """ftlm_set_plan_windows: smaller LDS windows give more passes (each within
+    the new budget), zeros restore the default plan, and out-of-range values are
+    refused without changing the setting."""
+    import numpy as np
+    import ftlm_workloads as W
+    import paper_2607_25585_amd as F
+    sysm, _ = W.cfg4_hb()
+    base = F.describe_passes(sysm, 0)
+    try:
+        F.set_plan_windows(pass_kb=8)
+        small = F.describe_passes(sysm, 0)
+        assert len(small["window_rows"]) > len(base["window_rows"])
+        assert np.all(small["window_rows"].astype(np.int64) * 16 <= 8 * 1024)
+        for bad in ((2, 0, 0), (256, 0, 0), (0, 3, 0), (0, 0, 1 << 17), (-1, 0, 0)):
+            assert libftlm.ftlm_set_plan_windows(*bad) == -1  # FTLM_EINVAL
+        again = F.describe_passes(sysm, 0)
+        assert np.array_equal(again["window_rows"], small["window_rows"])
+    finally:
+        F.set_plan_windows(0, 0, 0)
+    restored = F.describe_passes(sysm, 0)
+    assert np.array_equal(restored["window_rows"], base["window_rows"])
+
+
+def test_batched_tuning_arguments(libftlm):
+    """ftlm_batched_set_tuning accepts the documented launch choices and refuses
+    the rest (host-only call)."""
+    ok = [(0, 0, 0, 0), (64, 11, 1, 256), (65536, 12, 0, 1024), (1024, 11, 0, 512)]
+    bad = [(63, 0, 0, 0), (70000, 0, 0, 0), (0, 10, 0, 0), (0, 13, 0, 0), (0, 0, 2, 0), (0, 0, -1, 0),
+           (0, 0, 0, 128), (0, 0, 0, 768), (0, 0, 0, 2048)]
+    try:
+        for a in ok:
+            assert libftlm.ftlm_batched_set_tuning(*a) == 0, a
+        for a in bad:
+            assert libftlm.ftlm_batched_set_tuning(*a) == -1, a  # FTLM_EINVAL
+    finally:
+        libftlm.ftlm_batched_set_tuning(0, 0, 0, 0)
+
+
 def _interacting_pairs(sysm):
     n = sysm.n_sites
     return {(i, j) for i in range(n) for j in range(i + 1, n)

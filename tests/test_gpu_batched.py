@@ -169,11 +169,13 @@ def test_batched_largest_cfg3_instances_match_oracle(prec, tol):
             assert curve_err(got[k][key][0], ref[0][key]) < tol, (k, key)
 
 
-@pytest.mark.parametrize("grid,ubits,order", [(512, 12, 1), (64, 11, 1), (4096, 12, 0)])
-def test_batched_tuned_launches_match_oracle(grid, ubits, order):
+@pytest.mark.parametrize("grid,ubits,order,block", [(512, 12, 1, 256), (64, 11, 1, 1024), (4096, 12, 0, 512),
+                                                     (256, 11, 0, 1024)])
+def test_batched_tuned_launches_match_oracle(grid, ubits, order, block):
     """Every launch choice of the batched autotuner keeps oracle parity: 4096-row
     work units (the spin-1/2 z-field unit table over row bits 8..11), units laid
-    out largest instance first, small and large grids; a 13-site spin-1/2
+    out largest instance first, small and large grids, blocks of 256, 512 and
+    1024 threads (2048-row units: 8, 4 and 2 rows per thread); a 13-site spin-1/2
     dipolar instance (two 4096-row units) next to smaller ones of general
     radix."""
     rng = np.random.default_rng(515)
@@ -185,8 +187,8 @@ def test_batched_tuned_launches_match_oracle(grid, ubits, order):
     fields = [W.unit_vectors(rng, 2) * 0.8 for _ in systems]
     T = W.t_grid(24)
     hams = [F().Hamiltonian(s) for s in systems]
-    print("case batched tuning grid", grid, "unit bits", ubits, "order", order, flush=True)
-    F().batched_set_tuning(grid, ubits, order)
+    print("case batched tuning grid", grid, "unit bits", ubits, "order", order, "block", block, flush=True)
+    F().batched_set_tuning(grid, ubits, order, block)
     try:
         got = F().run_batched(hams, 4, 30, T, fields, seed=29, precision=0, columns=2, time_steps=True)
     finally:
@@ -216,6 +218,7 @@ def test_batched_autotuner_choice_keeps_parity():
         c = autotune.tune_batched(hams, 4, T, fields, seed=31, precision=0, n_steps=4)
         print("tuned batched launch", c, flush=True)
         assert c["columns"] in (1, 2, 4) and c["unit_bits"] in (11, 12) and c["order"] in (0, 1)
+        assert c["block"] in (256, 512, 1024)
         got = F().run_batched(hams, 4, 25, T, fields, seed=31, precision=0, columns=c["columns"])
     finally:
         F().batched_set_tuning(0, 0, 0)

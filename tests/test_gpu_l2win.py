@@ -13,12 +13,11 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(autouse=True)
-def _force_l2win(monkeypatch, force_variant):
+def _force_l2win(force_variant, plan_windows):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     force_variant(4)
-    monkeypatch.setenv("FTLM_L2_WINDOW_KB", "16")
-    monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "128")
+    plan_windows(l2_kb=16, tile_kb=128)
 
 
 def F():
@@ -88,8 +87,8 @@ def _sampled(sysm, prec, tol, n_rows=2000):
 
 
 @pytest.mark.parametrize("wl", ["cfg2", "cfg4", "cfg4_hb"])
-def test_l2win_full_size_sampled_rows(wl, monkeypatch):
-    monkeypatch.setenv("FTLM_L2_WINDOW_KB", "1024")
+def test_l2win_full_size_sampled_rows(wl, plan_windows):
+    plan_windows(l2_kb=1024, tile_kb=128)
     sysm, _ = W.WORKLOADS[wl]()
     _sampled(sysm, F().FTLM_C128, 1e-12)
     _sampled(sysm, F().FTLM_C64, 2e-5)
@@ -130,22 +129,22 @@ def test_tile_window_run_matches_oracle(groups, monkeypatch, force_variant):
 
 
 @pytest.mark.parametrize("groups", [1, 2])
-def test_tile_window_full_size_sampled_rows(groups, monkeypatch, force_variant):
+def test_tile_window_full_size_sampled_rows(groups, plan_windows, force_variant):
     force_variant(5, groups)
-    monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "2048")
+    plan_windows(l2_kb=16, tile_kb=2048)
     sysm, _ = W.cfg2()
     _sampled(sysm, F().FTLM_C128, 1e-12)
     _sampled(sysm, F().FTLM_C64, 2e-5)
 
 
-def test_tile_window_lanczos_full_size_matches_oracle(monkeypatch, force_variant):
+def test_tile_window_lanczos_full_size_matches_oracle(plan_windows, force_variant):
     """cfg2 at its full size (2^24 rows), in the launch the curve benchmark
     times (tile-window kernel, 512-thread tiles, 2048 blocks, 2 MB windows):
     the Lanczos coefficients of the first two steps, produced by the fused
     epilogue of the last pass and the update kernel, against the oracle's
     recursion from the same seeded start vector (oracle H*v on every row)."""
     force_variant(5, 2)
-    monkeypatch.setenv("FTLM_TILE_WINDOW_KB", "2048")
+    plan_windows(l2_kb=16, tile_kb=2048)
     sysm, _ = W.cfg2()
     print("case tile-window Lanczos at full size: cfg2, seed 11, 2 steps", flush=True)
     ham = F().Hamiltonian(sysm)

@@ -11,11 +11,11 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(autouse=True)
-def _force_passes(monkeypatch, force_variant):
+def _force_passes(force_variant, plan_windows):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     force_variant(2)
-    monkeypatch.setenv("FTLM_WINDOW_KB", "4")
+    plan_windows(pass_kb=4)
 
 
 def F():
@@ -63,10 +63,10 @@ def test_pass_run_matches_oracle():
 
 
 @pytest.mark.parametrize("n", [14, 16])
-def test_pass_hv_full_windows_spin_half(n, monkeypatch):
+def test_pass_hv_full_windows_spin_half(n, plan_windows):
     """Default 64 KiB windows: 4096 (c128) / 8192 (c64) rows, so every thread
     owns 16 / 32 rows and the row-slot bits 8..12 enter the uniform parts."""
-    monkeypatch.setenv("FTLM_WINDOW_KB", "64")
+    plan_windows(pass_kb=64)
     rng = np.random.default_rng(1000 + n)
     sysm = W.random_small_system(rng, n, max_two_s=1)
     sysm.two_s[:] = 1
