@@ -101,8 +101,8 @@ int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, con
  * the caller's device buffers v, w ([dim][n_cols], as ftlm_apply) -- variants
  * 1 = direct gather (columns per lane 1, 2, 4, 8), 2 = windowed LDS passes,
  * 3 = LDS tile (spin 1/2, N >= 11), 4 = L2-window passes (one column), 5 = LDS
- * tile walked over L2 windows (spin 1/2, N >= 12; 256 or 512 threads per tile,
- * given in the columns-per-lane field as 1 or 2 row groups), 6 = single pass
+ * tile walked over L2 windows (spin 1/2, N >= 12; 256, 512 or 1024 threads per
+ * tile, given in the columns-per-lane field as 1, 2 or 4 row groups), 6 = single pass
  * over LDS tiles of the low digits with coalesced partner reads for the terms
  * on outer sites (one column; Hamiltonians without s+- s^z pair pieces, i.e.
  * whose single-flip coefficients do not depend on the other sites; the

@@ -34,9 +34,8 @@ constexpr int kMaxUnitSub = 16;       // unit-table entries per (site, ladder) a
 // Launch choices of the batched run (the batched autotuner sets them): grid
 // cap, unit size, the order in which a wave's items take their units (0: curve
 // order, 1: largest instance first) and the threads of the H*v step's blocks.
-// An item's staged tables (about 37 KB for 22 spins 1/2 with dipolar pieces)
-// allow four blocks per CU, so blocks of 512 threads keep twice the waves of
-// 256 resident.
+// A block works on one unit at a time, so the block size sets how many of a
+// CU's resident waves share a unit's rows, partner rows and staged tables.
 struct BatchTuning {
   int grid_cap = 1024;
   int ubits = 11;

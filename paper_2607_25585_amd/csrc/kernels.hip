@@ -2054,11 +2054,12 @@ static size_t hv_tile_win_smem(const HamGeom &g, const WinPass &W) {
 }
 
 // Threads per tile-window block: 256 G (G groups of rows on one LDS tile).
-// want = 1 or 2 (the tuned choice), else 2 for complex128
-// (the tile's LDS allows two blocks per CU: eight more waves) and 1 for
-// complex64 (four 256-thread blocks already fit).
+// want = 1, 2 or 4 (the tuned choice), else 2 for complex128 (the tile's LDS
+// allows two blocks per CU, so every doubling of G doubles the resident waves
+// up to 8 per SIMD at G = 4) and 1 for complex64 (four 256-thread blocks
+// already fit).
 static int tile_win_groups(int want, bool f32) {
-  if (want == 1 || want == 2) return want;
+  if (want == 1 || want == 2 || want == 4) return want;
   return f32 ? 1 : 2;
 }
 
@@ -2090,7 +2091,8 @@ static int launch_tile_win(const DevHam &dh, const DevTables<R> &tb, const WinPl
     const size_t sm = hv_tile_win_smem<R>(g, W);
     if (sm > 160 * 1024) return FTLM_ERANGE;
     const dim3 grid(gx, P.K);
-    if (G == 2) launch_tile_win_g<R, 2>(grid, sm, s, g, tb, W, plan.d_plist, pcl, Pp);
+    if (G == 4) launch_tile_win_g<R, 4>(grid, sm, s, g, tb, W, plan.d_plist, pcl, Pp);
+    else if (G == 2) launch_tile_win_g<R, 2>(grid, sm, s, g, tb, W, plan.d_plist, pcl, Pp);
     else launch_tile_win_g<R, 1>(grid, sm, s, g, tb, W, plan.d_plist, pcl, Pp);
     *last_gx = gx;
   }

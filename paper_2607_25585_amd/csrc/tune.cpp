@@ -53,7 +53,7 @@ int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_
     if (n_cols == 1 && cap <= 2048) cands.push_back({4, cap, 0});
     if (n_cols == 1 && cap <= 2048 && g.spin_half && g.n > kTileBits &&
         !(precision == FTLM_C64 ? h->dev.tw32 : h->dev.tw64).passes.empty())
-      for (int groups : {1, 2}) cands.push_back({5, cap, groups});
+      for (int groups : {1, 2, 4}) cands.push_back({5, cap, groups});
     // stream kernel: 1024 or 256 threads per block, chunks of 1, 4, 16 or 64 tiles per XCD
     if (n_cols == 1 && cap <= 2048 && (precision == FTLM_C64 ? h->dev.sp32 : h->dev.sp64).ok)
       for (int nt : {0, 1})

@@ -94,7 +94,7 @@ def test_l2win_full_size_sampled_rows(wl, plan_windows):
     _sampled(sysm, F().FTLM_C64, 2e-5)
 
 
-@pytest.mark.parametrize("groups", [1, 2])
+@pytest.mark.parametrize("groups", [1, 2, 4])
 @pytest.mark.parametrize("seed,n", [(0, 12), (1, 14), (2, 16), (3, 13)])
 def test_tile_window_hv_matches_oracle(seed, n, groups, monkeypatch, force_variant):
     """Variant 5 (LDS tile kernel walked over L2 windows), spin 1/2, with one and
@@ -112,7 +112,7 @@ def test_tile_window_hv_matches_oracle(seed, n, groups, monkeypatch, force_varia
     assert rel_max(w32, oh.apply(v.astype(np.complex64).astype(np.complex128))) < 2e-5
 
 
-@pytest.mark.parametrize("groups", [1, 2])
+@pytest.mark.parametrize("groups", [1, 2, 4])
 def test_tile_window_run_matches_oracle(groups, monkeypatch, force_variant):
     force_variant(5, groups)
     rng = np.random.default_rng(2950)
@@ -128,7 +128,7 @@ def test_tile_window_run_matches_oracle(groups, monkeypatch, force_variant):
         assert err < 1e-8, key
 
 
-@pytest.mark.parametrize("groups", [1, 2])
+@pytest.mark.parametrize("groups", [1, 2, 4])
 def test_tile_window_full_size_sampled_rows(groups, plan_windows, force_variant):
     force_variant(5, groups)
     plan_windows(l2_kb=16, tile_kb=2048)
