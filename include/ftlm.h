@@ -107,8 +107,11 @@ int ftlm_apply(const ftlm_hamiltonian *h, int32_t precision, int32_t n_cols, con
  * on outer sites (one column; Hamiltonians without s+- s^z pair pieces, i.e.
  * whose single-flip coefficients do not depend on the other sites; the
  * columns-per-lane field carries the block size in bits 0..3 -- 1: 256
- * threads for tiles of up to 4096 rows, else 1024 -- and the log2 of the
- * tiles per XCD chunk in bits 4..7), each at 512, 1024, 2048 and 4096 blocks (variants 4, 5, 6: at most
+ * threads for tiles of up to 4096 rows, else 1024 --, the log2 of the
+ * tiles per XCD chunk in bits 4..7, and in bit 8 whether the partner tiles of
+ * the pairs with one tile site are staged in LDS, one per outer site and move,
+ * instead of read directly; not for systems of spins 1/2 only, where a launch
+ * with bit 8 set fails with FTLM_EINVAL), each at 512, 1024, 2048 and 4096 blocks (variants 4, 5, 6: at most
  * 2048) --
  * with HIP events on the stream (blocking): three launches each, then the four
  * fastest again with ten launches each.  Stores the fastest of that second

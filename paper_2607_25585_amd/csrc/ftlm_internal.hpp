@@ -201,6 +201,7 @@ struct StreamGeom {
   int np_in, np_mx, np_out;  // pairs in stream order: both sites < t | i < t <= j | t <= i
   uint32_t T, ntile, dim;   // rows per tile, tiles
   uint32_t smask;           // sites with single-site flips
+  int half;                 // every spin 1/2: one list entry per mixed pair (else four)
   int radix[kMaxSites];
   uint32_t st[kMaxSites];
   int lg[kMaxSites];        // log2 of the stride of a tile site (tile radices all powers of two)
@@ -317,7 +318,7 @@ int launch_hv(const DevHam &dh, const HvLaunch &L, hipStream_t s);
 struct HvParams;
 // Variant 6 (stream.hip): one launch of grid <= cap blocks; *gx receives its grid.
 // kc: bits 0..3 the block size (1: 256 threads, else 1024), bits 4..7 the log2 of
-// the tiles per XCD chunk.
+// the tiles per XCD chunk, bit 8 the LDS staging of the mixed pairs' partner tiles.
 int launch_stream(const DevHam &dh, int precision, const HvParams &P, int cap, int kc, unsigned *gx,
                   hipStream_t s);
 // (Re)computes the per-window records of both pass plans (allocates rec_block on

@@ -14,7 +14,10 @@
 //     given term the partner rows of a tile are the tile's rows shifted by one
 //     offset (plus, for a pair with one tile site, a shift inside the tile), so
 //     the loads are coalesced; their validity and coefficient are uniform over
-//     the tile except for the tile site's ladder factor.
+//     the tile except for the tile site's ladder factor.  Optionally (a launch
+//     choice) the pairs with one tile site are grouped by their outer site and
+//     move: each group's partner tile is staged in LDS once and all the group's
+//     pairs (every tile site, both of its ladder moves) read it from there.
 // Coefficients of invalid moves are zero in the site tables (the ladder factor
 // of a digit that would leave its range is 0), and such a move reads the row's
 // own element instead of an out-of-range one.
@@ -52,10 +55,10 @@ __device__ __forceinline__ void cfma(R &ar, R &ai, const Cx<R> c, const Cx<R> x)
 // LDS layout of the stream kernel (sizes from the plan, offsets 16-byte aligned).
 template <typename R>
 struct StreamLds {
-  size_t tile, hoff, pc, gp, gm, hd, pzz, phi, pij, ooff, oc, moff, mc0, mc1, mi, cnt, total;
-  __host__ __device__ StreamLds(const StreamGeom &g) {
+  size_t tile, hoff, pc, gp, gm, hd, pzz, phi, pij, ooff, oc, moff, mg, mc0, mc1, mi, cnt, ptile, total;
+  __host__ __device__ StreamLds(const StreamGeom &g, bool stage) {
     const size_t np = (size_t)(g.np_in + g.np_mx + g.np_out), cs = sizeof(Cx<R>), rs = sizeof(R);
-    const size_t no = 4 * ((size_t)g.np_out + (size_t)(g.n - g.t)), nm = 4 * (size_t)g.np_mx;
+    const size_t no = 4 * ((size_t)g.np_out + (size_t)(g.n - g.t)), nm = (g.half ? 1 : 4) * (size_t)g.np_mx;
     size_t o = 0;
     auto take = [&](size_t b) {
       const size_t r = o;
@@ -74,10 +77,12 @@ struct StreamLds {
     ooff = take(sizeof(int64_t) * no);
     oc = take(cs * no);
     moff = take(sizeof(int64_t) * nm);
+    mg = take(sizeof(int64_t) * nm);
     mc0 = take(cs * nm);
     mc1 = take(cs * nm);
     mi = take(sizeof(int) * nm);
     cnt = take(sizeof(int) * 2);
+    ptile = stage ? take(cs * g.T) : o;  // partner tile of the staged mixed pairs
     total = o;
   }
 };
@@ -110,7 +115,7 @@ __device__ __forceinline__ int wave_append(bool valid, int count, int *pos) {
   return count + __popcll(m);
 }
 
-template <typename R, bool POW2, bool HALF, bool CPLX, int RPT, int NT>
+template <typename R, bool POW2, bool HALF, bool CPLX, int RPT, int NT, bool STAGE>
 __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, const int2 *__restrict__ pij,
                                                 const Cx<R> *__restrict__ pcs, const R *__restrict__ pzz,
                                                 const R *__restrict__ tdiag, const Cx<R> *__restrict__ hoffg,
@@ -119,7 +124,7 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
   const int t = G.t, n = G.n, tid = threadIdx.x;
   const int np = G.np_in + G.np_mx + G.np_out;
   const uint32_t T = G.T;
-  const StreamLds<R> L(G);
+  const StreamLds<R> L(G, STAGE);
   Cx<R> *tile = reinterpret_cast<Cx<R> *>(smem + L.tile);  // [T]
   Cx<R> *s_hoff = reinterpret_cast<Cx<R> *>(smem + L.hoff); // [t][4][16] single flips of tile sites
   Cx<R> *s_pc = reinterpret_cast<Cx<R> *>(smem + L.pc);     // [np][4]
@@ -133,9 +138,10 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
   int64_t *s_ooff = reinterpret_cast<int64_t *>(smem + L.ooff);  // uniform terms: row offset
   Cx<R> *s_oc = reinterpret_cast<Cx<R> *>(smem + L.oc);          //   and coefficient
   int64_t *s_moff = reinterpret_cast<int64_t *>(smem + L.moff);  // mixed pairs: outer offset (+ tile shift)
+  int64_t *s_mg = reinterpret_cast<int64_t *>(smem + L.mg);      //   outer offset alone (the partner tile)
   Cx<R> *s_mc0 = reinterpret_cast<Cx<R> *>(smem + L.mc0);        //   uniform coefficient part
   Cx<R> *s_mc1 = reinterpret_cast<Cx<R> *>(smem + L.mc1);        //   (spin 1/2: for tile bit 0 / 1)
-  int *s_mi = reinterpret_cast<int *>(smem + L.mi);              //   tile site | ladder << 8
+  int *s_mi = reinterpret_cast<int *>(smem + L.mi);              //   tile site | ladder << 8 | partner tile << 9
   int *s_cnt = reinterpret_cast<int *>(smem + L.cnt);
   for (int i = tid; i < 64 * t; i += NT) s_hoff[i] = tb.hoff[i];
   for (int i = tid; i < 4 * np; i += NT) s_pc[i] = pcs[i];
@@ -252,13 +258,19 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
       }
       // pairs with one tile site: spin 1/2 -- one entry per pair (the move of the
       // outer bit is fixed by the tile; the tile bit picks the coefficient);
-      // general -- one per (pair, ladder pair) whose outer move is valid
+      // general -- one per (pair, ladder pair) whose outer move is valid.  The
+      // mixed pairs are sorted by outer site, and the candidates are taken in
+      // the order (outer ladder, pair, tile ladder), so that the entries that
+      // read the same partner tile (same outer site and move) are consecutive
       const int ncm = HALF ? G.np_mx : 4 * G.np_mx;
       for (int c0 = 0; c0 < ncm; c0 += 64) {
-        const int c = c0 + tid, p = G.np_in + (HALF ? c : c / 4), q = HALF ? 0 : (c & 3);
+        const int c = c0 + tid;
+        const int rem = HALF ? c : c % (2 * G.np_mx);
+        const int p = G.np_in + (HALF ? c : rem / 2);
+        const int q = HALF ? 0 : (((rem & 1) << 1) | (c / (2 * G.np_mx)));
         bool ok = c < ncm;
         Cx<R> c0v{0, 0}, c1v{0, 0};
-        int64_t off = 0;
+        int64_t off = 0, goff = 0;
         int mi = 0;
         if (ok) {
           const int2 ij = s_pij[p];
@@ -270,7 +282,8 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
             c1v = s_pc[4 * p + 3 - (2 | dj)];
             ok = (c0v.re != R(0) || c0v.im != R(0) || c1v.re != R(0) || c1v.im != R(0));
             off = dj ? -sj : sj;
-            mi = ij.x;
+            goff = off;
+            mi = ij.x | (ij.y << 9);
           } else {
             const Cx<R> cc = s_pc[4 * p + q];
             const bool im_ = (q >> 1) != 0, jm = (q & 1) != 0;
@@ -279,14 +292,16 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
               const R fj = jm ? s_gm[ij.y * 16 + dj] : s_gp[ij.y * 16 + dj];
               c0v = Cx<R>{cc.re * fj, cc.im * fj};
               const int64_t si = (int64_t)G.st[ij.x];
-              off = (jm ? sj : -sj) + (im_ ? si : -si);
-              mi = ij.x | ((int)im_ << 8);
+              goff = jm ? sj : -sj;
+              off = goff + (im_ ? si : -si);
+              mi = ij.x | ((int)im_ << 8) | (ij.y << 9) | ((int)jm << 15);
             }
           }
         }
         nm = wave_append(ok, nm, &pos);
         if (ok) {
           s_moff[pos] = off;
+          s_mg[pos] = goff;
           s_mc0[pos] = c0v;
           s_mc1[pos] = c1v;
           s_mi[pos] = mi;
@@ -399,7 +414,51 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
     }
     // pairs with one tile site i: the outer move is uniform; the tile site's
     // digit gives the ladder factor (or, spin 1/2, the coefficient) and validity.
-    // Rows whose move is invalid load nothing (coefficient 0, value 0)
+    if constexpr (STAGE) {
+      // staged: the entries that share a partner tile (same outer site and
+      // move) read it from LDS, staged once with coalesced loads
+      Cx<R> *ptile = reinterpret_cast<Cx<R> *>(smem + L.ptile);
+      for (int e = 0; e < nm;) {
+        const int key = __builtin_amdgcn_readfirstlane(s_mi[e] >> 9);
+        int eend = e + 1;
+        while (eend < nm && (s_mi[eend] >> 9) == key) eend++;
+        eend = __builtin_amdgcn_readfirstlane(eend);
+        const Cx<R> *src = v + ((int64_t)base + uniform_i64(s_mg[e]));
+        __syncthreads();  // the previous partner tile has been read
+#pragma unroll
+        for (int k = 0; k < RPT; k++) {
+          const uint32_t r = tid + (uint32_t)k * NT;
+          if (r < T) ptile[r] = src[r];
+        }
+        __syncthreads();
+        for (; e < eend; e++) {
+          const Cx<R> c0v = uniform_cx(s_mc0[e]), c1v = uniform_cx(s_mc1[e]);
+          const int mi = __builtin_amdgcn_readfirstlane(s_mi[e]);
+          const int i = mi & 255, im_ = (mi >> 8) & 1;
+          const R *gi = (im_ ? s_gm : s_gp) + i * 16;
+          const int sh = im_ ? (int)G.st[i] : -(int)G.st[i];
+#pragma unroll
+          for (int k = 0; k < RPT; k++) {
+            const uint32_t r = tid + (uint32_t)k * NT;
+            if (r >= T) continue;
+            Cx<R> cc;
+            uint32_t idx;
+            if (HALF) {
+              cc = ((r >> i) & 1u) ? c1v : c0v;
+              idx = r ^ (1u << i);
+            } else {
+              // a ladder factor of 0 marks a digit move out of range: read the row itself
+              const R fi = gi[digit(k, i)];
+              cc = Cx<R>{c0v.re * fi, c0v.im * fi};
+              idx = fi != R(0) ? (uint32_t)((int)r + sh) : r;
+            }
+            cfma<R, CPLX>(ar[k], ai[k], cc, ptile[idx]);
+          }
+        }
+      }
+    }
+    // direct: rows whose move is invalid load nothing (coefficient 0, value 0)
+    if constexpr (!STAGE)
     for (int e = 0; e < nm; e += 2) {
       Cx<R> y[2][RPT], cr[2][RPT];
 #pragma unroll
@@ -409,7 +468,7 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
         const Cx<R> *src = v + ((int64_t)base + uniform_i64(s_moff[eu]));
         const Cx<R> c0v = uniform_cx(s_mc0[eu]), c1v = uniform_cx(s_mc1[eu]);
         const int mi = __builtin_amdgcn_readfirstlane(s_mi[eu]);
-        const int i = mi & 255, im_ = mi >> 8;
+        const int i = mi & 255, im_ = (mi >> 8) & 1;
         const R *gi = (im_ ? s_gm : s_gp) + i * 16;
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
@@ -450,53 +509,66 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
 }
 
 template <typename R>
-size_t stream_smem(const StreamGeom &g) {
-  return StreamLds<R>(g).total;
+size_t stream_smem(const StreamGeom &g, bool stage) {
+  return StreamLds<R>(g, stage).total;
 }
 
 // kc of the tuning: bits 0..3 select the block (1: 256 threads, else 1024),
-// bits 4..7 the log2 of the tiles per XCD chunk
+// bits 4..7 the log2 of the tiles per XCD chunk, bit 8 stages the partner
+// tiles of the pairs with one tile site in LDS
 inline int stream_threads(int kc) { return (kc & 15) == 1 ? 256 : 1024; }
 inline uint32_t stream_chunk(int kc) { return 1u << ((kc >> 4) & 15); }
+inline bool stream_stage(int kc) { return ((kc >> 8) & 1) != 0; }
 
-template <typename R, bool POW2, bool HALF, bool CPLX, int RPT, int NT>
+template <typename R, bool POW2, bool HALF, bool CPLX, int RPT, int NT, bool STAGE>
 void launch_stream_t(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
                      hipStream_t s) {
   static size_t granted = 0;  // per instantiation
-  const size_t sm = stream_smem<R>(sp.geom);
+  const size_t sm = stream_smem<R>(sp.geom, STAGE);
   if (sm > granted) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_stream<R, POW2, HALF, CPLX, RPT, NT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&hv_stream<R, POW2, HALF, CPLX, RPT, NT, STAGE>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     granted = sm;
   }
-  hipLaunchKernelGGL((hv_stream<R, POW2, HALF, CPLX, RPT, NT>), dim3(gx), dim3(NT), sm, s, sp.geom, tb, sp.d_pij,
-                     reinterpret_cast<const Cx<R> *>(sp.d_pc), reinterpret_cast<const R *>(sp.d_pzz),
+  hipLaunchKernelGGL((hv_stream<R, POW2, HALF, CPLX, RPT, NT, STAGE>), dim3(gx), dim3(NT), sm, s, sp.geom, tb,
+                     sp.d_pij, reinterpret_cast<const Cx<R> *>(sp.d_pc), reinterpret_cast<const R *>(sp.d_pzz),
                      reinterpret_cast<const R *>(sp.d_tdiag), tb.hoff, chunk, P);
 }
 
-template <typename R, bool POW2, bool HALF, bool CPLX, int NT>
+template <typename R, bool POW2, bool HALF, bool CPLX, int NT, bool STAGE>
 void launch_stream_rpt(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
                        hipStream_t s) {
   // rows per thread: 4 or 8 at 1024 threads (tiles up to 8192 rows), 4, 8 or 16
   // at 256 (tiles up to 4096 rows; the caller checks)
   const uint32_t rpt = (sp.geom.T + NT - 1) / NT;
-  if (rpt <= 4) launch_stream_t<R, POW2, HALF, CPLX, 4, NT>(sp, tb, P, gx, chunk, s);
-  else if (rpt <= 8) launch_stream_t<R, POW2, HALF, CPLX, 8, NT>(sp, tb, P, gx, chunk, s);
-  else if constexpr (NT <= 256) launch_stream_t<R, POW2, HALF, CPLX, 16, NT>(sp, tb, P, gx, chunk, s);
+  if (rpt <= 4) launch_stream_t<R, POW2, HALF, CPLX, 4, NT, STAGE>(sp, tb, P, gx, chunk, s);
+  else if (rpt <= 8) launch_stream_t<R, POW2, HALF, CPLX, 8, NT, STAGE>(sp, tb, P, gx, chunk, s);
+  else if constexpr (NT <= 256) launch_stream_t<R, POW2, HALF, CPLX, 16, NT, STAGE>(sp, tb, P, gx, chunk, s);
 }
 
+// spin-1/2 systems take the direct mixed-pair reads only (the caller checks)
 template <typename R, int NT>
 void launch_stream_nt(const StreamPlan &sp, const DevTables<R> &tb, const HvParams &P, unsigned gx, uint32_t chunk,
-                      hipStream_t s) {
+                      bool stage, hipStream_t s) {
   if (sp.half) {
-    if (sp.cplx) launch_stream_rpt<R, true, true, true, NT>(sp, tb, P, gx, chunk, s);
-    else launch_stream_rpt<R, true, true, false, NT>(sp, tb, P, gx, chunk, s);
+    if (sp.cplx) launch_stream_rpt<R, true, true, true, NT, false>(sp, tb, P, gx, chunk, s);
+    else launch_stream_rpt<R, true, true, false, NT, false>(sp, tb, P, gx, chunk, s);
   } else if (sp.pow2) {
-    if (sp.cplx) launch_stream_rpt<R, true, false, true, NT>(sp, tb, P, gx, chunk, s);
-    else launch_stream_rpt<R, true, false, false, NT>(sp, tb, P, gx, chunk, s);
+    if (stage) {
+      if (sp.cplx) launch_stream_rpt<R, true, false, true, NT, true>(sp, tb, P, gx, chunk, s);
+      else launch_stream_rpt<R, true, false, false, NT, true>(sp, tb, P, gx, chunk, s);
+    } else {
+      if (sp.cplx) launch_stream_rpt<R, true, false, true, NT, false>(sp, tb, P, gx, chunk, s);
+      else launch_stream_rpt<R, true, false, false, NT, false>(sp, tb, P, gx, chunk, s);
+    }
   } else {
-    if (sp.cplx) launch_stream_rpt<R, false, false, true, NT>(sp, tb, P, gx, chunk, s);
-    else launch_stream_rpt<R, false, false, false, NT>(sp, tb, P, gx, chunk, s);
+    if (stage) {
+      if (sp.cplx) launch_stream_rpt<R, false, false, true, NT, true>(sp, tb, P, gx, chunk, s);
+      else launch_stream_rpt<R, false, false, false, NT, true>(sp, tb, P, gx, chunk, s);
+    } else {
+      if (sp.cplx) launch_stream_rpt<R, false, false, true, NT, false>(sp, tb, P, gx, chunk, s);
+      else launch_stream_rpt<R, false, false, false, NT, false>(sp, tb, P, gx, chunk, s);
+    }
   }
 }
 
@@ -507,12 +579,16 @@ int launch_stream_r(const StreamPlan &sp, const DevTables<R> &tb, const HvParams
   // 256 threads take tiles of up to 4096 rows (16 rows per thread); larger tiles take 1024
   const int nt = (stream_threads(kc) == 256 && sp.geom.T <= 4096u) ? 256 : 1024;
   if (sp.geom.T > 8192u) return FTLM_ERANGE;
-  if (stream_smem<R>(sp.geom) > 160 * 1024) return FTLM_ERANGE;
+  // staging serves several pairs per partner tile; spin-1/2 systems have one
+  // move per mixed pair and row and are not staged
+  const bool stage = stream_stage(kc);
+  if (stage && sp.half) return FTLM_EINVAL;
+  if (stream_smem<R>(sp.geom, stage) > 159 * 1024) return FTLM_ERANGE;  // 1 KB for static LDS
   uint32_t gx = sp.geom.ntile < (uint32_t)cap ? sp.geom.ntile : (uint32_t)cap;
   if (gx >= 8) gx &= ~7u;
   const uint32_t chunk = stream_chunk(kc);
-  if (nt == 256) launch_stream_nt<R, 256>(sp, tb, P, gx, chunk, s);
-  else launch_stream_nt<R, 1024>(sp, tb, P, gx, chunk, s);
+  if (nt == 256) launch_stream_nt<R, 256>(sp, tb, P, gx, chunk, stage, s);
+  else launch_stream_nt<R, 1024>(sp, tb, P, gx, chunk, stage, s);
   *gx_out = gx;
   return FTLM_OK;
 }
@@ -559,7 +635,15 @@ void plan_stream(const HostHam &hh, uint32_t tile_rows, StreamPlan &pl) {
   auto cls = [&](int p) { return (hh.pi[p] >= t) + (hh.pj[p] >= t); };
   pl.order.resize(hh.npair);
   for (int p = 0; p < hh.npair; p++) pl.order[p] = p;
-  std::stable_sort(pl.order.begin(), pl.order.end(), [&](int a, int b) { return cls(a) < cls(b); });
+  // classes in the order inside | mixed | outer; the mixed pairs (tile site i <
+  // outer site j) by outer site, so that the pairs sharing a partner tile are
+  // consecutive
+  std::stable_sort(pl.order.begin(), pl.order.end(), [&](int a, int b) {
+    const int ca = cls(a), cb = cls(b);
+    if (ca != cb) return ca < cb;
+    if (ca == 1 && hh.pj[a] != hh.pj[b]) return hh.pj[a] < hh.pj[b];
+    return false;
+  });
   for (int p = 0; p < hh.npair; p++) {
     const int c = cls(p);
     (c == 0 ? g.np_in : c == 1 ? g.np_mx : g.np_out)++;
@@ -574,6 +658,7 @@ void plan_stream(const HostHam &hh, uint32_t tile_rows, StreamPlan &pl) {
   pl.cplx = cplx;
   pl.pow2 = pow2;
   pl.half = hh.spin_half;
+  g.half = hh.spin_half ? 1 : 0;
   // diagonal over the tile sites, per tile row
   pl.tdiag.assign(T, 0.0);
   for (uint32_t r = 0; r < T; r++) {

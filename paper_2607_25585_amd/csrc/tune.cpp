@@ -54,10 +54,12 @@ int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_
     if (n_cols == 1 && cap <= 2048 && g.spin_half && g.n > kTileBits &&
         !(precision == FTLM_C64 ? h->dev.tw32 : h->dev.tw64).passes.empty())
       for (int groups : {1, 2, 4}) cands.push_back({5, cap, groups});
-    // stream kernel: 1024 or 256 threads per block, chunks of 1, 4, 16 or 64 tiles per XCD
+    // stream kernel: 1024 or 256 threads per block, chunks of 1, 4, 16 or 64 tiles per
+    // XCD, the mixed pairs' partner tiles read directly or staged in LDS
     if (n_cols == 1 && cap <= 2048 && (precision == FTLM_C64 ? h->dev.sp32 : h->dev.sp64).ok)
-      for (int nt : {0, 1})
-        for (int ch : {0, 2, 4, 6}) cands.push_back({6, cap, nt | (ch << 4)});
+      for (int st : {0, 1})
+        for (int nt : {0, 1})
+          for (int ch : {0, 2, 4, 6}) cands.push_back({6, cap, nt | (ch << 4) | (st << 8)});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

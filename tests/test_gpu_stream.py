@@ -40,8 +40,10 @@ def curve_err(x, ref):
 
 
 # launch shapes of the stream kernel (the tuning's kc): block of 1024 or 256
-# threads (bits 0..3 = 0 or 1) and 2^(bits 4..7) tiles per XCD chunk
+# threads (bits 0..3 = 0 or 1), 2^(bits 4..7) tiles per XCD chunk, and (bit 8)
+# the mixed pairs' partner tiles staged in LDS (not for systems of spins 1/2)
 SHAPES = [0, 1, 0x40, 0x21, 0x61, 0x60]
+STAGED = [0x100, 0x101, 0x140, 0x161]
 
 
 def _stream_ham(sysm, grid_cap=0, kc=0):
@@ -84,7 +86,7 @@ def test_stream_spin_half_all_pairs(grid_cap, kc):
 
 
 @pytest.mark.parametrize("seed", range(3))
-@pytest.mark.parametrize("kc", [0, 1, 0x41])
+@pytest.mark.parametrize("kc", [0, 1, 0x41] + STAGED)
 def test_stream_spin_two_ring_like(seed, kc):
     """Seven spins 2 (25 tiles of 5^5 rows): general radix, packed digits,
     complex single-ion terms along tilted axes."""
@@ -95,22 +97,37 @@ def test_stream_spin_two_ring_like(seed, kc):
 
 
 @pytest.mark.parametrize("seed", range(4))
-def test_stream_mixed_spins(seed):
+@pytest.mark.parametrize("kc", [0, 0x100])
+def test_stream_mixed_spins(seed, kc):
     rng = np.random.default_rng(80 + seed)
     s = _no_dipolar(rng, 7 if seed < 2 else 9, 5 if seed < 2 else 3, "mixed")
-    _check_full(s, 20 + seed)
+    _check_full(s, 20 + seed, 0, kc)
 
 
 def test_stream_single_tile_and_real_coefficients():
     """A system smaller than one tile (every term from LDS), and an isotropic
     ring in a field along z (real coefficients, no single flips)."""
     rng = np.random.default_rng(90)
-    _check_full(_no_dipolar(rng, 4, 3, "small"), 30)
+    small = _no_dipolar(rng, 4, 3, "small")
+    _check_full(small, 30)
+    _check_full(small, 30, 0, 0x100)
     n = 13
     ring = W.System(two_s=np.ones(n, np.int32), J=W.ring_couplings(n, 1.0, 0.3), d=None,
                     e=np.tile([0.0, 0.0, 1.0], (n, 1)), g=np.full(n, 2.0), B=np.array([0.0, 0.0, 0.7]),
                     pos=None, name="ring13")
     _check_full(ring, 31)
+
+
+def test_stream_staging_refused_for_spin_half():
+    """Spin-1/2 systems have one move per mixed pair and row, so the staged
+    launch is refused (FTLM_EINVAL) rather than run."""
+    rng = np.random.default_rng(92)
+    s = _no_dipolar(rng, 14, 1, "half14")
+    s.two_s[:] = 1
+    ham = _stream_ham(s, 0, 0x100)
+    v = torch.ones(ham.dim, dtype=torch.complex128, device="cuda")
+    with pytest.raises(RuntimeError, match="status -1"):
+        ham.apply(v)
 
 
 def test_stream_refuses_row_dependent_single_flips():
@@ -148,10 +165,14 @@ def test_stream_full_size_sampled_rows(which):
     _sampled(sysm, F().FTLM_C128, 1e-12)
     _sampled(sysm, F().FTLM_C64, 2e-5)
     _sampled(sysm, F().FTLM_C128, 1e-12, kc=0x42, grid_cap=1024)
+    if which != "cfg2_hb":  # staged launches: not for spins 1/2
+        _sampled(sysm, F().FTLM_C128, 1e-12, kc=0x100, grid_cap=1024)
+        _sampled(sysm, F().FTLM_C64, 2e-5, kc=0x100)
 
 
-@pytest.mark.parametrize("which,prec,tol", [("half14", 0, 1e-8), ("s2x6", 0, 1e-8), ("s2x6", 1, 1e-3)])
-def test_stream_lanczos_run_matches_oracle(which, prec, tol):
+@pytest.mark.parametrize("which,prec,tol,kc", [("half14", 0, 1e-8, 0), ("s2x6", 0, 1e-8, 0), ("s2x6", 1, 1e-3, 0),
+                                                ("s2x6", 0, 1e-8, 0x100), ("s2x6", 1, 1e-3, 0x100)])
+def test_stream_lanczos_run_matches_oracle(which, prec, tol, kc):
     """The fused Lanczos epilogue of the stream kernel inside ftlm_run."""
     rng = np.random.default_rng(95)
     if which == "half14":
@@ -160,7 +181,7 @@ def test_stream_lanczos_run_matches_oracle(which, prec, tol):
     else:
         s = _no_dipolar(rng, 6, 4, which)
         s.two_s[:] = 4
-    ham = _stream_ham(s)
+    ham = _stream_ham(s, 0, kc)
     T = W.t_grid(30)
     got = F().run(ham, 2, 40, T, seed=12, columns=1, precision=prec)
     ref = of.ftlm(s, 2, 40, T, seed=12)[0]
