@@ -202,6 +202,8 @@ struct StreamGeom {
   uint32_t T, ntile, dim;   // rows per tile, tiles
   uint32_t smask;           // sites with single-site flips
   int half;                 // every spin 1/2: one list entry per mixed pair (else four)
+  uint64_t gmask;           // bit 2 j + m: a mixed pair (i, j) has a nonzero coefficient whose
+                            // move of j is +stride (m = 1) or -stride (m = 0)
   int radix[kMaxSites];
   uint32_t st[kMaxSites];
   int lg[kMaxSites];        // log2 of the stride of a tile site (tile radices all powers of two)

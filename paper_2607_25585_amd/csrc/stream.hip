@@ -219,6 +219,9 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
         const int c = c0 + tid, j = t + c / 4, di = c & 3;
         const int D = (di < 2) ? di - 2 : di - 1;
         bool ok = c < nso && ((G.smask >> j) & 1u);
+        // staged: a move by one step whose partner tile a staged group reads
+        // (same outer site and move) is applied with that group instead
+        if (STAGE && (D == 1 || D == -1) && ((G.gmask >> (2 * j + (D > 0))) & 1ull)) ok = false;
         int d = 0;
         if (ok) {
           d = odig(j);
@@ -431,6 +434,20 @@ __global__ __launch_bounds__(NT) void hv_stream(StreamGeom G, DevTables<R> tb, c
           if (r < T) ptile[r] = src[r];
         }
         __syncthreads();
+        {
+          // the single flip of the group's outer site by the same move (a step of
+          // +1 for a move of +stride), if the site has single flips: left out of
+          // the uniform list, it reads the staged tile's own rows
+          const int j = key & 63, m = (key >> 6) & 1;
+          if ((G.smask >> j) & 1u) {
+            const Cx<R> cs1 = uniform_cx(hoffg[(j * 4 + (m ? 2 : 1)) * 16 + odig(j)]);
+#pragma unroll
+            for (int k = 0; k < RPT; k++) {
+              const uint32_t r = tid + (uint32_t)k * NT;
+              if (r < T) cfma<R, CPLX>(ar[k], ai[k], cs1, ptile[r]);
+            }
+          }
+        }
         for (; e < eend; e++) {
           const Cx<R> c0v = uniform_cx(s_mc0[e]), c1v = uniform_cx(s_mc1[e]);
           const int mi = __builtin_amdgcn_readfirstlane(s_mi[e]);
@@ -659,6 +676,11 @@ void plan_stream(const HostHam &hh, uint32_t tile_rows, StreamPlan &pl) {
   pl.pow2 = pow2;
   pl.half = hh.spin_half;
   g.half = hh.spin_half ? 1 : 0;
+  g.gmask = 0;
+  for (int p = 0; p < hh.npair; p++)
+    if (cls(p) == 1)
+      for (int q = 0; q < 4; q++)
+        if (hh.pc[4 * p + q].re != 0.0 || hh.pc[4 * p + q].im != 0.0) g.gmask |= 1ull << (2 * hh.pj[p] + (q & 1));
   // diagonal over the tile sites, per tile row
   pl.tdiag.assign(T, 0.0);
   for (uint32_t r = 0; r < T; r++) {
