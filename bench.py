@@ -78,10 +78,23 @@ def cpu_baseline(sysm, spec, budget_s=12.0):
     t_hv = float(np.median(times))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / (spec.R * spec.n_lanczos * t_hv), "unit": "curves/s",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "kind": "oracle", "cpu_model": _cpu_model(),
+            "cpus_visible": os.cpu_count(),
             "sample": "%d oracle H*v products on one column (%.2f s each, median), "
                       "extrapolated x R*N_L = %d per curve" % (len(times), t_hv,
                                                                spec.R * spec.n_lanczos)}
+
+
+def _cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def curve_err(x, ref):
@@ -155,6 +168,91 @@ def batched_vs_plain(n_dirs=4, tune=True, tune_cache=None):
             "plain_fp64_curves_per_s": round(n_curves / t_p, 4),
             "speedup": round(t_p / t_b, 3), "max_C_err_vs_plain_fp64": err_c,
             "max_M_err_vs_plain_fp64": err_m, "C_within_1e-3": bool(err_c <= 1e-3)}
+
+
+def cfg3_full(mode, first, last, save, group=8, tune_cache=None):
+    """The whole 64-instance batched workload (50 field directions, R = 16,
+    N_L = 120, 200 temperatures) or instances [first, last) of it: batched
+    FP32 storage (one run_batched call per group of instances, each instance
+    drawing its own random vectors, so the groups give the curves of one run)
+    or plain FP64 (one run per instance, all its directions), timed from the
+    first call to the last with the Hamiltonians compiled beforehand.  The
+    batched launch is the batched autotuner's choice on the stratified subset
+    (one instance per spin count, 4 directions), tuned outside the timed
+    region.  Saves every curve (ln Z, E, C, M) to `save` (npz) for
+    cfg3_compare."""
+    import numpy as np
+    import torch
+
+    import ftlm_workloads as W
+    import paper_2607_25585_amd as F
+    systems, spec, fields = W.cfg3()
+    idx = list(range(first, last))
+    hams = [F.Hamiltonian(systems[k]) for k in idx]
+    btune = None
+    if mode == "batched":
+        from paper_2607_25585_amd import autotune
+        if tune_cache:
+            os.environ["FTLM_TUNE_CACHE"] = tune_cache
+        pick = stratified_cfg3(systems)
+        th = [F.Hamiltonian(systems[k]) for k in pick]
+        btune = autotune.tune_batched(th, spec.R, spec.T, [fields[k][:4] for k in pick], seed=spec.seed,
+                                      precision=F.FTLM_C64, use_cache=bool(tune_cache))
+        for h in th:
+            h.close()
+        print("batched autotune done", btune, file=sys.stderr, flush=True)
+        F.run_batched(hams[:1], spec.R, 4, spec.T, [fields[idx[0]][:1]], seed=spec.seed, precision=F.FTLM_C64)
+    else:
+        F.run(hams[0], spec.R, 4, spec.T, seed=spec.seed, fields=fields[idx[0]][:1])
+    torch.cuda.synchronize()
+    out = {kk: np.zeros((len(idx), fields.shape[1], len(spec.T))) for kk in ("lnZ", "E", "C", "M")}
+    t0 = time.perf_counter()
+    if mode == "batched":
+        for g0 in range(0, len(idx), group):
+            res = F.run_batched(hams[g0:g0 + group], spec.R, spec.n_lanczos, spec.T,
+                                [fields[k] for k in idx[g0:g0 + group]], seed=spec.seed, precision=F.FTLM_C64,
+                                columns=btune["columns"], instance0=idx[g0])
+            for j, r in enumerate(res):
+                for kk in out:
+                    out[kk][g0 + j] = r[kk]
+            print("batched instances %d..%d done (%.1f s)" % (idx[g0], idx[min(g0 + group, len(idx)) - 1],
+                                                              time.perf_counter() - t0), file=sys.stderr, flush=True)
+        F.batched_set_tuning(0, 0, 0)
+    else:
+        for j, k in enumerate(idx):
+            r = F.run(hams[j], spec.R, spec.n_lanczos, spec.T, seed=spec.seed, fields=fields[k], instance=k)
+            for kk in out:
+                out[kk][j] = r[kk]
+            print("plain instance %d done (%.1f s)" % (k, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    np.savez(save, instances=np.array(idx), **out)
+    n_curves = len(idx) * fields.shape[1]
+    return {"mode": mode, "instances": [first, last], "curves": n_curves, "seconds": round(dt, 2),
+            "curves_per_s": round(n_curves / dt, 4), "batched_tuning": btune,
+            "spins": [systems[k].n_sites for k in idx]}
+
+
+def cfg3_compare(batched_file, plain_files):
+    """Accuracy gate of the whole batched workload: every batched FP32 curve
+    against the plain FP64 curve of the same instance, direction and random
+    vectors; max over T of the relative C and M error (floor 1e-3 of the
+    curve's maximum)."""
+    import numpy as np
+    b = np.load(batched_file)
+    bi = {int(k): j for j, k in enumerate(b["instances"])}
+    ec, em = [], []
+    for f in plain_files:
+        p = np.load(f)
+        for j, k in enumerate(p["instances"]):
+            jb = bi[int(k)]
+            for d in range(p["C"].shape[1]):
+                ec.append(curve_err(b["C"][jb, d], p["C"][j, d]))
+                em.append(curve_err(b["M"][jb, d], p["M"][j, d]))
+    ec, em = np.array(ec), np.array(em)
+    return {"curves_compared": int(len(ec)), "max_C_err": float(ec.max()), "p99_C_err": float(np.quantile(ec, 0.99)),
+            "max_M_err": float(em.max()), "curves_C_err_above_1e-3": int((ec > 1e-3).sum()),
+            "C_within_1e-3": bool(ec.max() <= 1e-3)}
 
 
 def hv_rate(ham, dt, reps):
@@ -501,6 +599,13 @@ def main():
                     help="skip the short-range H*v GB/s object (cfg4_hb, cfg2_hb)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched-FP32 vs plain-FP64 comparison on the cfg3 subset")
+    ap.add_argument("--cfg3-full", choices=["batched", "plain"], default=None,
+                    help="the whole 64-instance batched workload (or --instances) on one path; "
+                    "saves every curve to --save")
+    ap.add_argument("--instances", default="0:64", help="instance range first:last for --cfg3-full")
+    ap.add_argument("--save", default="cfg3_curves.npz")
+    ap.add_argument("--cfg3-compare", nargs="+", default=None,
+                    help="BATCHED.npz PLAIN.npz [PLAIN.npz ...]: accuracy gate of --cfg3-full runs (CPU only)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning cache: reuse a stored choice instead of timing the candidates")
@@ -525,6 +630,13 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.cfg3_compare:
+        out = {"metric": "max relative C, M error of batched FP32 against plain FP64, whole cfg3",
+               "config": {"workload": "cfg3: 64 instances x 50 field directions, R=16, N_L=120"}}
+        out.update(cfg3_compare(args.cfg3_compare[0], args.cfg3_compare[1:]))
+        print(json.dumps(out), flush=True)
+        return
+
     import numpy as np
     import torch
 
@@ -532,6 +644,15 @@ def main():
     import paper_2607_25585_amd as F
 
     torch.cuda.set_device(0)
+    if args.cfg3_full:
+        a, b = (int(x) for x in args.instances.split(":"))
+        out = {"metric": "FTLM curves/s, whole cfg3 (%s path)" % args.cfg3_full, "unit": "curves/s", "n_gpus": 1,
+               "dtype": "c64 storage, f64 recurrence" if args.cfg3_full == "batched" else "f64",
+               "data": "synthetic", "config": {"workload": "cfg3: instances %d..%d x 50 field directions, "
+                                                           "R=16, N_L=120, 200 temperatures" % (a, b - 1)}}
+        out.update(cfg3_full(args.cfg3_full, a, b, args.save, tune_cache=args.tune_cache))
+        print(json.dumps(out), flush=True)
+        return
     if args.extras:
         out = {"metric": "curves/s of sFTLM, Chebyshev and powder-averaged FTLM", "n_gpus": 1,
                "data": "synthetic", "config": {"workload": "ring6 / cfg1 / mn9"}}

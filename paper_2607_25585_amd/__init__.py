@@ -315,18 +315,20 @@ def batched_set_tuning(grid_cap: int = 0, unit_bits: int = 0, order: int = 0, bl
 
 def run_batched(hams, R: int, n_lanczos: int, T, fields_per_inst, seed: int = 0,
                 precision: int = FTLM_C64, workspace=None, columns: int = 0,
-                workspace_bytes: Optional[int] = None, time_steps: bool = False):
+                workspace_bytes: Optional[int] = None, time_steps: bool = False, instance0: int = 0):
     """Batched FTLM over many instances and field directions (one persistent
-    launch per Lanczos step).  fields_per_inst[k] is an [n_dirs, 3] array.
-    Returns a list of result dicts like :func:`run`; with time_steps the first
-    dict also holds "step_ms" (summed duration of the Lanczos step launches)
-    and "steps"."""
+    launch per Lanczos step).  fields_per_inst[k] is an [n_dirs, 3] array;
+    instance k draws the random vectors of instance index instance0 + k (so a
+    workload can be run in groups of instances with the same vectors as one
+    run, or as :func:`run` with instance=instance0 + k).  Returns a list of
+    result dicts like :func:`run`; with time_steps the first dict also holds
+    "step_ms" (summed duration of the Lanczos step launches) and "steps"."""
     torch = _torch()
     n = len(hams)
     ps = (_ffi.FtlmRunParams * n)()
     keep = []
     for k in range(n):
-        p, kp = _params(R, n_lanczos, T, seed, fields_per_inst[k], precision, columns, None, k)
+        p, kp = _params(R, n_lanczos, T, seed, fields_per_inst[k], precision, columns, None, instance0 + k)
         ps[k] = p
         keep.append(kp)
     hs = (ctypes.c_void_p * n)(*[h.handle for h in hams])
