@@ -122,7 +122,10 @@ int ftlm_hamiltonian_autotune(ftlm_hamiltonian *h, int32_t precision, int32_t n_
                               void *w, void *stream, int32_t *variant, int32_t *grid_cap,
                               int32_t *kc, float *best_ms);
 /* Sets the H*v configuration for (precision, n_cols) directly (e.g. from a cache
- * of earlier autotune results); variant 0 restores the built-in heuristic. */
+ * of earlier autotune results); variant 0 restores the built-in heuristic: for
+ * one column of at least 2^20 rows the single-pass tile kernel (variant 6) when
+ * the Hamiltonian has no s+- s^z pair pieces, else the LDS tile (spin 1/2, N >=
+ * 11) or the windowed passes; below that the direct gather. */
 int ftlm_hamiltonian_set_tuning(ftlm_hamiltonian *h, int32_t precision, int32_t n_cols,
                                 int32_t variant, int32_t grid_cap, int32_t kc);
 

@@ -2107,6 +2107,11 @@ int launch_hv(const DevHam &dh, const HvLaunch &Lin, hipStream_t s) {
     if (!L.grid_cap) L.grid_cap = tn.grid_cap;
     if (!L.kc) L.kc = tn.kc;
   }
+  // built-in choice for one column of a vector beyond the caches: the
+  // single-pass tile kernel wherever its plan exists (no s+- s^z pair pieces);
+  // it beat the multi-pass and tile kernels on every such workload measured
+  if (!L.variant && L.K == 1 && dh.geom.dim >= (1u << 20) && (L.precision == FTLM_C64 ? dh.sp32 : dh.sp64).ok)
+    L.variant = 6;
   g_variant = L.variant;
   int gx, gy, kc;
   const int rcg = hv_grid_blocks(dh, L, &gx, &gy, &kc);
