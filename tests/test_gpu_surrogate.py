@@ -100,7 +100,8 @@ def test_training_fits_smooth_function():
 
 def test_surrogate_gains_over_ftlm():
     """A small cfg5 data set: the trained ensemble predicts held-out curves better
-    than the mean training curve, runs far faster than FTLM, and the gate sends
+    than the mean training curve and than the curve of the nearest training set
+    (in the scaled input space), runs far faster than FTLM, and the gate sends
     out-of-domain parameters to FTLM."""
     import ftlm_workloads as W
     sur = S()
@@ -127,8 +128,15 @@ def test_surrogate_gains_over_ftlm():
     # error of C and M against FTLM, versus the mean training curve
     err_s = np.sqrt(np.mean((pc - cct) ** 2)) + np.sqrt(np.mean((pm - mmt) ** 2))
     err_0 = np.sqrt(np.mean((cc.mean(0)[None] - cct) ** 2)) + np.sqrt(np.mean((mm.mean(0)[None] - mmt) ** 2))
-    print("surrogate err", err_s, "mean-curve err", err_0, "t_ftlm", t_ftlm, "t_sur", t_sur, flush=True)
+    # nearest training set in the network's own input scaling (one temperature's row per set)
+    xt_tr = sur.encode_inputs(ptrain, T[:1])
+    xt_te = sur.encode_inputs(ptest, T[:1])
+    nn = np.argmin(((xt_te[:, None, :] - xt_tr[None, :, :]) ** 2).sum(-1), axis=1)
+    err_nn = np.sqrt(np.mean((cc[nn] - cct) ** 2)) + np.sqrt(np.mean((mm[nn] - mmt) ** 2))
+    print("surrogate err", err_s, "mean-curve err", err_0, "nearest-set err", err_nn, "t_ftlm", t_ftlm,
+          "t_sur", t_sur, flush=True)
     assert err_s < 0.7 * err_0
+    assert err_s < err_nn
     assert t_sur < t_ftlm / 20
     bad = ptest[:2].copy()
     bad[:, 3] = 9.0  # |B| outside the training range
