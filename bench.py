@@ -360,10 +360,10 @@ def hv_only(args, sysm, spec, ham, prec, K):
 
 
 def surrogate_report(n_train, n_test, train_s, n_val=500, tol=0.10, t_min=2.0, n_powder_sets=8, n_dirs=50,
-                     r_truth=160, tols=(0.05, 0.10, 0.20)):
+                     r_truth=160, tols=(0.05, 0.10, 0.15, 0.20), save=None, n_members=4):
     """The learned surrogate on the 8-spin s=3/2 ring data: FTLM training curves
-    (batched FP32 path, R=20, N_L=100, 200 temperatures), an ensemble of two MLPs
-    trained by the library's BF16/FP32 kernels, and its errors against a reference
+    (batched FP32 path, R=20, N_L=100, 200 temperatures), an ensemble of n_members
+    MLPs trained by the library's BF16/FP32 kernels, and its errors against a reference
     that is itself FTLM: FP64 curves with r_truth random vectors (statistical error
     sqrt(20 / r_truth) of the R=20 recipe's).  The gate is calibrated on a
     validation split so that the accepted curves have their 90th percentile of C
@@ -411,7 +411,7 @@ def surrogate_report(n_train, n_test, train_s, n_val=500, tol=0.10, t_min=2.0, n
     y = S.encode_targets(lz, mm, cc, T)
     models, losses = [], []
     t0 = time.perf_counter()
-    for seed in (0, 1):
+    for seed in range(n_members):
         m = S.MLP(seed=seed)
         last = [time.perf_counter()]
 
@@ -426,6 +426,14 @@ def surrogate_report(n_train, n_test, train_s, n_val=500, tol=0.10, t_min=2.0, n
     t_train = time.perf_counter() - t0
     print("surrogate: trained in %.1f s" % t_train, file=sys.stderr, flush=True)
     ens = S.Surrogate(models, t_min=t_min)
+    if save:
+        # every member's decoded curves on the validation and held-out sets, with the
+        # reference curves, for studies of the gate score
+        mv = [S.decode_outputs(y, T) for y in ens._members(pval, T)]
+        mt = [S.decode_outputs(y, T) for y in ens._members(ptest, T)]
+        np.savez(save, T=T, pval=pval, ptest=ptest, C_val_ref=ccv, C_test_ref=cct, M_test_ref=mmt,
+                 C_test_r20=ccr, C_val_members=np.array([m[2] for m in mv]),
+                 C_test_members=np.array([m[2] for m in mt]), M_test_members=np.array([m[1] for m in mt]))
     plz, pm, pc, score = ens.predict(ptest, T)
     dom = ens.in_domain(ptest, T)
     eC1_all = S.c_relerr(pc, cct, T, t_min)
@@ -490,7 +498,8 @@ def surrogate_report(n_train, n_test, train_s, n_val=500, tol=0.10, t_min=2.0, n
             "ftlm_R%d_fp64_C_relerr_A12_T_ge_tmin" % spec.R: q(ftlm_r20),
             "ftlm_R%d_fp64_M_relerr_A12_T_ge_tmin" % spec.R: q(rel(mmr, mmt, hi)),
             "gate_scan": gate_scan,
-            "gate": {"score": "ensemble disagreement on C above t_min (relative measure)",
+            "members": n_members,
+            "gate": {"score": "ensemble spread on C above t_min (std over members / |mean|, floor 1e-3 max)",
                      "tolerance": "p90 of C relative error above %g K <= %g" % (t_min, tol),
                      "threshold": ens.threshold, "validation_acceptance": acc_val,
                      "heldout_acceptance": float(np.mean(acc)),
@@ -618,12 +627,15 @@ def main():
                     help="surrogate report on the s=3/2 ring data instead of the FTLM curve bench")
     ap.add_argument("--surrogate-train", type=int, default=20000)
     ap.add_argument("--surrogate-test", type=int, default=1000)
-    ap.add_argument("--surrogate-train-s", type=float, default=200.0)
+    ap.add_argument("--surrogate-train-s", type=float, default=120.0, help="training seconds per member")
     ap.add_argument("--surrogate-tol", type=float, default=0.10,
                     help="gate contract: p90 of the C relative error above --surrogate-tmin")
     ap.add_argument("--surrogate-tmin", type=float, default=2.0)
     ap.add_argument("--surrogate-rtruth", type=int, default=160,
                     help="random vectors of the FP64 FTLM reference curves (held-out and validation sets)")
+    ap.add_argument("--surrogate-members", type=int, default=4, help="ensemble members")
+    ap.add_argument("--surrogate-save", default=None,
+                    help="npz file for the members' curves and the reference curves (gate studies)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -671,7 +683,8 @@ def main():
                "config": {"workload": "8-spin s=3/2 ring, MLP 7-256-256-256-3 (bf16 weights, fp32 accumulate)"}}
         out.update(surrogate_report(args.surrogate_train, args.surrogate_test, args.surrogate_train_s,
                                     tol=args.surrogate_tol, t_min=args.surrogate_tmin,
-                                    r_truth=args.surrogate_rtruth))
+                                    r_truth=args.surrogate_rtruth, save=args.surrogate_save,
+                                    n_members=args.surrogate_members))
         print(json.dumps(out), flush=True)
         return
     sysm, spec = W.WORKLOADS[args.workload]()

@@ -7,10 +7,9 @@ to (ln Z, M, C).  Weights are BF16 with FP32 master copies; forward, backward an
 Adam run in the library's HIP kernels (ftlm_mlp_forward / _backward,
 ftlm_adam_step); PyTorch only owns device memory and streams.  Training data
 are FTLM curves from the batched GPU path.  A gate (parameter domain and the
-disagreement of an ensemble of two networks on C, with a threshold calibrated
-on a validation split so that accepted curves meet a stated error quantile)
-decides when to fall back to full FTLM, which also measures the surrogate's
-error.
+spread of an ensemble of networks on C, with a threshold calibrated on a
+validation split so that accepted curves meet a stated error quantile) decides
+when to fall back to full FTLM, which also measures the surrogate's error.
 
 Encodings (readings, not from the paper):
   inputs  -- J/3, d/5, 2 tilt/(pi/2) - 1, |B|/3.5 - 1, 2 theta/pi - 1,
@@ -269,13 +268,25 @@ def c_relerr(C, C_ref, T, t_min: float = 1.0) -> np.ndarray:
                   axis=1)
 
 
-class Surrogate:
-    """Ensemble of two MLPs with a gate and FTLM fallback.
+def c_spread(Cs, T, t_min: float = 1.0) -> np.ndarray:
+    """Per set: max over T >= t_min of std_m(C_m) / max(|mean_m C_m|, 1e-3 max_T
+    |mean_m C_m|), for member curves Cs [members, sets, T]."""
+    Cs = np.asarray(Cs, np.float64)
+    hi = np.asarray(T) >= t_min
+    mean = Cs[:, :, hi].mean(0)
+    floor = 1e-3 * np.max(np.abs(mean), axis=1, keepdims=True)
+    return np.max(Cs[:, :, hi].std(0) / np.maximum(np.abs(mean), np.maximum(floor, 1e-12)), axis=1)
 
-    Gate: a parameter set is answered by the surrogate when its parameters and
-    temperatures lie in the training domain and the ensemble's disagreement on
-    C (the two members' C curves compared with the relative measure of
-    c_relerr, above t_min) is at most the threshold.  ``calibrate`` sets the
+
+class Surrogate:
+    """Ensemble of MLPs (two or more) with a gate and FTLM fallback.
+
+    Prediction: the members' outputs averaged in the network's normalised
+    units, then decoded.  Gate: a parameter set is answered by the surrogate
+    when its parameters and temperatures lie in the training domain and the
+    ensemble's relative spread on C (the standard deviation of the members' C
+    over the magnitude of their mean, with the floor of c_relerr, maximised
+    over T >= t_min) is at most the threshold.  ``calibrate`` sets the
     threshold from a validation split with FTLM truth so that the accepted
     curves meet a stated error quantile; everything else goes to FTLM."""
 
@@ -290,13 +301,11 @@ class Surrogate:
         return [m.forward(x).cpu().numpy().astype(np.float64) for m in self.models]
 
     def predict(self, params: np.ndarray, T: np.ndarray):
-        """Mean prediction and the gate score (ensemble disagreement on C)."""
+        """Mean prediction and the gate score (ensemble spread on C)."""
         ys = self._members(params, T)
         lnZ, M, C = decode_outputs(np.mean(ys, axis=0), T)
-        c0 = decode_outputs(ys[0], T)[2]
-        c1 = decode_outputs(ys[-1], T)[2]
-        score = c_relerr(c0, c1, T, self.t_min)
-        return lnZ, M, C, score
+        cs = np.array([decode_outputs(y, T)[2] for y in ys])
+        return lnZ, M, C, c_spread(cs, T, self.t_min)
 
     def in_domain(self, params: np.ndarray, T: np.ndarray):
         p = np.asarray(params, np.float64).reshape(-1, 6)

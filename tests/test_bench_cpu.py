@@ -1,6 +1,6 @@
-"""Host-side parts of bench.py: the one-GPU contract, the traffic lookup keyed
-by the kernel sources' hash, and the accuracy gate of the whole batched
-workload (no GPU needed)."""
+"""Host-side logic (no GPU needed): bench.py's one-GPU contract, its traffic
+lookup keyed by the kernel sources' hash and the accuracy gate of the whole
+batched workload, and the surrogate gate's spread score."""
 import json
 import os
 import subprocess
@@ -63,3 +63,18 @@ def test_whole_workload_gate_matches_curves(tmp_path):
     assert out["max_C_err"] == pytest.approx(2e-3 / (1 + 2e-3), rel=1e-9)
     assert out["max_M_err"] == 0.0
     assert out["C_within_1e-3"] is False
+
+
+def test_surrogate_gate_spread():
+    """The gate score: zero for identical members; for two members the relative
+    half-difference; the floor (1e-3 of the curve's largest mean) caps it where
+    the mean curve is tiny; only temperatures from t_min up count."""
+    from paper_2607_25585_amd.surrogate import c_spread
+    T = np.array([0.5, 1.0, 2.0, 4.0])
+    a = np.array([[1.0, 2.0, 3.0, 4.0]])
+    assert c_spread(np.stack([a, a, a]), T, 1.0)[0] == 0.0
+    b = a * np.array([[10.0, 1.0, 1.1, 1.0]])  # differs at T = 0.5 (ignored) and T = 2
+    assert c_spread(np.stack([a, b]), T, 1.0)[0] == pytest.approx(0.1 * 3.0 / 2 / (3.15))
+    tiny = np.array([[1e-9, 1.0, 1.0, 1.0]])
+    tiny2 = np.array([[3e-9, 1.0, 1.0, 1.0]])
+    assert c_spread(np.stack([tiny, tiny2]), T, 0.1)[0] == pytest.approx(1e-9 / 1e-3)
