@@ -317,6 +317,43 @@ def hv_hbm(cases=(("cfg4", "c128"), ("cfg4", "c64"), ("cfg4_hb", "c128"), ("cfg2
     return out
 
 
+def stream_bw(sizes_mib=(48, 96, 4096)):
+    """Streaming rates of plain device kernels (torch's copy and sum) by buffer
+    size, each timed with HIP events on the current stream: the ceiling the
+    H*v traffic rates compare with.  Buffers of 48 and 96 MiB stay in the
+    last-level cache once touched; 4 GiB streams from HBM."""
+    import torch
+    out = []
+    for mb in sizes_mib:
+        n = mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+            a.sum()
+        torch.cuda.synchronize()
+        reps = max(10, 8000 // mb)
+
+        def ms_per(fn):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        nbytes = mb * (1 << 20)
+        tc = ms_per(lambda: b.copy_(a))
+        ts = ms_per(lambda: a.sum())
+        out.append({"MiB": mb, "copy_GBps_read_plus_write": round(2 * nbytes / (tc * 1e-3) / 1e9, 1),
+                    "sum_GBps_read": round(nbytes / (ts * 1e-3) / 1e9, 1), "reps": reps})
+        print("stream_bw %d MiB done" % mb, file=sys.stderr, flush=True)
+        del a, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def hv_only(args, sysm, spec, ham, prec, K):
     """H*v throughput alone: a plain device copy of 1 GiB (the calibration
     kernel for HBM byte counters), then args.hv_reps applications of the tuned
@@ -621,6 +658,8 @@ def main():
     ap.add_argument("--hv-only", action="store_true",
                     help="time the H*v product alone (GB/s line) instead of whole curves")
     ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--stream-bw", action="store_true",
+                    help="streaming rates of plain device copy and sum kernels by buffer size")
     ap.add_argument("--extras", action="store_true",
                     help="sFTLM (ring6), Chebyshev vs Lanczos (cfg1) and Mn9 powder throughput")
     ap.add_argument("--surrogate", action="store_true",
@@ -663,6 +702,12 @@ def main():
                "data": "synthetic", "config": {"workload": "cfg3: instances %d..%d x 50 field directions, "
                                                            "R=16, N_L=120, 200 temperatures" % (a, b - 1)}}
         out.update(cfg3_full(args.cfg3_full, a, b, args.save, tune_cache=args.tune_cache))
+        print(json.dumps(out), flush=True)
+        return
+    if args.stream_bw:
+        out = {"metric": "device streaming GB/s by buffer size (torch copy and sum)", "n_gpus": 1,
+               "peak_GBps": HBM_PEAK_GBPS, "data": "synthetic", "config": {"workload": "float64 buffers"}}
+        out["sizes"] = stream_bw()
         print(json.dumps(out), flush=True)
         return
     if args.extras:
