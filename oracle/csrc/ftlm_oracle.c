@@ -341,6 +341,14 @@ void oracle_gaussian_vector(uint64_t seed, uint32_t r, uint32_t field, uint32_t 
   for (int64_t nu = 0; nu < dim; nu++) out[nu] = gaussian_component(seed, r, field, inst, (uint32_t)nu);
 }
 
+/* The same components at the listed indices only (each below 2^32). */
+void oracle_gaussian_entries(uint64_t seed, uint32_t r, uint32_t field, uint32_t inst,
+                             const int64_t *idx, int64_t n, double *out_ri) {
+  cplx *out = (cplx *)out_ri;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; k++) out[k] = gaussian_component(seed, r, field, inst, (uint32_t)idx[k]);
+}
+
 /* ---- Lanczos (Paige order) ---- */
 static double dot_re(const cplx *a, const cplx *b, int64_t n) {
   double s = 0;

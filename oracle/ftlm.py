@@ -63,6 +63,9 @@ def lib():
         L.oracle_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
         L.oracle_gaussian_vector.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                              ctypes.c_uint32, ctypes.c_int64, dp]
+        L.oracle_gaussian_entries.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                              ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.c_int64, dp]
         L.oracle_lanczos.restype = ctypes.c_int
         L.oracle_lanczos.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_int,
                                      ctypes.c_int, dp, dp, dp, ip]
@@ -176,6 +179,18 @@ def gaussian_vector(seed, r, field, instance, dim):
     out = np.empty(int(dim), np.complex128)
     lib().oracle_gaussian_vector(ctypes.c_uint64(int(seed)), r, field, instance, int(dim),
                                  _dp(out.view(np.float64)))
+    return out
+
+
+def gaussian_entries(seed, r, field, instance, idx):
+    """Components idx of :func:`gaussian_vector` (any dimension above them),
+    without forming the vector."""
+    idx = np.ascontiguousarray(np.asarray(idx, np.int64))
+    assert idx.size == 0 or (idx.min() >= 0 and idx.max() < (1 << 32))
+    out = np.empty(len(idx), np.complex128)
+    lib().oracle_gaussian_entries(ctypes.c_uint64(int(seed)), r, field, instance,
+                                  idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(idx),
+                                  _dp(out.view(np.float64)))
     return out
 
 

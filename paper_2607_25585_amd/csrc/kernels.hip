@@ -2234,7 +2234,9 @@ __global__ __launch_bounds__(kBlock) void start_kernel(StartParams S) {
 #pragma unroll
   for (int q = 0; q < KC; q++) red[0][q] = 0.0;
   Cx<R> *out = reinterpret_cast<Cx<R> *>(S.out);
-  for (uint32_t row = blockIdx.x * kBlock + threadIdx.x; row < S.dim; row += gridDim.x * kBlock) {
+  // 64-bit row counter: near dim = 2^32 a 32-bit row + stride would wrap
+  for (uint64_t row = (uint64_t)blockIdx.x * kBlock + threadIdx.x; row < S.dim;
+       row += (uint64_t)gridDim.x * kBlock) {
 #pragma unroll
     for (int q = 0; q < KC; q++) {
       double x, y;
@@ -2243,7 +2245,7 @@ __global__ __launch_bounds__(kBlock) void start_kernel(StartParams S) {
         x = z.x;
         y = z.y;
       } else {
-        gauss(S.seed, row, S.r0 + c0 + q, S.field, S.inst, x, y);
+        gauss(S.seed, (uint32_t)row, S.r0 + c0 + q, S.field, S.inst, x, y);
       }
       const Cx<R> z{(R)x, (R)y};
       out[(size_t)row * S.K + c0 + q] = z;

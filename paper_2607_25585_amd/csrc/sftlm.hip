@@ -64,13 +64,14 @@ __global__ __launch_bounds__(256) void gram_kernel(const Cx<R> *__restrict__ X, 
   __shared__ Cx<R> wsh[kGT][kGC + 1];
   const int t = threadIdx.x, ta = t / kGT, tb = t % kGT;
   const int a0 = blockIdx.x * kGT, b0 = blockIdx.y * kGT;
-  const uint32_t lo = blockIdx.z * chunk, hi = min(dim, lo + chunk);
+  // 64-bit bounds: lo + chunk and r0 + kGC may pass 2^32 when dim is near it
+  const uint64_t lo = (uint64_t)blockIdx.z * chunk, hi = min((uint64_t)dim, lo + chunk);
   double ar = 0, ai = 0;
-  for (uint32_t r0 = lo; r0 < hi; r0 += kGC) {
+  for (uint64_t r0 = lo; r0 < hi; r0 += kGC) {
     __syncthreads();
     for (int idx = t; idx < kGT * kGC; idx += 256) {
       const int q = idx / kGC, k = idx % kGC;
-      const uint32_t row = r0 + k;
+      const uint64_t row = r0 + k;
       const bool ok = row < hi;
       xs[q][k] = (ok && a0 + q < nl) ? X[(size_t)(a0 + q) * xstride + row] : Cx<R>{0, 0};
       wsh[q][k] = (ok && b0 + q < nl) ? Wv[(size_t)(b0 + q) * xstride + row] : Cx<R>{0, 0};

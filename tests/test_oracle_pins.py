@@ -361,6 +361,16 @@ def test_gaussian_vector_statistics():
     assert np.array_equal(of.gaussian_vector(123, 2, 1, 0, 1000), z[:1000])
 
 
+def test_gaussian_entries_are_the_vector_components():
+    """Listed components equal the whole vector's, in any order and repeated;
+    a component depends on its index alone, not on the dimension."""
+    z = of.gaussian_vector(321, 4, 2, 7, 5000)
+    idx = np.array([4999, 0, 17, 17, 2500, 1])
+    assert np.array_equal(of.gaussian_entries(321, 4, 2, 7, idx), z[idx])
+    assert np.array_equal(of.gaussian_entries(321, 4, 2, 7, np.array([], np.int64)), np.zeros(0, complex))
+    assert of.gaussian_vector(321, 4, 2, 7, 18)[17] == z[17]
+
+
 # ------------------------------------------------------ C8 FTLM vs exact
 def test_ftlm_statistical_vs_exact():
     """FTLM (Eqs. E-2-C, E-2-D) against exact diagonalisation: the exact curve
