@@ -316,9 +316,10 @@ class Surrogate:
     def calibrate(self, params: np.ndarray, C_true: np.ndarray, T: np.ndarray, tol: float = 0.05,
                   quantile: float = 0.9):
         """Largest threshold at which the accepted validation sets have their
-        quantile of C error (c_relerr above t_min) at most tol: the sets are
-        taken in order of increasing score while that holds.  Returns the
-        validation acceptance rate."""
+        quantile of C error (c_relerr above t_min) at most tol: with the
+        in-domain sets in order of increasing score, the longest prefix whose
+        quantile meets tol sets the threshold (its last score; -1, accepting
+        nothing, if no prefix does).  Returns the validation acceptance rate."""
         _l, _m, C, score = self.predict(params, T)
         err = c_relerr(C, C_true, T, self.t_min)
         dom = self.in_domain(params, T)
