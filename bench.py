@@ -85,6 +85,74 @@ def cpu_baseline(sysm, spec, budget_s=12.0):
                                                                spec.R * spec.n_lanczos)}
 
 
+def cpu_oracle_report(cfg4=True):
+    """The oracle (CPU, FP64, OpenMP) timed on this host for every workload:
+    H*v per workload (median of five products for cfg1 and cfg2_hb, two for
+    cfg2, one for the 5^12-row cfg4 and cfg4_hb); one whole cfg1 curve
+    (R=20, N_L=100) and one whole surrogate-ring run; curves/s of cfg2 and cfg4
+    extrapolated from their H*v products (x R*N_L), and of the stratified
+    batched subset (one instance per spin count x 4 directions) from one H*v
+    per instance (x directions*R*N_L).  Each entry says what it extrapolates."""
+    import numpy as np
+
+    import ftlm_workloads as W
+    from oracle import ftlm as of
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {"cpu_model": _cpu_model(), "threads": threads, "cpus_visible": os.cpu_count(), "workloads": {}}
+    res = out["workloads"]
+
+    def hv_s(sysm, n=2):
+        ham = of.Ham(sysm)
+        rng = np.random.default_rng(0)
+        v = rng.standard_normal(ham.dim) + 1j * rng.standard_normal(ham.dim)
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            v = ham.apply(v)
+            ts.append(time.perf_counter() - t0)
+            v /= np.linalg.norm(v)
+            print("cpu oracle H*v dim %d: %.3f s" % (ham.dim, ts[-1]), file=sys.stderr, flush=True)
+        del ham
+        return float(np.median(ts)), len(ts)
+
+    for name in ("cfg1", "cfg2", "cfg2_hb", "cfg4_hb") + (("cfg4",) if cfg4 else ()):
+        sysm, spec = W.WORKLOADS[name]()
+        t, n = hv_s(sysm, 5 if name in ("cfg1", "cfg2_hb") else 1 if name.startswith("cfg4") else 2)
+        res[name] = {"dim": W.dimension(sysm.two_s), "oracle_hv_s": round(t, 5), "hv_samples": n,
+                     "curves_per_s_extrapolated": 1.0 / (spec.R * spec.n_lanczos * t),
+                     "extrapolation": "x R*N_L = %d H*v per curve" % (spec.R * spec.n_lanczos)}
+        print("cpu oracle %s done" % name, file=sys.stderr, flush=True)
+    s1, spec1 = W.cfg1()
+    t0 = time.perf_counter()
+    of.ftlm(s1, spec1.R, spec1.n_lanczos, spec1.T, seed=spec1.seed)
+    res["cfg1"]["whole_curve_s"] = round(time.perf_counter() - t0, 4)
+    res["cfg1"]["curves_per_s_measured"] = 1.0 / res["cfg1"]["whole_curve_s"]
+    s5 = W.cfg5_system(W.cfg5_params(1)[0])
+    sp5 = W.cfg5_runspec()
+    t0 = time.perf_counter()
+    of.ftlm(s5, sp5.R, sp5.n_lanczos, sp5.T, seed=1)
+    t5 = time.perf_counter() - t0
+    res["surrogate_ring"] = {"dim": W.dimension(s5.two_s), "whole_run_s": round(t5, 4),
+                             "curves_per_s_measured": 1.0 / t5,
+                             "run": "R=%d, N_L=%d, %d temperatures" % (sp5.R, sp5.n_lanczos, len(sp5.T))}
+    print("cpu oracle surrogate ring done", file=sys.stderr, flush=True)
+    systems, spec3, _fields = W.cfg3()
+    pick = stratified_cfg3(systems)
+    n_dirs = 4
+    total = 0.0
+    per = []
+    for k in pick:
+        t, _n = hv_s(systems[k], 1)
+        per.append({"instance": k, "N": systems[k].n_sites, "oracle_hv_s": round(t, 5)})
+        total += n_dirs * spec3.R * spec3.n_lanczos * t
+    res["cfg3_stratified"] = {"curves": len(pick) * n_dirs, "instances": per,
+                              "curves_per_s_extrapolated": len(pick) * n_dirs / total,
+                              "extrapolation": "one H*v per instance x %d directions x R*N_L = %d" % (
+                                  n_dirs, spec3.R * spec3.n_lanczos)}
+    print("cpu oracle cfg3 subset done", file=sys.stderr, flush=True)
+    return out
+
+
 def _cpu_model():
     """The host CPU's model name (Linux /proc/cpuinfo), or None."""
     try:
@@ -635,7 +703,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg2_hb", "cfg4", "cfg4_hb", "ring6", "mn9"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg2_hb", "cfg4", "cfg4_hb", "ring6", "mn9"])
     ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
     ap.add_argument("--columns", type=int, default=0,
                     help="random vectors iterated together (0 = library default)")
@@ -658,6 +726,8 @@ def main():
     ap.add_argument("--hv-only", action="store_true",
                     help="time the H*v product alone (GB/s line) instead of whole curves")
     ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--cpu-oracle", action="store_true",
+                    help="time the CPU oracle on every workload (no GPU used)")
     ap.add_argument("--stream-bw", action="store_true",
                     help="streaming rates of plain device copy and sum kernels by buffer size")
     ap.add_argument("--extras", action="store_true",
@@ -680,6 +750,13 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_oracle:
+        out = {"metric": "CPU oracle timings by workload (FP64, OpenMP)", "data": "synthetic",
+               "config": {"workload": "cfg1, cfg2, cfg2_hb, cfg4_hb, cfg4, surrogate ring, cfg3 stratified subset"}}
+        out.update(cpu_oracle_report())
+        print(json.dumps(out), flush=True)
+        return
 
     if args.cfg3_compare:
         out = {"metric": "max relative C, M error of batched FP32 against plain FP64, whole cfg3",
