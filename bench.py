@@ -814,7 +814,8 @@ def main():
     ham = F.Hamiltonian(sysm)
     # the library's default column count (ftlm_run_params.columns = 0)
     K = args.columns if args.columns > 0 else (
-        1 if ham.dim >= (1 << 20) else min(spec.R, 4) if ham.dim >= (1 << 17) else min(spec.R, 16))
+        1 if ham.dim >= (1 << 20) else min(spec.R, 4) if ham.dim >= (1 << 17)
+        else min(spec.R, 16) if ham.dim >= (1 << 14) else min(spec.R, 64))
     ws = None
 
     def step(time_hv=False):

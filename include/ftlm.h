@@ -168,7 +168,7 @@ typedef struct {
   int32_t precision;    /* ftlm_precision */
   int32_t columns;      /* K: random vectors iterated together, 1..64; 0 = automatic
                            (1 for dim >= 2^20, min(R, 4) for dim >= 2^17,
-                           else min(R, 16)) */
+                           min(R, 16) for dim >= 2^14, else min(R, 64)) */
   const void *r_init;   /* optional device complex128 start vectors (not
                            normalised) replacing the generator, element (f, nu, r)
                            at offset (f*dim + nu)*R + r; NULL */

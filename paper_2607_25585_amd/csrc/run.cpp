@@ -68,10 +68,15 @@ void make_plan(const ftlm_hamiltonian *h, const ftlm_run_params *p, RunPlan &pl)
   pl.prec = p->precision;
   pl.es = p->precision == FTLM_C64 ? 8 : 16;
   // columns = 0: one vector per wave once the vectors leave the caches (the tile
-  // and pass kernels stage one column), four between 2^17 and 2^20 rows, else up
-  // to 16 columns per gather (measured on the s=1/2 dipolar rings of 14..20 sites)
+  // and pass kernels stage one column), four between 2^17 and 2^20 rows, up to
+  // 16 columns per gather from 2^14 rows (measured on the s=1/2 dipolar rings of
+  // 14..20 sites), and below 2^14 rows every vector in one wave (at most 64):
+  // there a Lanczos step costs its launch latency more than its columns
   pl.K = p->columns > 0 ? p->columns
-                        : (h->host.dim >= (1ull << 20) ? 1 : h->host.dim >= (1ull << 17) ? 4 : std::min(p->R, 16));
+                        : (h->host.dim >= (1ull << 20)   ? 1
+                           : h->host.dim >= (1ull << 17) ? 4
+                           : h->host.dim >= (1ull << 14) ? std::min(p->R, 16)
+                                                         : std::min(p->R, 64));
   pl.K = std::min(pl.K, p->R);
   pl.dim = h->host.dim;
   Carve c;

@@ -242,6 +242,23 @@ def test_run_cfg1_matches_oracle():
         assert curve_err(got[key][0], ref[key]) < 1e-8, key
 
 
+@pytest.mark.parametrize("R", [40, 64])
+def test_run_one_wave_of_many_columns(R):
+    """Below 2^14 rows the default wave holds every random vector (at most 64):
+    curves against the oracle on the same seeded vectors."""
+    rng = np.random.default_rng(50 + R)
+    sysm = W.random_small_system(rng, 6, max_two_s=2)
+    dim = W.dimension(sysm.two_s)
+    assert 64 <= dim < (1 << 14)
+    T = W.t_grid(30)
+    print("case one wave R", R, "dim", dim, flush=True)
+    ham, got = _run_pair(sysm, R, 30, T, 23)
+    ref = of.ftlm(sysm, R, 30, T, seed=23)[0]
+    for key in ("lnZ", "E", "C", "M"):
+        assert curve_err(got[key][0], ref[key]) < 1e-8, key
+    assert np.array_equal(got["n_lanczos_used"][0], ref["n_lanczos_used"])
+
+
 def test_run_spin_half_tiles_matches_oracle():
     rng = np.random.default_rng(8)
     sysm = W.random_small_system(rng, 10, max_two_s=1)
