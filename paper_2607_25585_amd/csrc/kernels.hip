@@ -39,30 +39,31 @@ static inline UniformTabs<R> uniform_tabs(const DevTables<R> &tb, bool half) {
   return UniformTabs<R>{half ? tb.pc_half : tb.pc, tb.czp, tb.czm, tb.pij, tb.pzz};
 }
 
-// One block: alpha_j and y_j of every column from the H*v kernel's per-block
-// partials (layout [cb][bx][3][KC], gx blocks along x), in block order.
+// alpha_j and y_j of every column from the H*v kernel's per-block partials
+// (layout [cb][bx][3][KC], gx blocks along x): one block per (column,
+// quantity), each summing its partials in block order, so the sums are those
+// of one block taking them in turn but the columns do not wait on each other.
 template <int KC>
-__global__ __launch_bounds__(kBlock) void hv_lanczos_finish(HvParams P, unsigned gx, unsigned gy) {
-  const int ncol = gy * KC;
-  for (int idx = 0; idx < 3 * ncol; idx++) {
-    const int c = idx / 3, a = idx % 3;
-    const int cb = c / KC, q = c % KC;
-    double s = block_sum_strided(P.part + ((size_t)cb * gx * 3 + a) * KC + q, gx, (size_t)3 * KC);
-    s *= P.scale[c];
-    if (threadIdx.x == 0) {
-      if (a == 0) P.alpha_out[c] = s;
-      else if (a == 1) { if (P.ov1) P.yre_out[c] = s; }
-      else { if (P.ov1) P.yim_out[c] = s; }
-    }
+__global__ __launch_bounds__(kBlock) void hv_lanczos_finish(HvParams P, unsigned gx) {
+  const int c = blockIdx.x / 3, a = blockIdx.x % 3;
+  if (a != 0 && !P.ov1) return;
+  const int cb = c / KC, q = c % KC;
+  double s = block_sum_strided(P.part + ((size_t)cb * gx * 3 + a) * KC + q, gx, (size_t)3 * KC);
+  s *= P.scale[c];
+  if (threadIdx.x == 0) {
+    if (a == 0) P.alpha_out[c] = s;
+    else if (a == 1) P.yre_out[c] = s;
+    else P.yim_out[c] = s;
   }
 }
 
 static void launch_hv_finish(const HvParams &P, unsigned gx, unsigned gy, int kc, hipStream_t s) {
+  const dim3 grid(3 * gy * (unsigned)kc);
   switch (kc) {
-    case 8: hipLaunchKernelGGL(hv_lanczos_finish<8>, dim3(1), dim3(kBlock), 0, s, P, gx, gy); break;
-    case 4: hipLaunchKernelGGL(hv_lanczos_finish<4>, dim3(1), dim3(kBlock), 0, s, P, gx, gy); break;
-    case 2: hipLaunchKernelGGL(hv_lanczos_finish<2>, dim3(1), dim3(kBlock), 0, s, P, gx, gy); break;
-    default: hipLaunchKernelGGL(hv_lanczos_finish<1>, dim3(1), dim3(kBlock), 0, s, P, gx, gy); break;
+    case 8: hipLaunchKernelGGL(hv_lanczos_finish<8>, grid, dim3(kBlock), 0, s, P, gx); break;
+    case 4: hipLaunchKernelGGL(hv_lanczos_finish<4>, grid, dim3(kBlock), 0, s, P, gx); break;
+    case 2: hipLaunchKernelGGL(hv_lanczos_finish<2>, grid, dim3(kBlock), 0, s, P, gx); break;
+    default: hipLaunchKernelGGL(hv_lanczos_finish<1>, grid, dim3(kBlock), 0, s, P, gx); break;
   }
 }
 
@@ -2255,15 +2256,14 @@ __global__ __launch_bounds__(kBlock) void start_kernel(StartParams S) {
   block_partials_store<1, KC>(red, S.part, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
-// One block: sx0 = 1/|r| of every column from the start kernel's partials.
+// sx0 = 1/|r| of every column from the start kernel's partials, one block per
+// column (each summing in block order).
 template <int KC>
-__global__ __launch_bounds__(kBlock) void start_finish(StartParams S, unsigned gx, unsigned gy) {
-  const int ncol = gy * KC;
-  for (int c = 0; c < ncol; c++) {
-    const int cb = c / KC, q = c % KC;
-    const double s = block_sum_strided(S.part + (size_t)cb * gx * KC + q, gx, KC);
-    if (threadIdx.x == 0) S.sx0[c] = s > 0 ? 1.0 / sqrt(s) : 0.0;
-  }
+__global__ __launch_bounds__(kBlock) void start_finish(StartParams S, unsigned gx) {
+  const int c = blockIdx.x;
+  const int cb = c / KC, q = c % KC;
+  const double s = block_sum_strided(S.part + (size_t)cb * gx * KC + q, gx, KC);
+  if (threadIdx.x == 0) S.sx0[c] = s > 0 ? 1.0 / sqrt(s) : 0.0;
 }
 
 template <typename R, bool COPY>
@@ -2278,11 +2278,12 @@ static void launch_start_r(const StartParams &S, int grid_cap, hipStream_t s) {
     case 2: hipLaunchKernelGGL((start_kernel<R, 2, COPY>), grid, dim3(kBlock), 0, s, S); break;
     default: hipLaunchKernelGGL((start_kernel<R, 1, COPY>), grid, dim3(kBlock), 0, s, S); break;
   }
+  const dim3 fgrid(grid.y * (unsigned)kc);
   switch (kc) {
-    case 8: hipLaunchKernelGGL(start_finish<8>, dim3(1), dim3(kBlock), 0, s, S, grid.x, grid.y); break;
-    case 4: hipLaunchKernelGGL(start_finish<4>, dim3(1), dim3(kBlock), 0, s, S, grid.x, grid.y); break;
-    case 2: hipLaunchKernelGGL(start_finish<2>, dim3(1), dim3(kBlock), 0, s, S, grid.x, grid.y); break;
-    default: hipLaunchKernelGGL(start_finish<1>, dim3(1), dim3(kBlock), 0, s, S, grid.x, grid.y); break;
+    case 8: hipLaunchKernelGGL(start_finish<8>, fgrid, dim3(kBlock), 0, s, S, grid.x); break;
+    case 4: hipLaunchKernelGGL(start_finish<4>, fgrid, dim3(kBlock), 0, s, S, grid.x); break;
+    case 2: hipLaunchKernelGGL(start_finish<2>, fgrid, dim3(kBlock), 0, s, S, grid.x); break;
+    default: hipLaunchKernelGGL(start_finish<1>, fgrid, dim3(kBlock), 0, s, S, grid.x); break;
   }
 }
 
@@ -2375,15 +2376,16 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs A) {
   block_partials_store<1, KC>(red, A.part, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
-// One block: beta_j = |u| from the update kernel's per-block partials (layout
-// [cb][bx][KC]), the next scale 1/beta_j and the breakdown test.
+// One block per column: beta_j = |u| from the update kernel's per-block
+// partials (layout [cb][bx][KC], summed in block order), the next scale
+// 1/beta_j and the breakdown test.
 template <int KC>
-__global__ __launch_bounds__(kBlock) void update_finish(UpdateArgs A, unsigned gx, unsigned gy) {
-  const int ncol = gy * KC;
-  for (int c = 0; c < ncol; c++) {
+__global__ __launch_bounds__(kBlock) void update_finish(UpdateArgs A, unsigned gx) {
+  const int c = blockIdx.x;  // one block per column
+  {
     const int cb = c / KC, q = c % KC;
     const double s = block_sum_strided(A.part + (size_t)cb * gx * KC + q, gx, KC);
-    if (threadIdx.x != 0) continue;
+    if (threadIdx.x != 0) return;
     double b = sqrt(s);
     const double al = fabs(A.alpha[c]);
     double sm = A.scale_max[c];
@@ -2431,11 +2433,12 @@ int launch_update(const UpdateArgs &a, hipStream_t s) {
       else hipLaunchKernelGGL((update_kernel<double, 1>), grid, dim3(kBlock), 0, s, a);
       break;
   }
+  const dim3 fgrid(grid.y * (unsigned)kc);
   switch (kc) {
-    case 8: hipLaunchKernelGGL(update_finish<8>, dim3(1), dim3(kBlock), 0, s, a, grid.x, grid.y); break;
-    case 4: hipLaunchKernelGGL(update_finish<4>, dim3(1), dim3(kBlock), 0, s, a, grid.x, grid.y); break;
-    case 2: hipLaunchKernelGGL(update_finish<2>, dim3(1), dim3(kBlock), 0, s, a, grid.x, grid.y); break;
-    default: hipLaunchKernelGGL(update_finish<1>, dim3(1), dim3(kBlock), 0, s, a, grid.x, grid.y); break;
+    case 8: hipLaunchKernelGGL(update_finish<8>, fgrid, dim3(kBlock), 0, s, a, grid.x); break;
+    case 4: hipLaunchKernelGGL(update_finish<4>, fgrid, dim3(kBlock), 0, s, a, grid.x); break;
+    case 2: hipLaunchKernelGGL(update_finish<2>, fgrid, dim3(kBlock), 0, s, a, grid.x); break;
+    default: hipLaunchKernelGGL(update_finish<1>, fgrid, dim3(kBlock), 0, s, a, grid.x); break;
   }
   return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
 }
@@ -2565,64 +2568,85 @@ int launch_tridiag(int n_cols, int n_lanczos, const int *n_used, int used_stride
 }
 
 // ------------------------------------------------------------------ Boltzmann sums
-// One thread per (curve, temperature).  Columns f*R .. f*R+R-1 of the
-// [n_lanczos][n_curves*R] arrays belong to curve f.  With
+// One block of kBz threads per (curve, temperature).  Columns f*R .. f*R+R-1 of
+// the [n_lanczos][n_curves*R] arrays belong to curve f; the curve's terms
+// k = i R + r (Ritz value i of vector r) are dealt to the threads in a fixed
+// stride and every sum and extremum meets in a fixed LDS tree, so the results
+// do not depend on scheduling.  With
 //   l_{rn} = ln Q_1n^2 - (eps_n - E_min)/T,  lmax = max l:
 //   ln Z = ln(dim/R) - E_min/T + lmax + ln sum exp(l - lmax)        (Eq. E-2-D)
 //   <A>  = sum exp(l - lmax) A(eps) / sum exp(l - lmax)
 //   M    = sum exp(-(eps-E_min)/T - lmax) Q_1n (sum_a Q_an y_a) / sum exp(l - lmax)
-__global__ void boltzmann_kernel(int n_curves, int R, int nl, const int *n_used,
-                                 const double *eps, const double *q1, const double *qy,
-                                 const double *dims, const double *T, int n_T, double *lnZ,
-                                 double *E, double *C, double *M, double *E_min) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n_curves * n_T) return;
-  const int f = id / n_T, it = id % n_T;
-  const int ncol = n_curves * R;
+constexpr int kBz = 256;
+
+template <int OP>  // 0: sum, 1: max, 2: min
+__device__ __forceinline__ double bz_tree(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kBz / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double a = sh[threadIdx.x], b = sh[threadIdx.x + w];
+      sh[threadIdx.x] = OP == 0 ? a + b : OP == 1 ? fmax(a, b) : fmin(a, b);
+    }
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kBz) void boltzmann_kernel(int n_curves, int R, int nl, const int *n_used,
+                                                        const double *eps, const double *q1, const double *qy,
+                                                        const double *dims, const double *T, int n_T,
+                                                        double *lnZ, double *E, double *C, double *M,
+                                                        double *E_min) {
+  __shared__ double sh[kBz];
+  const int f = blockIdx.x / n_T, it = blockIdx.x % n_T;
+  const int ncol = n_curves * R, nterm = nl * R;
   const double temp = T[it];
-  double emin = INFINITY;
-  for (int r = 0; r < R; r++) {
-    const int c = f * R + r;
-    const int n = n_used[c];
-    for (int i = 0; i < n; i++) emin = fmin(emin, eps[(size_t)i * ncol + c]);
+  double loc = INFINITY;
+  for (int k = threadIdx.x; k < nterm; k += kBz) {
+    const int i = k / R, c = f * R + k % R;
+    if (i < n_used[c]) loc = fmin(loc, eps[(size_t)i * ncol + c]);
   }
-  double lmax = -INFINITY;
-  for (int r = 0; r < R; r++) {
-    const int c = f * R + r;
-    const int n = n_used[c];
-    for (int i = 0; i < n; i++) {
-      const double qq = q1[(size_t)i * ncol + c];
-      if (qq == 0.0) continue;
-      const double l = log(qq * qq) - (eps[(size_t)i * ncol + c] - emin) / temp;
-      lmax = fmax(lmax, l);
-    }
+  const double emin = bz_tree<2>(loc, sh);
+  loc = -INFINITY;
+  for (int k = threadIdx.x; k < nterm; k += kBz) {
+    const int i = k / R, c = f * R + k % R;
+    if (i >= n_used[c]) continue;
+    const size_t o = (size_t)i * ncol + c;
+    const double qq = q1[o];
+    if (qq == 0.0) continue;
+    loc = fmax(loc, log(qq * qq) - (eps[o] - emin) / temp);
   }
+  const double lmax = bz_tree<1>(loc, sh);
   double z = 0, ez = 0, mz = 0;
-  for (int r = 0; r < R; r++) {
-    const int c = f * R + r;
-    const int n = n_used[c];
-    for (int i = 0; i < n; i++) {
-      const size_t o = (size_t)i * ncol + c;
-      const double w = exp(-(eps[o] - emin) / temp - lmax);
-      const double qq = q1[o];
-      z += w * qq * qq;
-      ez += w * qq * qq * eps[o];
-      mz += w * qq * qy[o];
-    }
+  for (int k = threadIdx.x; k < nterm; k += kBz) {
+    const int i = k / R, c = f * R + k % R;
+    if (i >= n_used[c]) continue;
+    const size_t o = (size_t)i * ncol + c;
+    const double w = exp(-(eps[o] - emin) / temp - lmax);
+    const double qq = q1[o];
+    z += w * qq * qq;
+    ez += w * qq * qq * eps[o];
+    mz += w * qq * qy[o];
   }
+  z = bz_tree<0>(z, sh);
+  ez = bz_tree<0>(ez, sh);
+  mz = bz_tree<0>(mz, sh);
   const double em = ez / z;
   double cz = 0;
-  for (int r = 0; r < R; r++) {
-    const int c = f * R + r;
-    const int n = n_used[c];
-    for (int i = 0; i < n; i++) {
-      const size_t o = (size_t)i * ncol + c;
-      const double w = exp(-(eps[o] - emin) / temp - lmax);
-      const double qq = q1[o];
-      const double de = eps[o] - em;
-      cz += w * qq * qq * de * de;
-    }
+  for (int k = threadIdx.x; k < nterm; k += kBz) {
+    const int i = k / R, c = f * R + k % R;
+    if (i >= n_used[c]) continue;
+    const size_t o = (size_t)i * ncol + c;
+    const double w = exp(-(eps[o] - emin) / temp - lmax);
+    const double qq = q1[o];
+    const double de = eps[o] - em;
+    cz += w * qq * qq * de * de;
   }
+  cz = bz_tree<0>(cz, sh);
+  if (threadIdx.x != 0) return;
   const size_t out = (size_t)f * n_T + it;
   lnZ[out] = log(dims[f] / R) - emin / temp + lmax + log(z);
   E[out] = em;
@@ -2635,9 +2659,10 @@ int launch_boltzmann(int n_curves, int R, int n_lanczos, const int *n_used, cons
                      const double *q1, const double *qy, const double *dims, const double *T,
                      int n_T, double *lnZ, double *E, double *C, double *M, double *E_min,
                      hipStream_t s) {
-  const int n = n_curves * n_T;
-  hipLaunchKernelGGL(boltzmann_kernel, dim3((n + 127) / 128), dim3(128), 0, s, n_curves, R,
-                     n_lanczos, n_used, eps, q1, qy, dims, T, n_T, lnZ, E, C, M, E_min);
+  const unsigned n = (unsigned)n_curves * (unsigned)n_T;
+  if (n == 0) return FTLM_OK;
+  hipLaunchKernelGGL(boltzmann_kernel, dim3(n), dim3(kBz), 0, s, n_curves, R, n_lanczos, n_used, eps,
+                     q1, qy, dims, T, n_T, lnZ, E, C, M, E_min);
   return hipGetLastError() == hipSuccess ? FTLM_OK : FTLM_EHIP;
 }
 
