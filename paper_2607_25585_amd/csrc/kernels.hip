@@ -2495,9 +2495,14 @@ __global__ void tridiag_kernel(int n_cols, int nl, const int *n_used, int used_s
     int iter = 0;
     while (true) {
       int m = l;
-      for (; m < n - 1; m++) {
-        const double dd = fabs(AT(d, m)) + fabs(AT(d, m + 1));
-        if (fabs(AT(e, m)) <= 2.220446049250313e-16 * dd) break;
+      {
+        double dm = AT(d, l);
+        for (; m < n - 1; m++) {
+          const double dm1 = AT(d, m + 1);
+          const double dd = fabs(dm) + fabs(dm1);
+          if (fabs(AT(e, m)) <= 2.220446049250313e-16 * dd) break;
+          dm = dm1;
+        }
       }
       if (m == l || iter++ >= 100) break;
       double gg = (AT(d, l + 1) - AT(d, l)) / (2.0 * AT(e, l));
@@ -2506,32 +2511,54 @@ __global__ void tridiag_kernel(int n_cols, int nl, const int *n_used, int used_s
       double s = 1.0, c = 1.0, p = 0.0;
       int i = m - 1;
       bool underflow = false;
+      // A step at i reads e[i], d[i], d[i+1] and rows i, i+1 of the tracked Z
+      // rows and writes indices i+1 and i only, so the next step's reads (index
+      // i-1) are issued one step ahead, d[i+1] is the previous step's d[i], and
+      // the rotated Z entries of index i stay in registers for the next step.
+      double d_hi = AT(d, m), z1_hi = AT(z1, m), zy_hi = AT(zy, m);
+      double e_i = AT(e, m - 1), d_i = AT(d, m - 1), z1_i = AT(z1, m - 1), zy_i = AT(zy, m - 1);
       for (; i >= l; i--) {
-        const double f = s * AT(e, i), b = c * AT(e, i);
+        double e_n = 0.0, d_n = 0.0, z1_n = 0.0, zy_n = 0.0;
+        if (i > l) {
+          e_n = AT(e, i - 1);
+          d_n = AT(d, i - 1);
+          z1_n = AT(z1, i - 1);
+          zy_n = AT(zy, i - 1);
+        }
+        const double f = s * e_i, b = c * e_i;
         r = hypot(f, gg);
         AT(e, i + 1) = r;
         if (r == 0.0) {
-          AT(d, i + 1) -= p;
+          AT(d, i + 1) = d_hi - p;
           AT(e, m) = 0.0;
+          AT(z1, i + 1) = z1_hi;
+          AT(zy, i + 1) = zy_hi;
           underflow = true;
           break;
         }
         s = f / r;
         c = gg / r;
-        gg = AT(d, i + 1) - p;
-        r = (AT(d, i) - gg) * s + 2.0 * c * b;
+        gg = d_hi - p;
+        r = (d_i - gg) * s + 2.0 * c * b;
         p = s * r;
         AT(d, i + 1) = gg + p;
         gg = c * r - b;
         // rotate columns i, i+1 of Z in the two tracked rows
-        double fz = AT(z1, i + 1);
-        AT(z1, i + 1) = s * AT(z1, i) + c * fz;
-        AT(z1, i) = c * AT(z1, i) - s * fz;
-        fz = AT(zy, i + 1);
-        AT(zy, i + 1) = s * AT(zy, i) + c * fz;
-        AT(zy, i) = c * AT(zy, i) - s * fz;
+        const double z1_lo = c * z1_i - s * z1_hi;
+        AT(z1, i + 1) = s * z1_i + c * z1_hi;
+        z1_hi = z1_lo;
+        const double zy_lo = c * zy_i - s * zy_hi;
+        AT(zy, i + 1) = s * zy_i + c * zy_hi;
+        zy_hi = zy_lo;
+        d_hi = d_i;
+        e_i = e_n;
+        d_i = d_n;
+        z1_i = z1_n;
+        zy_i = zy_n;
       }
       if (underflow) continue;
+      AT(z1, l) = z1_hi;
+      AT(zy, l) = zy_hi;
       AT(d, l) -= p;
       AT(e, l) = gg;
       AT(e, m) = 0.0;
